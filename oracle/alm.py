@@ -1,0 +1,179 @@
+"""Algorithm alg1 (ManiDSDP), FP64 dense oracle.
+
+Steps per outer iteration k (Algorithm alg1, section "The ManiDSDP algorithm"):
+ 1. approximately solve Sub-k by RTR, warm-started at Y^k and supplied with the
+    carried direction U;
+ 2. y^{k+1} = (AA*)^{-1} A(S^{k+1} + C);
+ 3. Xt^{k+1} = Xt^k - sigma_k (A* y^{k+1} - S^{k+1} - C)   (= Xt^k + sigma_k Q(Z));
+ 4. z^{k+1} = diag((Xt^{k+1} + D) S^{k+1});
+ 5. X^{k+1} = Xt^{k+1} + D - Diag(z^{k+1});
+ 6. if lambda_min(X^{k+1}) < 0 form U as in Theorem sec5:thm1, else U = 0;
+ 7. update p (zero-padding Y and U);
+ 8. update sigma by eq. sec5:eq1;
+and the KKT residuals eta_p, eta_d, eta_g of eq. res with the stop at
+eta_max <= tol.
+
+Readings of points the paper leaves open (each also listed in the design doc):
+* Y^0: the paper writes the zero matrix, which is not on the manifold; we take
+  the given row-normalised Gaussian start.
+* "supplied with the carried direction": from Yhat = [Y, 0] we backtrack
+  t = sqrt(n), sqrt(n)/2, ... along R_Yhat(t U) until the new Psi_k decreases,
+  then start RTR there (RTR alone cannot leave a saddle along U: the
+  gradient vanishes on the new columns).
+* rank rule (delegated by the paper to ManiSDP section 5.1, not in the text):
+  after each subproblem, drop singular directions of Y below tau_rank * s_1
+  (Y <- Y V_r, rows renormalised), then append one zero column per carried
+  eigenvector (at most n_neg of them, p <= p_max).
+* inner tolerance: RTR stops at ||grad|| <= max(gtol_min, min(gtol0, 0.1 eta_max^k)).
+* sigma constants: sigma_0 = 1, sigma_min = 1e-3, sigma_max = 1e6, gamma = 2,
+  kappa_1 = 0.1, kappa_2 = 10 (the paper states none).
+* eigenvector sign: the largest-magnitude component is made positive.
+
+Parity: not pinned on iterates; the result is pinned by brute force (q <= 16,
+v <= min f, equality when rank S = 1), by the rank-one rounding certificate,
+and by the invariants of Lemmas lm1 and sec3:lm1.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .operators import A_adj, D_matrix, Q_op, class_average
+from .rtr import rtr
+from .subproblem import Subproblem, retract, rowdot
+
+__all__ = ["ALMOptions", "ALMResult", "solve", "kkt_residuals", "rank_one_rounding"]
+
+
+@dataclass
+class ALMOptions:
+    tol: float = 1e-8
+    max_outer: int = 200
+    sigma0: float = 1.0
+    sigma_min: float = 1e-3
+    sigma_max: float = 1e6
+    gamma: float = 2.0
+    kappa1: float = 0.1
+    kappa2: float = 10.0
+    p_max: int = 64
+    n_neg: int = 1
+    tau_rank: float = 1e-4
+    gtol0: float = 1e-2
+    gtol_min: float = 1e-10
+    rtr_maxiter: int = 50
+    neg_tol: float = 1e-12
+
+
+@dataclass
+class ALMResult:
+    Y: np.ndarray
+    y: np.ndarray
+    Xt: np.ndarray
+    z: np.ndarray
+    X: np.ndarray
+    sigma: float
+    value: float  # b^T y
+    eta: tuple
+    history: list = field(default_factory=list)
+
+
+def kkt_residuals(S, y, X, z, b, cls, C=None):
+    """eq. res: eta_p, eta_d, eta_g (Frobenius norms; eigenvalues by LAPACK)."""
+    n = S.shape[0]
+    Cm = np.zeros((n, n)) if C is None else C
+    R = A_adj(y, cls) - S - Cm
+    eta_p = float(np.linalg.norm(R) / (1.0 + np.linalg.norm(Cm)))
+    ev = np.linalg.eigvalsh(X)
+    eta_d = float(max(0.0, -ev[0]) / (1.0 + abs(ev[-1])))
+    prim = float(np.sum(Cm * (X + np.diag(z))) + np.sum(z))
+    dual = float(b @ y)
+    eta_g = abs(prim - dual) / (1.0 + abs(prim) + abs(dual))
+    return eta_p, eta_d, eta_g
+
+
+def _escape(sub: Subproblem, Y: np.ndarray, U: np.ndarray) -> np.ndarray:
+    f0 = sub.cost(Y)
+    t = math.sqrt(Y.shape[0])
+    while t > 1e-8:
+        Yt = retract(Y, t * U)
+        if sub.cost(Yt) < f0:
+            return Yt
+        t *= 0.5
+    return Y
+
+
+def rank_one_rounding(Y: np.ndarray, Q: np.ndarray, c: np.ndarray, order_basis: np.ndarray):
+    """Read x_hat = sign(S[0, x_i]) from the leading row block of S = YY^T."""
+    q = c.size
+    s0 = Y[0] @ Y[1:1 + q].T
+    x = np.where(s0 >= 0, 1.0, -1.0)
+    return x, float(x @ Q @ x + c @ x)
+
+
+def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
+          opts: ALMOptions | None = None, C: np.ndarray | None = None) -> ALMResult:
+    opts = opts or ALMOptions()
+    n = cls.shape[0]
+    Xt = np.zeros((n, n))
+    sigma = opts.sigma0
+    Y = Y0 / np.linalg.norm(Y0, axis=1, keepdims=True)
+    D = D_matrix(b, cls, counts)
+    U = None
+    eta_max = 1.0
+    hist = []
+    normb = float(np.linalg.norm(b))
+    y = z = X = None
+    eta = (np.inf, np.inf, np.inf)
+    for k in range(opts.max_outer):
+        sub = Subproblem(cls, counts, b, Xt, sigma, C)
+        if U is not None:
+            Y = _escape(sub, Y, U)
+        gtol = max(opts.gtol_min, min(opts.gtol0, 0.1 * eta_max))
+        res = rtr(sub, Y, gtol, maxiter=opts.rtr_maxiter)
+        Y = res.Y
+        S = Y @ Y.T
+        Z = S if C is None else S + C
+        y = class_average(Z, cls, counts)
+        Rq = Q_op(Z, cls, counts)  # = -(A* y - S - C)
+        Xt = Xt + sigma * Rq
+        z = rowdot((Xt + D) @ Y, Y)
+        X = Xt + D - np.diag(z)
+        evals, evecs = np.linalg.eigh(X)
+        lmin, lmax = float(evals[0]), float(evals[-1])
+        eta = kkt_residuals(S, y, X, z, b, cls, C)
+        eta_max = max(eta)
+        hist.append(dict(k=k, p=Y.shape[1], sigma=sigma, eta=eta, value=float(b @ y),
+                         gradnorm=res.gradnorm, rtr_iters=res.iters, n_hvp=res.n_hvp,
+                         lmin=lmin, lmax=lmax))
+        if eta_max <= opts.tol:
+            break
+        # negative-curvature directions (Theorem sec5:thm1)
+        neg = np.nonzero(evals < -opts.neg_tol * (1.0 + abs(lmax)))[0][: opts.n_neg]
+        V = evecs[:, neg]
+        for j in range(V.shape[1]):
+            i = int(np.argmax(np.abs(V[:, j])))
+            if V[i, j] < 0:
+                V[:, j] = -V[:, j]
+        # rank update
+        _, s, Vt = np.linalg.svd(Y, full_matrices=False)
+        r = max(1, int(np.sum(s > opts.tau_rank * s[0])))
+        if r < Y.shape[1]:
+            Y = Y @ Vt[:r].T
+            Y = Y / np.linalg.norm(Y, axis=1, keepdims=True)
+        d = min(V.shape[1], opts.p_max - Y.shape[1])
+        if d > 0:
+            Y = np.hstack([Y, np.zeros((n, d))])
+            U = np.hstack([np.zeros((n, Y.shape[1] - d)), V[:, :d]])
+        else:
+            U = None
+        # sigma rule, eq. sec5:eq1
+        ratio = float(np.linalg.norm(Rq)) / (1.0 + normb)
+        if ratio < opts.kappa1 * res.gradnorm:
+            sigma = max(sigma / opts.gamma, opts.sigma_min)
+        elif ratio > opts.kappa2 * res.gradnorm:
+            sigma = min(opts.gamma * sigma, opts.sigma_max)
+    return ALMResult(Y=Y, y=y, Xt=Xt, z=z, X=X, sigma=sigma, value=float(b @ y),
+                     eta=eta, history=hist)
