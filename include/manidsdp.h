@@ -1,0 +1,223 @@
+/*
+ * manidsdp.h -- C ABI of the MI355X (gfx950) ManiDSDP subproblem library.
+ *
+ * The library evaluates, on one GPU, the quantities inside each ALM
+ * subproblem of ManiDSDP (Wang, Hu, Xia, arXiv 2512.04406) for SDPs of the
+ * form DSDP (introduction):
+ *
+ *     inf_y  b^T y   s.t.  S = A*(y) - C  PSD,  diag(S) = 1,
+ *
+ * whose constraint matrices A_gamma are 0/1 indicators of pairwise disjoint
+ * sets of matrix entries ("classes"), as in moment relaxations, so that AA* is
+ * diagonal (remarks after Algorithm alg1).  With S = Y Y^T, Y in R^{n x p} with
+ * unit rows (oblique manifold, eq. maniY), Z = S + C, and the projectors
+ * P = A*(AA*)^{-1}A, Q = I - P (eq. projection-operators):
+ *
+ *   cost    Psi(Y)   = <D + Xt, Z> + sigma/2 ||Q(Z)||_F^2  (eq. reduced-ALM-subproblem)
+ *   G                = Xt + D + sigma Q(Z)                  (Lemma lm:suboptimality)
+ *   egrad            = 2 G Y
+ *   z                = diag(G S) = rowdot(G Y, Y)
+ *   rgrad            = egrad - Diag(rowdot(egrad, Y)) Y = 2 X Y  (Prop. prop, eq. sec4:eq6)
+ *   ehess[U]         = 2 G U + 2 sigma Q(Y U^T + U Y^T) Y   (Prop. prop)
+ *   rhess[U]         = ehess[U] - Diag(rowdot(ehess[U], Y)) Y - 2 Diag(z) U  (eq. sec4:eq7)
+ *
+ * where D = A*(AA*)^{-1} b and Xt is the ALM multiplier (dense symmetric).
+ *
+ * Conventions for every entry point:
+ *  - Return value: MDSDP_OK or a negative mdsdp_status; mdsdp_last_error()
+ *    gives a message (thread-local).  Nothing is thrown across the ABI.
+ *  - "dev" pointers are device (HBM) pointers owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller.  The library never
+ *    frees caller memory.  Host inputs are copied before the call returns.
+ *  - Matrices Y, U, V, outputs: FP64, row-major n x p, contiguous (ld = p).
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL = the
+ *    default stream) and is asynchronous unless stated; device scalar outputs
+ *    become valid when the stream reaches them.
+ *  - Argument errors are detected synchronously (MDSDP_EINVAL) before any work
+ *    is enqueued.  A problem handle must not be used from two streams at once.
+ *  - p may be 1..16 for cost/gradient/HVP (MFMA tiles are 16 wide).
+ */
+#ifndef MANIDSDP_H
+#define MANIDSDP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mdsdp_problem_s* mdsdp_problem;
+
+typedef enum {
+  MDSDP_OK = 0,
+  MDSDP_EINVAL = -1,      /* bad argument (sizes, ids, NULL where required) */
+  MDSDP_ENOMEM = -2,      /* device allocation failed */
+  MDSDP_EHIP = -3,        /* a HIP runtime call failed */
+  MDSDP_ENOTORTH = -4,    /* sparse A supports overlap: AA* not diagonal */
+  MDSDP_ENONFINITE = -5,  /* NaN/Inf met in an input or a reduction */
+  MDSDP_EUNSUPPORTED = -6,/* e.g. p > 16, no gfx950 device */
+  MDSDP_ENOCONV = -7      /* iteration limit reached before the tolerance */
+} mdsdp_status;
+
+/* Tile precision of the HVP pass.  Class sums are always accumulated in
+ * 64-bit fixed point; cost, gradient, multiplier update and KKT are FP64. */
+typedef enum { MDSDP_FP64 = 0, MDSDP_FP32 = 1 } mdsdp_prec;
+
+/* Basis order for the BQP builder: paper order (lexicographic products) or the
+ * colex order (products by larger index) that groups each class's entries. */
+typedef enum { MDSDP_ORDER_LEX = 0, MDSDP_ORDER_COLEX = 1 } mdsdp_order;
+
+const char* mdsdp_last_error(void);
+const char* mdsdp_version(void);
+
+/* ---- BQP relaxation builder (host only, no device work) -------------------
+ * Order-2 moment relaxation of min x^T Q x + c^T x over x in {-1,1}^q
+ * (paragraph "Binary quadratic programs", basis v(x) and eq.
+ * bqp-number-moments): n = 1 + q + q(q-1)/2, m = sum_{d<=4} C(q,d).  The class
+ * of entry (alpha, beta) is the symmetric difference of the index sets; class
+ * ids are ordered by degree, then by colex rank of the sorted index set
+ * (id = off[d] + sum_i C(c_i, i), 0-based c_1 < ... < c_d).
+ * mdsdp_bqp_sizes: writes n and m.
+ * mdsdp_bqp_classmap: writes n(n+1)/2 int32 ids of the packed upper triangle,
+ *   row-major (row a holds columns a..n-1), into host buffer cls_out.
+ * mdsdp_bqp_b: writes b (length m, host): b_{} = tr Q, b_{i} = c_i,
+ *   b_{ij} = Q_ij + Q_ji, 0 for degree 3 and 4.  Q: q*q row-major host. */
+mdsdp_status mdsdp_bqp_sizes(int32_t q, int32_t* n_out, int64_t* m_out);
+mdsdp_status mdsdp_bqp_classmap(int32_t q, int32_t order, int32_t* cls_out);
+mdsdp_status mdsdp_bqp_b(int32_t q, const double* Q_host, const double* c_host, double* b_out);
+
+/* ---- problem lifetime ------------------------------------------------------
+ * mdsdp_create_classmap: cls_host = packed upper-triangle class ids (row-major,
+ * length n(n+1)/2, ids in [0, m), every class non-empty, all diagonal entries
+ * in classes that contain only diagonal entries is NOT required); b_host
+ * length m; C_host = dense symmetric n x n row-major or NULL for C = 0.
+ * Computes |gamma| (= AA*), D = b/|gamma|, A(C), builds the tile-major device
+ * layout and allocates all workspaces.  Xt starts at 0, sigma at 1.
+ * Errors: EINVAL for n < 1, m < 1, ids out of range or empty classes;
+ * ENOMEM; EUNSUPPORTED if the current device is not gfx950. */
+mdsdp_status mdsdp_create_classmap(int32_t n, int64_t m, const int32_t* cls_host,
+                                   const double* b_host, const double* C_host,
+                                   mdsdp_problem* out);
+/* Sparse A given as a list of (class, row, col, value) with row <= col; values
+ * must all be 1 (0/1 indicators) and every (row, col) of the upper triangle
+ * must be covered exactly once (disjoint supports; AA* diagonal).  Overlaps:
+ * ENOTORTH; uncovered entries or non-unit values: EUNSUPPORTED. */
+mdsdp_status mdsdp_create_sparse_A(int32_t n, int64_t m, int64_t nnz, const int32_t* cls_host,
+                                   const int32_t* row_host, const int32_t* col_host,
+                                   const double* val_host, const double* b_host,
+                                   const double* C_host, mdsdp_problem* out);
+mdsdp_status mdsdp_destroy(mdsdp_problem prob);
+mdsdp_status mdsdp_problem_info(mdsdp_problem prob, int32_t* n, int64_t* m, int64_t* n_slots,
+                                int32_t* n_tiles);
+
+/* ---- multiplier and penalty ------------------------------------------------
+ * set: Xt_dev = dense symmetric n x n row-major FP64 device matrix, or NULL for
+ * Xt = 0 (the spec lambda is -Xt).  get: writes the same layout. */
+mdsdp_status mdsdp_set_multiplier(mdsdp_problem prob, const double* Xt_dev, double sigma,
+                                  void* stream);
+mdsdp_status mdsdp_get_multiplier(mdsdp_problem prob, double* Xt_dev, void* stream);
+mdsdp_status mdsdp_set_sigma(mdsdp_problem prob, double sigma);
+
+/* ---- subproblem evaluation -------------------------------------------------
+ * cost_grad at Y (dev, n x p): f_dev (1 double, nullable), egrad_dev and
+ * rgrad_dev (n x p, nullable).  Caches y(S) (class averages), z = diag(G S)
+ * and the class coefficients used by the following mdsdp_hvp calls at the
+ * same Y.  Section: eq. reduced-ALM-subproblem, Lemma lm:suboptimality,
+ * Proposition prop. */
+mdsdp_status mdsdp_cost_grad(mdsdp_problem prob, int32_t p, const double* Y_dev, double* f_dev,
+                             double* egrad_dev, double* rgrad_dev, void* stream);
+/* HVP at the Y of the last mdsdp_cost_grad call (same Y_dev contents).
+ * riemannian = 0: ehess[U]; 1: rhess[U] (U should be tangent).  prec selects
+ * the tile precision.  Proposition prop, eq. sec4:eq7. */
+mdsdp_status mdsdp_hvp(mdsdp_problem prob, int32_t p, int32_t prec, const double* Y_dev,
+                       const double* U_dev, double* HU_dev, int32_t riemannian, void* stream);
+/* Class averages y(S) of Z = Y Y^T + C (variable projection, section 3):
+ * y_dev length m. */
+mdsdp_status mdsdp_class_average(mdsdp_problem prob, int32_t p, const double* Y_dev,
+                                 double* y_dev, void* stream);
+/* Retraction R_Y(t V) = rows of (Y + t V) normalised; Yout may alias Y. */
+mdsdp_status mdsdp_retract(int32_t n, int32_t p, const double* Y_dev, const double* V_dev,
+                           double t, double* Yout_dev, void* stream);
+/* Tangent projection P_Y(U) = U - Diag(U Y^T) Y (Lemma sec4:lm1); out may alias U. */
+mdsdp_status mdsdp_project_tangent(int32_t n, int32_t p, const double* Y_dev,
+                                   const double* U_dev, double* out_dev, void* stream);
+
+/* ---- outer-loop steps (Algorithm alg1, steps 5-8) --------------------------
+ * update_multiplier: y = class averages of Z, Xt <- Xt + sigma Q(Z),
+ * z = diag((Xt + D) S).  Outputs (dev, nullable): y (m), z (n),
+ * kkt[4] = { ||Q(Z)||_F, b^T y, sum z, <C, X + Diag z> }.  FP64. */
+mdsdp_status mdsdp_update_multiplier(mdsdp_problem prob, int32_t p, const double* Y_dev,
+                                     double* y_dev, double* z_dev, double* kkt_dev, void* stream);
+/* X v = (Xt + D) v - z o v for k vectors (columns of V, n x k row-major,
+ * k <= 16), with z from the last update_multiplier.  FP64. */
+mdsdp_status mdsdp_certificate_matvec(mdsdp_problem prob, int32_t k, const double* V_dev,
+                                      double* XV_dev, void* stream);
+/* Smallest eigenpair and largest eigenvalue of X = Xt + D - Diag(z) by
+ * Lanczos with full reorthogonalisation (eq. res, step 9 of Algorithm alg1).
+ * Synchronous.  evec_dev: n doubles (nullable).  Stops when the residual of
+ * the smallest Ritz pair is <= tol (1 + |lambda_max|) or after maxit steps
+ * (then returns MDSDP_ENOCONV with the best estimate written). */
+mdsdp_status mdsdp_min_eigpair(mdsdp_problem prob, double tol, int32_t maxit, uint64_t seed,
+                               double* lambda_min, double* lambda_max, double* evec_dev,
+                               int32_t* iters, void* stream);
+/* Adjoint of the optimal value w.r.t. C: dv/dC = X + Diag z = Xt + D
+ * (Lagrangian duality, dual problem PSDP).  Writes a dense n x n FP64 device
+ * matrix. */
+mdsdp_status mdsdp_adjoint_C(mdsdp_problem prob, double* dC_dev, void* stream);
+
+/* ---- full solve (Algorithm alg1 with RTR + truncated CG) ------------------- */
+typedef struct {
+  double tol;          /* stop when eta_max <= tol (eq. res); default 1e-8 */
+  int32_t max_outer;   /* default 200 */
+  double sigma0, sigma_min, sigma_max, gamma, kappa1, kappa2; /* eq. sec5:eq1 */
+  int32_t p_max;       /* <= 16 */
+  double tau_rank;     /* drop singular directions below tau_rank * s_1 */
+  double gtol0, gtol_min;  /* inner tolerance max(gtol_min, min(gtol0, 0.1 eta)) */
+  int32_t rtr_maxiter, tcg_maxinner;
+  int32_t hvp_prec;    /* mdsdp_prec for tCG HVPs */
+  int32_t polish_fp64; /* switch HVPs to FP64 once eta_max < polish_eta */
+  double polish_eta;
+  double eig_tol;
+  int32_t eig_maxit;
+  double time_limit_s; /* 0 = none */
+  int32_t verbose;
+  uint64_t seed;
+} mdsdp_options;
+
+typedef struct {
+  int32_t status;       /* mdsdp_status of the solve */
+  int32_t outer_iters;
+  int64_t rtr_iters, hvps, cost_grads, eig_iters;
+  int32_t p_final, p_max_reached;
+  double value;         /* b^T y */
+  double eta_p, eta_d, eta_g;
+  double sigma;
+  double seconds;
+  double t_eval, t_hvp, t_eig, t_update; /* seconds per phase */
+} mdsdp_result;
+
+void mdsdp_default_options(mdsdp_options* opt);
+/* Y_dev: device buffer of n * p_max doubles; on entry its first n*p0 values
+ * (row-major n x p0) are the start (rows are normalised); on exit it holds
+ * the final Y as row-major n x p_final.  history_host (nullable) receives up
+ * to history_cap records of 8 doubles per outer iteration:
+ * {k, p, sigma, eta_p, eta_d, eta_g, value, hvps}. */
+mdsdp_status mdsdp_solve(mdsdp_problem prob, const mdsdp_options* opt, int32_t p0, double* Y_dev,
+                         mdsdp_result* res, double* history_host, int32_t history_cap,
+                         void* stream);
+
+/* ---- diagnostics -----------------------------------------------------------
+ * Export internal tile-major arrays back to packed order (host buffers of
+ * n(n+1)/2): the class map as seen by the kernels, and Xt. */
+mdsdp_status mdsdp_export_classmap(mdsdp_problem prob, int32_t* cls_host);
+mdsdp_status mdsdp_export_multiplier_packed(mdsdp_problem prob, double* Xt_host);
+/* Per-kernel device timing of the most recent call of each entry point,
+ * measured with HIP events on the launch stream (milliseconds). */
+mdsdp_status mdsdp_kernel_times(mdsdp_problem prob, double* ms_out, int32_t cap,
+                                int32_t* count);
+mdsdp_status mdsdp_enable_timing(mdsdp_problem prob, int32_t on);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MANIDSDP_H */

@@ -1,0 +1,585 @@
+// C ABI entry points: problem construction (host), layout, and the
+// subproblem evaluations, each a short sequence of kernel launches.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "mdsdp_internal.hpp"
+
+namespace mdsdp {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+mdsdp_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
+  return e == hipErrorOutOfMemory ? MDSDP_ENOMEM : MDSDP_EHIP;
+}
+
+static mdsdp_status einval(const std::string& m) {
+  g_err = m;
+  return MDSDP_EINVAL;
+}
+
+// ---------------------------------------------------------------------------
+// BQP relaxation builder (host)
+// ---------------------------------------------------------------------------
+static long long binom(long long a, int k) {
+  if (k < 0 || a < k) return 0;
+  long long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (a - k + i) / i;
+  return r;
+}
+
+struct Mono {
+  int a, b;  // sorted variable indices, -1 = absent
+};
+
+static std::vector<Mono> bqp_basis(int q, int order) {
+  std::vector<Mono> v;
+  v.reserve(1 + q + (size_t)q * (q - 1) / 2);
+  v.push_back({-1, -1});
+  for (int i = 0; i < q; ++i) v.push_back({i, -1});
+  if (order == MDSDP_ORDER_LEX) {
+    for (int i = 0; i < q; ++i)
+      for (int j = i + 1; j < q; ++j) v.push_back({i, j});
+  } else {
+    for (int j = 0; j < q; ++j)
+      for (int i = 0; i < j; ++i) v.push_back({i, j});
+  }
+  return v;
+}
+
+// class id of x^u x^v: symmetric difference of the index sets, ranked by
+// degree, then colex (off[d] + sum_i C(c_i, i)).
+static long long bqp_class(const Mono& u, const Mono& v, const long long* off) {
+  int e[4];
+  int k = 0;
+  const int in[4] = {u.a, u.b, v.a, v.b};
+  for (int t = 0; t < 4; ++t)
+    if (in[t] >= 0) e[k++] = in[t];
+  std::sort(e, e + k);
+  int out[4];
+  int d = 0;
+  for (int t = 0; t < k;) {
+    if (t + 1 < k && e[t] == e[t + 1]) {
+      t += 2;  // x_i^2 = 1
+    } else {
+      out[d++] = e[t++];
+    }
+  }
+  long long id = off[d];
+  for (int i = 0; i < d; ++i) id += binom(out[i], i + 1);
+  return id;
+}
+
+static void bqp_offsets(int q, long long* off) {
+  off[0] = 0;
+  for (int d = 0; d < 5; ++d) off[d + 1] = off[d] + binom(q, d);
+}
+
+}  // namespace mdsdp
+
+using namespace mdsdp;
+
+extern "C" {
+
+const char* mdsdp_last_error(void) { return g_err.c_str(); }
+const char* mdsdp_version(void) { return "manidsdp-gfx950 0.1"; }
+
+mdsdp_status mdsdp_bqp_sizes(int32_t q, int32_t* n_out, int64_t* m_out) {
+  if (q < 1 || q > 362) return einval("q must be in [1, 362] (n < 65536)");
+  long long off[6];
+  bqp_offsets(q, off);
+  if (n_out) *n_out = (int32_t)(1 + q + (long long)q * (q - 1) / 2);
+  if (m_out) *m_out = off[5];
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_bqp_classmap(int32_t q, int32_t order, int32_t* cls_out) {
+  if (q < 1 || q > 362) return einval("q must be in [1, 362]");
+  if (order != MDSDP_ORDER_LEX && order != MDSDP_ORDER_COLEX) return einval("bad basis order");
+  if (!cls_out) return einval("cls_out is NULL");
+  long long off[6];
+  bqp_offsets(q, off);
+  std::vector<Mono> B = bqp_basis(q, order);
+  const long long n = (long long)B.size();
+  long long idx = 0;
+  for (long long r = 0; r < n; ++r)
+    for (long long c = r; c < n; ++c) cls_out[idx++] = (int32_t)bqp_class(B[r], B[c], off);
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_bqp_b(int32_t q, const double* Q, const double* c, double* b) {
+  if (q < 1 || q > 362) return einval("q must be in [1, 362]");
+  if (!Q || !c || !b) return einval("NULL argument");
+  long long off[6];
+  bqp_offsets(q, off);
+  for (long long g = 0; g < off[5]; ++g) b[g] = 0.0;
+  double tr = 0.0;
+  for (int i = 0; i < q; ++i) tr += Q[(size_t)i * q + i];
+  b[0] = tr;
+  for (int i = 0; i < q; ++i) b[off[1] + i] = c[i];
+  for (int j = 0; j < q; ++j)
+    for (int i = 0; i < j; ++i) b[off[2] + binom(i, 1) + binom(j, 2)] = Q[(size_t)i * q + j] + Q[(size_t)j * q + i];
+  return MDSDP_OK;
+}
+
+}  // extern "C"
+
+namespace mdsdp {
+
+static void free_problem(mdsdp_problem P) {
+  if (!P) return;
+  void* ptrs[] = {P->cls,      P->Xt,     P->Xt32,    P->Ct,      P->segs,   P->seg_start, P->cinf,
+                  P->Cavg,     P->sS[0],  P->sS[1],   P->sZ[0],   P->sZ[1],  P->Yp,        P->Up,
+                  P->zvec,     P->zmult,  P->rowpart, P->colpart, P->wgpart, P->zpart,     P->gram,
+                  P->gpart,    P->scal,   P->bound,   P->dotpart, (void*)P->dotptr, P->lz_V, P->lz_w,
+                  P->lz_h,     P->lz_hpart, P->work};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto e : P->timer.ev) (void)hipEventDestroy(e);
+  delete P;
+}
+
+template <typename T>
+static mdsdp_status dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  return MDSDP_OK;
+}
+
+#define TRY(x)                        \
+  do {                                \
+    mdsdp_status st__ = (x);          \
+    if (st__ != MDSDP_OK) {           \
+      free_problem(P);                \
+      return st__;                    \
+    }                                 \
+  } while (0)
+
+static mdsdp_status check_device() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    set_error(std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    return MDSDP_EUNSUPPORTED;
+  }
+  return MDSDP_OK;
+}
+
+// Builds the device problem from a packed-upper class map (row-major).
+static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, const double* b,
+                                       const double* C, mdsdp_problem* out) {
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  if (n < 1 || n >= 65536) return einval("n must be in [1, 65535]");
+  if (m < 1 || m > (long long)CLS_MASK) return einval("m out of range");
+  if (!cls || !b) return einval("cls and b are required");
+  mdsdp_status st = check_device();
+  if (st != MDSDP_OK) return st;
+
+  const long long ne = (long long)n * (n + 1) / 2;
+  std::vector<long long> cnt(m, 0);
+  {
+    long long idx = 0;
+    for (long long r = 0; r < n; ++r)
+      for (long long c = r; c < n; ++c, ++idx) {
+        const long long g = cls[idx];
+        if (g < 0 || g >= m) return einval("class id out of range at packed index " + std::to_string(idx));
+        cnt[g] += (r == c) ? 1 : 2;
+      }
+  }
+  long long kmax = 0;
+  for (long long g = 0; g < m; ++g) {
+    if (cnt[g] == 0) return einval("class " + std::to_string(g) + " is empty (AA* singular)");
+    kmax = std::max(kmax, cnt[g]);
+  }
+  for (long long g = 0; g < m; ++g)
+    if (!std::isfinite(b[g])) return einval("b is not finite");
+
+  mdsdp_problem P = new mdsdp_problem_s();
+  (void)hipGetDevice(&P->device);
+  P->n = n;
+  P->m = m;
+  P->nb = (n + TS - 1) / TS;
+  P->npad = P->nb * TS;
+  P->ntiles = P->nb * (P->nb + 1) / 2;
+  P->nslots = (long long)P->ntiles * TSLOTS;
+  P->kmax = kmax;
+  P->hasC = C != nullptr;
+  double nb2 = 0.0;
+  for (long long g = 0; g < m; ++g) nb2 += b[g] * b[g];
+  P->normb = sqrt(nb2);
+
+  // tile-major class words and C
+  std::vector<uint32_t> hcls(P->nslots);
+  std::vector<double> hC;
+  if (C) hC.assign(P->nslots, 0.0);
+  std::vector<char> seen(m, 0);
+  double nC2 = 0.0;
+  for (int J = 0; J < P->nb; ++J)
+    for (int I = 0; I <= J; ++I) {
+      const long long t = (long long)J * (J + 1) / 2 + I;
+      for (int sb = 0; sb < 16; ++sb)
+        for (int e = 0; e < 256; ++e) {
+          const long long s = t * TSLOTS + sb * 256 + e;
+          const int r = I * TS + (sb >> 2) * SB + (e >> 4);
+          const int c = J * TS + (sb & 3) * SB + (e & 15);
+          if (r >= n || c >= n) {
+            hcls[s] = 0xFFFFFFFFu;
+            continue;
+          }
+          const long long rr = std::min(r, c), cc = std::max(r, c);
+          const long long pidx = rr * n - rr * (rr - 1) / 2 + (cc - rr);
+          const uint32_t g = (uint32_t)cls[pidx];
+          uint32_t wv = g;
+          // owner: first slot of the class in slot order (diagonal tiles hold
+          // both (r, c) and (c, r); either may own)
+          if (!seen[g]) {
+            seen[g] = 1;
+            wv |= OWNER_BIT;
+          }
+          hcls[s] = wv;
+          if (C) hC[s] = C[(size_t)r * n + c];
+        }
+    }
+  if (C)
+    for (long long i = 0; i < (long long)n * n; ++i) nC2 += C[i] * C[i];
+  P->normC = sqrt(nC2);
+
+  // per-class constants
+  std::vector<double2> hcinf(m);
+  for (long long g = 0; g < m; ++g) hcinf[g] = make_double2(b[g] / (double)cnt[g], 1.0 / (double)cnt[g]);
+  std::vector<double> hCavg;
+  if (C) {
+    hCavg.assign(m, 0.0);
+    long long idx = 0;
+    for (long long r = 0; r < n; ++r)
+      for (long long c = r; c < n; ++c, ++idx) hCavg[cls[idx]] += (r == c ? 1.0 : 2.0) * C[(size_t)r * n + c];
+    for (long long g = 0; g < m; ++g) hCavg[g] /= (double)cnt[g];
+  }
+
+  // segments: column block J, row blocks in chunks of SEGLEN
+  const int SEGLEN = 4;
+  std::vector<Seg> hseg;
+  std::vector<int> hstart(P->nb + 1, 0);
+  for (int J = 0; J < P->nb; ++J) {
+    hstart[J] = (int)hseg.size();
+    for (int I0 = 0; I0 <= J; I0 += SEGLEN) hseg.push_back({J, I0, std::min(J, I0 + SEGLEN - 1)});
+  }
+  hstart[P->nb] = (int)hseg.size();
+  P->nseg = (int)hseg.size();
+
+  TRY(dalloc(&P->cls, P->nslots));
+  TRY(dalloc(&P->Xt, P->nslots));
+  TRY(dalloc(&P->Xt32, P->nslots));
+  if (C) TRY(dalloc(&P->Ct, P->nslots));
+  TRY(dalloc(&P->segs, P->nseg));
+  TRY(dalloc(&P->seg_start, P->nb + 1));
+  TRY(dalloc(&P->cinf, m));
+  if (C) TRY(dalloc(&P->Cavg, m));
+  for (int i = 0; i < 2; ++i) {
+    TRY(dalloc(&P->sS[i], m));
+    TRY(dalloc(&P->sZ[i], m));
+  }
+  TRY(dalloc((double**)&P->Yp, (size_t)P->npad * 16));
+  TRY(dalloc((double**)&P->Up, (size_t)P->npad * 16));
+  TRY(dalloc(&P->zvec, n));
+  TRY(dalloc(&P->zmult, n));
+  TRY(dalloc(&P->rowpart, (size_t)P->ntiles * 64 * 16));
+  TRY(dalloc(&P->colpart, (size_t)P->nseg * 64 * 16));
+  TRY(dalloc(&P->wgpart, (size_t)P->nseg * 4));
+  TRY(dalloc(&P->zpart, (size_t)(n * 16 + 255) / 256 + 1));
+  TRY(dalloc(&P->gram, 512));
+  TRY(dalloc(&P->gpart, (size_t)((n + 63) / 64) * 512));
+  TRY(dalloc(&P->scal, SC_COUNT));
+  TRY(dalloc(&P->bound, 2));
+  P->dot_nblk = 256;
+  TRY(dalloc(&P->dotpart, (size_t)P->dot_nblk * 8));
+  TRY(dalloc((double**)&P->dotptr, 16));
+  TRY(dalloc(&P->work, (size_t)n * 16 * 8));
+
+  hipError_t e;
+#define CP(dst, src, bytes)                                      \
+  e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);         \
+  if (e != hipSuccess) {                                         \
+    mdsdp_status s2 = hip_fail(e, "hipMemcpy");                  \
+    free_problem(P);                                             \
+    return s2;                                                   \
+  }
+  CP(P->cls, hcls.data(), P->nslots * sizeof(uint32_t));
+  if (C) CP(P->Ct, hC.data(), P->nslots * sizeof(double));
+  CP(P->segs, hseg.data(), hseg.size() * sizeof(Seg));
+  CP(P->seg_start, hstart.data(), hstart.size() * sizeof(int));
+  CP(P->cinf, hcinf.data(), m * sizeof(double2));
+  if (C) CP(P->Cavg, hCavg.data(), m * sizeof(double));
+#undef CP
+  for (int i = 0; i < 2; ++i) {
+    TRY(hipMemset(P->sS[i], 0, m * sizeof(long long)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
+    TRY(hipMemset(P->sZ[i], 0, m * sizeof(long long)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
+  }
+  TRY(hipMemset(P->scal, 0, SC_COUNT * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
+  TRY(hipMemset(P->zvec, 0, n * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
+  TRY(hipMemset(P->zmult, 0, n * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
+  TRY(launch_set_dense(P, nullptr, nullptr));
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    mdsdp_status s2 = hip_fail(e, "hipDeviceSynchronize");
+    free_problem(P);
+    return s2;
+  }
+  P->sigma = 1.0;
+  *out = P;
+  return MDSDP_OK;
+}
+
+static mdsdp_status check_p(mdsdp_problem P, int p) {
+  if (!P) return einval("problem is NULL");
+  if (p < 1 || p > 16) {
+    set_error("p must be in [1, 16]");
+    return p < 1 ? MDSDP_EINVAL : MDSDP_EUNSUPPORTED;
+  }
+  return MDSDP_OK;
+}
+
+}  // namespace mdsdp
+
+extern "C" {
+
+mdsdp_status mdsdp_create_classmap(int32_t n, int64_t m, const int32_t* cls, const double* b, const double* C,
+                                   mdsdp_problem* out) {
+  return create_from_packed(n, m, cls, b, C, out);
+}
+
+mdsdp_status mdsdp_create_sparse_A(int32_t n, int64_t m, int64_t nnz, const int32_t* cls, const int32_t* row,
+                                   const int32_t* col, const double* val, const double* b, const double* C,
+                                   mdsdp_problem* out) {
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  if (n < 1 || n >= 65536) return einval("n must be in [1, 65535]");
+  if (nnz < 0 || !cls || !row || !col || !val) return einval("sparse A arrays required");
+  const long long ne = (long long)n * (n + 1) / 2;
+  std::vector<int32_t> packed(ne, -1);
+  for (long long t = 0; t < nnz; ++t) {
+    const long long r = row[t], c = col[t];
+    if (r < 0 || c < r || c >= n) return einval("sparse A entry not in the upper triangle");
+    if (cls[t] < 0 || cls[t] >= m) return einval("sparse A class out of range");
+    if (val[t] != 1.0) {
+      set_error("only 0/1 class-indicator constraint matrices are supported");
+      return MDSDP_EUNSUPPORTED;
+    }
+    const long long pidx = r * n - r * (r - 1) / 2 + (c - r);
+    if (packed[pidx] >= 0) {
+      set_error("sparse A supports overlap at (" + std::to_string(r) + ", " + std::to_string(c) + ")");
+      return MDSDP_ENOTORTH;
+    }
+    packed[pidx] = cls[t];
+  }
+  for (long long i = 0; i < ne; ++i)
+    if (packed[i] < 0) {
+      set_error("sparse A leaves matrix entries uncovered");
+      return MDSDP_EUNSUPPORTED;
+    }
+  return create_from_packed(n, m, packed.data(), b, C, out);
+}
+
+mdsdp_status mdsdp_destroy(mdsdp_problem P) {
+  if (!P) return einval("problem is NULL");
+  (void)hipDeviceSynchronize();
+  free_problem(P);
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_problem_info(mdsdp_problem P, int32_t* n, int64_t* m, int64_t* n_slots, int32_t* n_tiles) {
+  if (!P) return einval("problem is NULL");
+  if (n) *n = P->n;
+  if (m) *m = P->m;
+  if (n_slots) *n_slots = P->nslots;
+  if (n_tiles) *n_tiles = P->ntiles;
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_set_multiplier(mdsdp_problem P, const double* Xt_dev, double sigma, void* stream) {
+  if (!P) return einval("problem is NULL");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return einval("sigma must be positive and finite");
+  P->sigma = sigma;
+  return launch_set_dense(P, Xt_dev, (hipStream_t)stream);
+}
+
+mdsdp_status mdsdp_get_multiplier(mdsdp_problem P, double* Xt_dev, void* stream) {
+  if (!P || !Xt_dev) return einval("NULL argument");
+  return launch_get_dense(P, Xt_dev, false, (hipStream_t)stream);
+}
+
+mdsdp_status mdsdp_set_sigma(mdsdp_problem P, double sigma) {
+  if (!P) return einval("problem is NULL");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return einval("sigma must be positive and finite");
+  P->sigma = sigma;
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_cost_grad(mdsdp_problem P, int32_t p, const double* Y, double* f, double* egrad,
+                             double* rgrad, void* stream) {
+  mdsdp_status st = check_p(P, p);
+  if (st != MDSDP_OK) return st;
+  if (!Y) return einval("Y is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = launch_stage(P, p, Y, nullptr, false, s)) != MDSDP_OK) return st;
+  if ((st = launch_classsum_S(P, s)) != MDSDP_OK) return st;
+  if ((st = launch_resid(P, M_GRAD, false, s)) != MDSDP_OK) return st;
+  return launch_rowfinal_grad(P, p, Y, egrad, rgrad, f, s);
+}
+
+mdsdp_status mdsdp_hvp(mdsdp_problem P, int32_t p, int32_t prec, const double* Y, const double* U, double* HU,
+                       int32_t riemannian, void* stream) {
+  mdsdp_status st = check_p(P, p);
+  if (st != MDSDP_OK) return st;
+  if (!Y || !U || !HU) return einval("NULL argument");
+  if (prec != MDSDP_FP64 && prec != MDSDP_FP32) return einval("bad precision");
+  const bool fp32 = prec == MDSDP_FP32;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = launch_stage(P, p, Y, U, fp32, s)) != MDSDP_OK) return st;
+  if ((st = launch_gram(P, p, Y, U, s)) != MDSDP_OK) return st;
+  if ((st = launch_classsum_Z(P, fp32, s)) != MDSDP_OK) return st;
+  if ((st = launch_resid(P, M_HVP, fp32, s)) != MDSDP_OK) return st;
+  return launch_rowfinal_hvp(P, p, fp32, Y, U, HU, riemannian ? 1 : 0, s);
+}
+
+mdsdp_status mdsdp_class_average(mdsdp_problem P, int32_t p, const double* Y, double* y, void* stream) {
+  mdsdp_status st = check_p(P, p);
+  if (st != MDSDP_OK) return st;
+  if (!Y || !y) return einval("NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = launch_stage(P, p, Y, nullptr, false, s)) != MDSDP_OK) return st;
+  if ((st = launch_classsum_S(P, s)) != MDSDP_OK) return st;
+  return launch_y_export(P, y, s);
+}
+
+mdsdp_status mdsdp_retract(int32_t n, int32_t p, const double* Y, const double* V, double t, double* Yout,
+                           void* stream) {
+  if (n < 1 || p < 1) return einval("bad sizes");
+  if (!Y || !V || !Yout) return einval("NULL argument");
+  return launch_retract(n, p, Y, V, t, Yout, (hipStream_t)stream);
+}
+
+mdsdp_status mdsdp_project_tangent(int32_t n, int32_t p, const double* Y, const double* U, double* out,
+                                   void* stream) {
+  if (n < 1 || p < 1) return einval("bad sizes");
+  if (!Y || !U || !out) return einval("NULL argument");
+  return launch_project(n, p, Y, U, out, (hipStream_t)stream);
+}
+
+mdsdp_status mdsdp_update_multiplier(mdsdp_problem P, int32_t p, const double* Y, double* y, double* z,
+                                     double* kkt, void* stream) {
+  mdsdp_status st = check_p(P, p);
+  if (st != MDSDP_OK) return st;
+  if (!Y) return einval("Y is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = launch_stage(P, p, Y, nullptr, false, s)) != MDSDP_OK) return st;
+  if ((st = launch_classsum_S(P, s)) != MDSDP_OK) return st;
+  if (y && (st = launch_y_export(P, y, s)) != MDSDP_OK) return st;
+  if ((st = launch_resid(P, M_MULT, false, s)) != MDSDP_OK) return st;
+  return launch_rowfinal_mult(P, p, Y, z, kkt, s);
+}
+
+mdsdp_status mdsdp_certificate_matvec(mdsdp_problem P, int32_t k, const double* V, double* XV, void* stream) {
+  mdsdp_status st = check_p(P, k);
+  if (st != MDSDP_OK) return st;
+  if (!V || !XV) return einval("NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = launch_stage(P, k, V, V, false, s)) != MDSDP_OK) return st;
+  if ((st = launch_resid(P, M_XMV, false, s)) != MDSDP_OK) return st;
+  return launch_rowfinal_xmv(P, k, V, XV, s);
+}
+
+mdsdp_status mdsdp_adjoint_C(mdsdp_problem P, double* dC, void* stream) {
+  if (!P || !dC) return einval("NULL argument");
+  return launch_get_dense(P, dC, true, (hipStream_t)stream);
+}
+
+mdsdp_status mdsdp_export_classmap(mdsdp_problem P, int32_t* out) {
+  if (!P || !out) return einval("NULL argument");
+  std::vector<uint32_t> h(P->nslots);
+  MDSDP_HIP(hipMemcpy(h.data(), P->cls, P->nslots * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  const int n = P->n;
+  for (int J = 0; J < P->nb; ++J)
+    for (int I = 0; I <= J; ++I) {
+      const long long t = (long long)J * (J + 1) / 2 + I;
+      for (int sb = 0; sb < 16; ++sb)
+        for (int e = 0; e < 256; ++e) {
+          const int r = I * TS + (sb >> 2) * SB + (e >> 4);
+          const int c = J * TS + (sb & 3) * SB + (e & 15);
+          if (r >= n || c >= n || r > c) continue;
+          const long long pidx = (long long)r * n - (long long)r * (r - 1) / 2 + (c - r);
+          out[pidx] = (int32_t)(h[t * TSLOTS + sb * 256 + e] & CLS_MASK);
+        }
+    }
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_export_multiplier_packed(mdsdp_problem P, double* out) {
+  if (!P || !out) return einval("NULL argument");
+  std::vector<double> h(P->nslots);
+  MDSDP_HIP(hipMemcpy(h.data(), P->Xt, P->nslots * sizeof(double), hipMemcpyDeviceToHost));
+  const int n = P->n;
+  for (int J = 0; J < P->nb; ++J)
+    for (int I = 0; I <= J; ++I) {
+      const long long t = (long long)J * (J + 1) / 2 + I;
+      for (int sb = 0; sb < 16; ++sb)
+        for (int e = 0; e < 256; ++e) {
+          const int r = I * TS + (sb >> 2) * SB + (e >> 4);
+          const int c = J * TS + (sb & 3) * SB + (e & 15);
+          if (r >= n || c >= n || r > c) continue;
+          const long long pidx = (long long)r * n - (long long)r * (r - 1) / 2 + (c - r);
+          out[pidx] = h[t * TSLOTS + sb * 256 + e];
+        }
+    }
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_enable_timing(mdsdp_problem P, int32_t on) {
+  if (!P) return einval("problem is NULL");
+  P->timer.on = on != 0;
+  for (auto e : P->timer.ev) (void)hipEventDestroy(e);
+  P->timer.ev.clear();
+  P->timer.names.clear();
+  return MDSDP_OK;
+}
+
+// Returns, per timed kernel launch since the last call, the elapsed time in
+// ms (synchronises).  Names are concatenated as "name;name;..." in the error
+// buffer for diagnostics.
+mdsdp_status mdsdp_kernel_times(mdsdp_problem P, double* ms_out, int32_t cap, int32_t* count) {
+  if (!P || !count) return einval("NULL argument");
+  MDSDP_HIP(hipDeviceSynchronize());
+  std::string names;
+  int k = 0;
+  auto& T = P->timer;
+  for (size_t i = 0; i + 1 < T.ev.size(); i += 2) {
+    float ms = 0.f;
+    MDSDP_HIP(hipEventElapsedTime(&ms, T.ev[i], T.ev[i + 1]));
+    if (k < cap && ms_out) ms_out[k] = ms;
+    names += T.names[i] + ";";
+    ++k;
+  }
+  for (auto e : T.ev) (void)hipEventDestroy(e);
+  T.ev.clear();
+  T.names.clear();
+  *count = k;
+  g_err = names;
+  return MDSDP_OK;
+}
+
+}  // extern "C"

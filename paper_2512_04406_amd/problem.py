@@ -1,0 +1,264 @@
+"""Python face of the library: one `Problem` per DSDP instance.
+
+PyTorch supplies device memory and the current HIP stream; every operation is
+a call into libmanidsdp.so (see include/manidsdp.h for the definitions).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Options, Result, call, lib
+
+FP64, FP32 = 0, 1
+ORDER_LEX, ORDER_COLEX = 0, 1
+
+
+def _ptr(t) -> C.c_void_p:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return C.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    raise TypeError(type(t))
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return t
+
+
+def bqp_sizes(q: int) -> tuple[int, int]:
+    n = C.c_int32()
+    m = C.c_int64()
+    call("mdsdp_bqp_sizes", q, C.byref(n), C.byref(m))
+    return n.value, m.value
+
+
+def bqp_classmap(q: int, order: int = ORDER_COLEX) -> np.ndarray:
+    """Packed upper-triangle class ids (row-major) of the order-2 BQP relaxation."""
+    n, _ = bqp_sizes(q)
+    out = np.empty(n * (n + 1) // 2, dtype=np.int32)
+    call("mdsdp_bqp_classmap", q, order, _ptr(out))
+    return out
+
+
+def bqp_b(Q: np.ndarray, c: np.ndarray) -> np.ndarray:
+    q = c.size
+    _, m = bqp_sizes(q)
+    Qc = np.ascontiguousarray(Q, dtype=np.float64)
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    out = np.empty(m, dtype=np.float64)
+    call("mdsdp_bqp_b", q, _ptr(Qc), _ptr(cc), _ptr(out))
+    return out
+
+
+@dataclass
+class SolveResult:
+    Y: torch.Tensor
+    value: float
+    eta: tuple
+    status: int
+    outer_iters: int
+    rtr_iters: int
+    hvps: int
+    cost_grads: int
+    eig_iters: int
+    p_final: int
+    p_max_reached: int
+    sigma: float
+    seconds: float
+    phases: dict
+    history: np.ndarray
+
+
+class Problem:
+    """A DSDP instance with class-indicator constraints, resident on the GPU."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+        n = C.c_int32()
+        m = C.c_int64()
+        ns = C.c_int64()
+        nt = C.c_int32()
+        call("mdsdp_problem_info", self._h, C.byref(n), C.byref(m), C.byref(ns), C.byref(nt))
+        self.n, self.m, self.n_slots, self.n_tiles = n.value, m.value, ns.value, nt.value
+        self.sigma = 1.0
+
+    # ---- construction -------------------------------------------------------
+    @classmethod
+    def from_classmap(cls, n: int, cls_packed: np.ndarray, b: np.ndarray, C_dense: np.ndarray | None = None):
+        clsp = np.ascontiguousarray(cls_packed, dtype=np.int32)
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        if clsp.size != n * (n + 1) // 2:
+            raise ValueError("class map must hold n(n+1)/2 packed entries")
+        Cd = None if C_dense is None else np.ascontiguousarray(C_dense, dtype=np.float64)
+        h = C.c_void_p()
+        call("mdsdp_create_classmap", n, bb.size, _ptr(clsp), _ptr(bb), _ptr(Cd), C.byref(h))
+        return cls(h)
+
+    @classmethod
+    def from_sparse_A(cls, n, m, cls_idx, rows, cols, vals, b, C_dense=None):
+        ci = np.ascontiguousarray(cls_idx, dtype=np.int32)
+        ri = np.ascontiguousarray(rows, dtype=np.int32)
+        co = np.ascontiguousarray(cols, dtype=np.int32)
+        va = np.ascontiguousarray(vals, dtype=np.float64)
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        Cd = None if C_dense is None else np.ascontiguousarray(C_dense, dtype=np.float64)
+        h = C.c_void_p()
+        call("mdsdp_create_sparse_A", n, m, ci.size, _ptr(ci), _ptr(ri), _ptr(co), _ptr(va), _ptr(bb),
+             _ptr(Cd), C.byref(h))
+        return cls(h)
+
+    @classmethod
+    def bqp(cls, Q: np.ndarray, c: np.ndarray, order: int = ORDER_COLEX):
+        q = c.size
+        n, _ = bqp_sizes(q)
+        return cls.from_classmap(n, bqp_classmap(q, order), bqp_b(Q, c))
+
+    def close(self):
+        if self._h:
+            call("mdsdp_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().mdsdp_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    # ---- multiplier -----------------------------------------------------------
+    def set_multiplier(self, Xt: torch.Tensor | None, sigma: float) -> None:
+        if Xt is not None:
+            _dev_f64(Xt, "Xt")
+            if Xt.shape != (self.n, self.n):
+                raise ValueError("Xt must be n x n")
+        call("mdsdp_set_multiplier", self._h, _ptr(Xt), float(sigma), _stream())
+        self.sigma = float(sigma)
+
+    def set_sigma(self, sigma: float) -> None:
+        call("mdsdp_set_sigma", self._h, float(sigma))
+        self.sigma = float(sigma)
+
+    def get_multiplier(self) -> torch.Tensor:
+        X = torch.empty(self.n, self.n, dtype=torch.float64, device="cuda")
+        call("mdsdp_get_multiplier", self._h, _ptr(X), _stream())
+        return X
+
+    # ---- evaluations ------------------------------------------------------------
+    def cost_grad(self, Y: torch.Tensor, want_egrad: bool = True, want_rgrad: bool = True):
+        _dev_f64(Y, "Y")
+        n, p = Y.shape
+        f = torch.empty(1, dtype=torch.float64, device=Y.device)
+        eg = torch.empty_like(Y) if want_egrad else None
+        rg = torch.empty_like(Y) if want_rgrad else None
+        call("mdsdp_cost_grad", self._h, p, _ptr(Y), _ptr(f), _ptr(eg), _ptr(rg), _stream())
+        return f, eg, rg
+
+    def hvp(self, Y: torch.Tensor, U: torch.Tensor, prec: int = FP64, riemannian: bool = True,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+        _dev_f64(Y, "Y")
+        _dev_f64(U, "U")
+        if out is None:
+            out = torch.empty_like(U)
+        call("mdsdp_hvp", self._h, Y.shape[1], prec, _ptr(Y), _ptr(U), _ptr(out), 1 if riemannian else 0,
+             _stream())
+        return out
+
+    def class_average(self, Y: torch.Tensor) -> torch.Tensor:
+        _dev_f64(Y, "Y")
+        y = torch.empty(self.m, dtype=torch.float64, device=Y.device)
+        call("mdsdp_class_average", self._h, Y.shape[1], _ptr(Y), _ptr(y), _stream())
+        return y
+
+    def update_multiplier(self, Y: torch.Tensor):
+        _dev_f64(Y, "Y")
+        y = torch.empty(self.m, dtype=torch.float64, device=Y.device)
+        z = torch.empty(self.n, dtype=torch.float64, device=Y.device)
+        kkt = torch.empty(4, dtype=torch.float64, device=Y.device)
+        call("mdsdp_update_multiplier", self._h, Y.shape[1], _ptr(Y), _ptr(y), _ptr(z), _ptr(kkt), _stream())
+        return y, z, kkt
+
+    def certificate_matvec(self, V: torch.Tensor) -> torch.Tensor:
+        _dev_f64(V, "V")
+        XV = torch.empty_like(V)
+        call("mdsdp_certificate_matvec", self._h, V.shape[1], _ptr(V), _ptr(XV), _stream())
+        return XV
+
+    def min_eigpair(self, tol: float = 1e-10, maxit: int = 300, seed: int = 0):
+        lmin = C.c_double()
+        lmax = C.c_double()
+        it = C.c_int32()
+        v = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        code = lib().mdsdp_min_eigpair(self._h, tol, maxit, seed, C.byref(lmin), C.byref(lmax), _ptr(v),
+                                        C.byref(it), _stream())
+        if code not in (0, -7):
+            _lib.check(code, "mdsdp_min_eigpair")
+        return lmin.value, lmax.value, v, it.value, code == 0
+
+    def adjoint_C(self) -> torch.Tensor:
+        X = torch.empty(self.n, self.n, dtype=torch.float64, device="cuda")
+        call("mdsdp_adjoint_C", self._h, _ptr(X), _stream())
+        return X
+
+    def export_classmap(self) -> np.ndarray:
+        out = np.empty(self.n * (self.n + 1) // 2, dtype=np.int32)
+        call("mdsdp_export_classmap", self._h, _ptr(out))
+        return out
+
+    def export_multiplier_packed(self) -> np.ndarray:
+        out = np.empty(self.n * (self.n + 1) // 2, dtype=np.float64)
+        call("mdsdp_export_multiplier_packed", self._h, _ptr(out))
+        return out
+
+    def enable_timing(self, on: bool = True) -> None:
+        call("mdsdp_enable_timing", self._h, 1 if on else 0)
+
+    def kernel_times(self) -> list[tuple[str, float]]:
+        cap = 1 << 16
+        buf = np.empty(cap, dtype=np.float64)
+        cnt = C.c_int32()
+        call("mdsdp_kernel_times", self._h, _ptr(buf), cap, C.byref(cnt))
+        names = lib().mdsdp_last_error().decode().split(";")[: cnt.value]
+        return list(zip(names, buf[: cnt.value].tolist()))
+
+    # ---- solve ------------------------------------------------------------------
+    @staticmethod
+    def default_options() -> Options:
+        o = Options()
+        lib().mdsdp_default_options(C.byref(o))
+        return o
+
+    def solve(self, Y0: torch.Tensor, opts: Options | None = None, history_cap: int = 1000) -> SolveResult:
+        _dev_f64(Y0, "Y0")
+        opts = opts or self.default_options()
+        n, p0 = Y0.shape
+        Ybuf = torch.zeros(n * max(opts.p_max, p0), dtype=torch.float64, device=Y0.device)
+        Ybuf[: n * p0] = Y0.reshape(-1)
+        res = Result()
+        hist = np.zeros((history_cap, 8), dtype=np.float64)
+        code = lib().mdsdp_solve(self._h, C.byref(opts), p0, _ptr(Ybuf), C.byref(res), _ptr(hist), history_cap,
+                                 _stream())
+        if code not in (0, -7):
+            _lib.check(code, "mdsdp_solve")
+        torch.cuda.current_stream().synchronize()
+        Y = Ybuf[: n * res.p_final].reshape(n, res.p_final).clone()
+        return SolveResult(Y=Y, value=res.value, eta=(res.eta_p, res.eta_d, res.eta_g), status=res.status,
+                           outer_iters=res.outer_iters, rtr_iters=res.rtr_iters, hvps=res.hvps,
+                           cost_grads=res.cost_grads, eig_iters=res.eig_iters, p_final=res.p_final,
+                           p_max_reached=res.p_max_reached, sigma=res.sigma, seconds=res.seconds,
+                           phases=dict(eval=res.t_eval, hvp=res.t_hvp, eig=res.t_eig, update=res.t_update),
+                           history=hist[: min(res.outer_iters, history_cap)].copy())

@@ -1,0 +1,75 @@
+"""CPU-side checks of the C ABI library (no GPU needed): every symbol the
+header declares is exported, the host BQP builder is bit-exact with the
+oracle, and argument validation fails synchronously with MDSDP_EINVAL."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bqp
+from synth import bqp_instance
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "manidsdp.h")
+LIB = os.path.join(ROOT, "paper_2512_04406_amd", "libmanidsdp.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libmanidsdp.so not built")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mdsdp_[A-Za-z_0-9]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    lib = C.CDLL(LIB)
+    names = _declared()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_header():
+    from paper_2512_04406_amd import _lib
+
+    assert set(_declared()) == set(_lib.SIGNATURES)
+
+
+@pytest.mark.parametrize("order,oname", [(0, "lex"), (1, "colex")])
+@pytest.mark.parametrize("q", [1, 2, 3, 6, 11, 20, 33])
+def test_builder_classmap_bit_exact(q, order, oname):
+    from paper_2512_04406_amd.problem import bqp_classmap, bqp_sizes
+
+    n, m = bqp_sizes(q)
+    ref = bqp.class_map_packed(q, oname)
+    got = bqp_classmap(q, order)
+    assert got.shape == ref.shape and got.dtype == np.int32
+    assert got.tobytes() == ref.tobytes()
+    assert m == bqp.m_sos_closed_form(q)
+
+
+@pytest.mark.parametrize("q", [4, 9, 17])
+def test_builder_b_matches_oracle(q):
+    from paper_2512_04406_amd.problem import bqp_b
+
+    Q, c = bqp_instance(q, 3)
+    Q = Q + np.diag(np.arange(q, dtype=float))  # exercise the trace term
+    np.testing.assert_array_equal(bqp_b(Q, c), bqp.build_b(q, Q, c))
+
+
+def test_argument_validation_is_synchronous():
+    from paper_2512_04406_amd import _lib
+
+    L = _lib.lib()
+    h = C.c_void_p()
+    cls = np.zeros(1, dtype=np.int32)
+    b = np.zeros(1)
+    assert L.mdsdp_create_classmap(0, 1, cls.ctypes.data_as(C.c_void_p), b.ctypes.data_as(C.c_void_p), None,
+                                   C.byref(h)) == -1
+    assert L.mdsdp_bqp_sizes(0, None, None) == -1
+    assert L.mdsdp_cost_grad(None, 2, None, None, None, None, None) == -1
+    assert b"NULL" in L.mdsdp_last_error() or b"problem" in L.mdsdp_last_error()

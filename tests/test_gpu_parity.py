@@ -1,0 +1,184 @@
+"""GPU parity of the HIP hot path against the FP64 oracle (element by element).
+
+Cases span one ragged tile (n = 7, 22), several 64-tiles with ragged tails
+(n = 79, 211, 466, 821) and p = 1..16.  Inputs: random (Q, c), Y with unit
+rows, tangent U, a multiplier Xt with A(Xt) = 0, sigma > 0.  FP64 outputs must
+agree to 1e-10 relative (Frobenius, scaled by the reference's norm); class
+averages to 1e-12 absolute on values of size <= 1; the FP32-tile HVP is
+reported and gated at 1e-4.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import bqp
+from oracle.operators import D_matrix, Q_op, class_average
+from oracle.subproblem import Subproblem, proj_tangent
+from synth import bqp_instance, gaussian
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = [(2, 3), (5, 2), (6, 7), (10, 2), (12, 5), (20, 4), (30, 16), (40, 7)]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _case(q, p, seed=0, sigma=1.7):
+    from paper_2512_04406_amd.problem import ORDER_COLEX, Problem
+
+    Q, c = bqp_instance(q, seed)
+    rel = bqp.build_relaxation(Q, c, "colex")
+    print(f"[case] q={q} n={rel.n} m={rel.m} p={p} seed={seed}", flush=True)
+    W = gaussian(rel.n, rel.n, 1000 + seed)
+    Xt = Q_op(0.1 * (W + W.T), rel.cls, rel.counts)
+    Y = gaussian(rel.n, p, 2000 + seed)
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    U = proj_tangent(Y, gaussian(rel.n, p, 3000 + seed))
+    sub = Subproblem(rel.cls, rel.counts, rel.b, Xt, sigma)
+    prob = Problem.bqp(Q, c, ORDER_COLEX)
+    prob.set_multiplier(torch.from_numpy(Xt).cuda(), sigma)
+    return rel, sub, prob, Xt, Y, U, sigma
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("q,p", CASES)
+def test_cost_grad_parity(q, p):
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+    f, eg, rg = prob.cost_grad(_t(Y))
+    torch.cuda.synchronize()
+    f_ref = sub.cost(Y)
+    assert abs(f.item() - f_ref) <= 1e-10 * (1 + abs(f_ref))
+    assert _rel(eg.cpu().numpy(), sub.egrad(Y)) <= 1e-10
+    assert _rel(rg.cpu().numpy(), sub.rgrad(Y)) <= 1e-10
+
+
+@pytest.mark.parametrize("q,p", CASES)
+def test_hvp_parity_fp64(q, p):
+    from paper_2512_04406_amd.problem import FP64
+
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+    Yt, Ut = _t(Y), _t(U)
+    prob.cost_grad(Yt)
+    Hr = prob.hvp(Yt, Ut, FP64, riemannian=True)
+    He = prob.hvp(Yt, Ut, FP64, riemannian=False)
+    torch.cuda.synchronize()
+    assert _rel(Hr.cpu().numpy(), sub.rhess(Y, U)) <= 1e-10
+    assert _rel(He.cpu().numpy(), sub.ehess(Y, U)) <= 1e-10
+
+
+@pytest.mark.parametrize("q,p", CASES)
+def test_hvp_parity_fp32_tiles(q, p):
+    from paper_2512_04406_amd.problem import FP32
+
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+    Yt, Ut = _t(Y), _t(U)
+    prob.cost_grad(Yt)
+    Hr = prob.hvp(Yt, Ut, FP32, riemannian=True)
+    torch.cuda.synchronize()
+    err = _rel(Hr.cpu().numpy(), sub.rhess(Y, U))
+    print(f"[fp32-hvp] q={q} p={p} rel err {err:.3e}")
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("q,p", CASES[:6])
+def test_class_average_parity(q, p):
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+    y = prob.class_average(_t(Y)).cpu().numpy()
+    y_ref = class_average(Y @ Y.T, rel.cls, rel.counts)
+    assert np.max(np.abs(y - y_ref)) <= 1e-12
+
+
+@pytest.mark.parametrize("q,p", [(6, 3), (12, 5), (30, 16), (40, 4)])
+def test_update_multiplier_and_certificate_parity(q, p):
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+    Yt = _t(Y)
+    y, z, kkt = prob.update_multiplier(Yt)
+    torch.cuda.synchronize()
+    S = Y @ Y.T
+    y_ref = class_average(S, rel.cls, rel.counts)
+    R = Q_op(S, rel.cls, rel.counts)
+    Xt1 = Xt + sigma * R
+    D = D_matrix(rel.b, rel.cls, rel.counts)
+    z_ref = np.einsum("ij,ij->i", (Xt1 + D) @ Y, Y)
+    assert np.max(np.abs(y.cpu().numpy() - y_ref)) <= 1e-12
+    assert _rel(z.cpu().numpy(), z_ref) <= 1e-10
+    k = kkt.cpu().numpy()
+    assert abs(k[0] - np.linalg.norm(R)) <= 1e-10 * (1 + np.linalg.norm(R))
+    assert abs(k[1] - rel.b @ y_ref) <= 1e-10 * (1 + abs(rel.b @ y_ref))
+    assert abs(k[2] - z_ref.sum()) <= 1e-10 * (1 + np.abs(z_ref).sum())
+    iu = np.triu_indices(rel.n)
+    Xp = prob.export_multiplier_packed()
+    assert _rel(Xp, Xt1[iu]) <= 1e-13
+    # certificate matvec X V = (Xt + D) V - z o V
+    X = Xt1 + D - np.diag(z_ref)
+    V = gaussian(rel.n, 3, 77)
+    XV = prob.certificate_matvec(_t(V)).cpu().numpy()
+    assert _rel(XV, X @ V) <= 1e-10
+    # adjoint dv/dC = Xt + D
+    dC = prob.adjoint_C().cpu().numpy()
+    assert _rel(dC, Xt1 + D) <= 1e-13
+
+
+def test_determinism_bitwise():
+    from paper_2512_04406_amd.problem import FP32, FP64
+
+    rel, sub, prob, Xt, Y, U, sigma = _case(30, 16)
+    Yt, Ut = _t(Y), _t(U)
+    outs = []
+    for _ in range(3):
+        f, eg, rg = prob.cost_grad(Yt)
+        h64 = prob.hvp(Yt, Ut, FP64)
+        h32 = prob.hvp(Yt, Ut, FP32)
+        torch.cuda.synchronize()
+        outs.append([f.cpu().numpy().tobytes(), eg.cpu().numpy().tobytes(), h64.cpu().numpy().tobytes(),
+                     h32.cpu().numpy().tobytes()])
+    assert outs[0] == outs[1] == outs[2]
+
+
+def test_retract_and_project_parity():
+    from paper_2512_04406_amd import _lib
+    from paper_2512_04406_amd.problem import _ptr, _stream
+
+    n, p = 301, 5
+    Y = gaussian(n, p, 1)
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    V = gaussian(n, p, 2)
+    out = torch.empty(n, p, dtype=torch.float64, device="cuda")
+    _lib.call("mdsdp_retract", n, p, _ptr(_t(Y)), _ptr(_t(V)), 0.3, _ptr(out), _stream())
+    ref = (Y + 0.3 * V) / np.linalg.norm(Y + 0.3 * V, axis=1, keepdims=True)
+    assert _rel(out.cpu().numpy(), ref) <= 1e-14
+    _lib.call("mdsdp_project_tangent", n, p, _ptr(_t(Y)), _ptr(_t(V)), _ptr(out), _stream())
+    assert _rel(out.cpu().numpy(), proj_tangent(Y, V)) <= 1e-14
+
+
+def test_nonzero_C_parity():
+    """Generic class map with C != 0 (DSDP allows any C): cost, gradient, HVP."""
+    from paper_2512_04406_amd.problem import FP64, Problem
+
+    q, p, sigma = 6, 3, 0.9
+    Q, c = bqp_instance(q, 4)
+    rel = bqp.build_relaxation(Q, c, "lex")
+    Cm = gaussian(rel.n, rel.n, 5)
+    Cm = 0.05 * (Cm + Cm.T)
+    W = gaussian(rel.n, rel.n, 6)
+    Xt = Q_op(0.1 * (W + W.T), rel.cls, rel.counts)
+    sub = Subproblem(rel.cls, rel.counts, rel.b, Xt, sigma, C=Cm)
+    iu = np.triu_indices(rel.n)
+    prob = Problem.from_classmap(rel.n, rel.cls[iu].astype(np.int32), rel.b, Cm)
+    prob.set_multiplier(_t(Xt), sigma)
+    Y = gaussian(rel.n, p, 7)
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    U = proj_tangent(Y, gaussian(rel.n, p, 8))
+    f, eg, rg = prob.cost_grad(_t(Y))
+    H = prob.hvp(_t(Y), _t(U), FP64)
+    torch.cuda.synchronize()
+    assert abs(f.item() - sub.cost(Y)) <= 1e-10 * (1 + abs(sub.cost(Y)))
+    assert _rel(rg.cpu().numpy(), sub.rgrad(Y)) <= 1e-10
+    assert _rel(H.cpu().numpy(), sub.rhess(Y, U)) <= 1e-10
