@@ -59,8 +59,9 @@ typedef enum {
   MDSDP_ENOCONV = -7      /* iteration limit reached before the tolerance */
 } mdsdp_status;
 
-/* Tile precision of the HVP pass.  Class sums are always accumulated in
- * 64-bit fixed point; cost, gradient, multiplier update and KKT are FP64. */
+/* Tile precision of the HVP pass.  Class sums are accumulated in FP64
+ * (structured BQP path) or in 64-bit fixed point (generic class maps); cost,
+ * gradient, multiplier update and KKT are always FP64. */
 typedef enum { MDSDP_FP64 = 0, MDSDP_FP32 = 1 } mdsdp_prec;
 
 /* Basis order for the BQP builder: paper order (lexicographic products) or the
@@ -88,8 +89,7 @@ mdsdp_status mdsdp_bqp_b(int32_t q, const double* Q_host, const double* c_host, 
 
 /* ---- problem lifetime ------------------------------------------------------
  * mdsdp_create_classmap: cls_host = packed upper-triangle class ids (row-major,
- * length n(n+1)/2, ids in [0, m), every class non-empty, all diagonal entries
- * in classes that contain only diagonal entries is NOT required); b_host
+ * length n(n+1)/2, ids in [0, m), every class non-empty); b_host
  * length m; C_host = dense symmetric n x n row-major or NULL for C = 0.
  * Computes |gamma| (= AA*), D = b/|gamma|, A(C), builds the tile-major device
  * layout and allocates all workspaces.  Xt starts at 0, sigma at 1.
@@ -98,6 +98,13 @@ mdsdp_status mdsdp_bqp_b(int32_t q, const double* Q_host, const double* c_host, 
 mdsdp_status mdsdp_create_classmap(int32_t n, int64_t m, const int32_t* cls_host,
                                    const double* b_host, const double* C_host,
                                    mdsdp_problem* out);
+/* BQP relaxation built in-library from Q (q x q row-major host) and c (q,
+ * host), in the given basis order.  With MDSDP_ORDER_COLEX the class sums use
+ * structured kernels that read no class map and use no atomics (the class
+ * structure of the order-2 BQP relaxation is arithmetic); results agree with
+ * the generic class-map path to rounding.  Errors as mdsdp_create_classmap. */
+mdsdp_status mdsdp_create_bqp(int32_t q, int32_t order, const double* Q_host, const double* c_host,
+                              mdsdp_problem* out);
 /* Sparse A given as a list of (class, row, col, value) with row <= col; values
  * must all be 1 (0/1 indicators) and every (row, col) of the upper triangle
  * must be covered exactly once (disjoint supports; AA* diagonal).  Overlaps:
@@ -112,7 +119,8 @@ mdsdp_status mdsdp_problem_info(mdsdp_problem prob, int32_t* n, int64_t* m, int6
 
 /* ---- multiplier and penalty ------------------------------------------------
  * set: Xt_dev = dense symmetric n x n row-major FP64 device matrix, or NULL for
- * Xt = 0 (the spec lambda is -Xt).  get: writes the same layout. */
+ * Xt = 0.  Writing the subproblem residual as Q(S + C) - lambda/sigma, the
+ * multiplier lambda is -Xt.  get: writes the same layout. */
 mdsdp_status mdsdp_set_multiplier(mdsdp_problem prob, const double* Xt_dev, double sigma,
                                   void* stream);
 mdsdp_status mdsdp_get_multiplier(mdsdp_problem prob, double* Xt_dev, void* stream);

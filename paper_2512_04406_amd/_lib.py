@@ -50,6 +50,7 @@ SIGNATURES = {
     "mdsdp_bqp_classmap": (_i32, [_i32, _i32, _vp]),
     "mdsdp_bqp_b": (_i32, [_i32, _vp, _vp, _vp]),
     "mdsdp_create_classmap": (_i32, [_i32, _i64, _vp, _vp, _vp, C.POINTER(_vp)]),
+    "mdsdp_create_bqp": (_i32, [_i32, _i32, _vp, _vp, C.POINTER(_vp)]),
     "mdsdp_create_sparse_A": (_i32, [_i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
     "mdsdp_destroy": (_i32, [_vp]),
     "mdsdp_problem_info": (_i32, [_vp, _pi32, _pi64, _pi64, _pi32]),

@@ -136,14 +136,19 @@ namespace mdsdp {
 
 static void free_problem(mdsdp_problem P) {
   if (!P) return;
-  void* ptrs[] = {P->cls,      P->Xt,     P->Xt32,    P->Ct,      P->segs,   P->seg_start, P->cinf,
-                  P->Cavg,     P->sS[0],  P->sS[1],   P->sZ[0],   P->sZ[1],  P->Yp,        P->Up,
+  void* ptrs[] = {P->cls,      P->Xt,     P->Xt32,    P->Ct,      P->segs,   P->seg_start, P->cy,
+                  P->Cavg,     P->yp,     P->invc,    P->bvec,    P->sacc,   P->Yp,        P->Up,
+                  P->bqp4a_items, P->bqp_cd,
                   P->zvec,     P->zmult,  P->rowpart, P->colpart, P->wgpart, P->zpart,     P->gram,
                   P->gpart,    P->scal,   P->bound,   P->dotpart, (void*)P->dotptr, P->lz_V, P->lz_w,
                   P->lz_h,     P->lz_hpart, P->work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  for (auto e : P->timer.ev) (void)hipEventDestroy(e);
+  if (P->hbuf) (void)hipHostFree(P->hbuf);
+  for (auto& r : P->timer.recs) {
+    if (r.ev0) (void)hipEventDestroy(r.ev0);
+    if (r.ev1) (void)hipEventDestroy(r.ev1);
+  }
   delete P;
 }
 
@@ -260,8 +265,16 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   P->normC = sqrt(nC2);
 
   // per-class constants
-  std::vector<double2> hcinf(m);
-  for (long long g = 0; g < m; ++g) hcinf[g] = make_double2(b[g] / (double)cnt[g], 1.0 / (double)cnt[g]);
+  std::vector<double2> hcy(m);
+  std::vector<double> hinvc(m);
+  for (long long g = 0; g < m; ++g) {
+    hcy[g] = make_double2(b[g] / (double)cnt[g], 0.0);
+    hinvc[g] = 1.0 / (double)cnt[g];
+  }
+  long long last_b = 0;
+  for (long long g = 0; g < m; ++g)
+    if (b[g] != 0.0) last_b = g + 1;
+  P->bty_range = last_b;
   std::vector<double> hCavg;
   if (C) {
     hCavg.assign(m, 0.0);
@@ -288,12 +301,12 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   if (C) TRY(dalloc(&P->Ct, P->nslots));
   TRY(dalloc(&P->segs, P->nseg));
   TRY(dalloc(&P->seg_start, P->nb + 1));
-  TRY(dalloc(&P->cinf, m));
+  TRY(dalloc(&P->cy, m));
+  TRY(dalloc(&P->yp, m));
+  TRY(dalloc(&P->invc, m));
+  TRY(dalloc(&P->bvec, m));
+  TRY(dalloc(&P->sacc, m));
   if (C) TRY(dalloc(&P->Cavg, m));
-  for (int i = 0; i < 2; ++i) {
-    TRY(dalloc(&P->sS[i], m));
-    TRY(dalloc(&P->sZ[i], m));
-  }
   TRY(dalloc((double**)&P->Yp, (size_t)P->npad * 16));
   TRY(dalloc((double**)&P->Up, (size_t)P->npad * 16));
   TRY(dalloc(&P->zvec, n));
@@ -303,13 +316,21 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   TRY(dalloc(&P->wgpart, (size_t)P->nseg * 4));
   TRY(dalloc(&P->zpart, (size_t)(n * 16 + 255) / 256 + 1));
   TRY(dalloc(&P->gram, 512));
-  TRY(dalloc(&P->gpart, (size_t)((n + 63) / 64) * 512));
+  TRY(dalloc(&P->gpart, std::max((size_t)((n + 63) / 64) * 512, (size_t)8192)));
   TRY(dalloc(&P->scal, SC_COUNT));
   TRY(dalloc(&P->bound, 2));
   P->dot_nblk = 256;
   TRY(dalloc(&P->dotpart, (size_t)P->dot_nblk * 8));
   TRY(dalloc((double**)&P->dotptr, 16));
-  TRY(dalloc(&P->work, (size_t)n * 16 * 8));
+  TRY(dalloc(&P->work, (size_t)n * 16 * 12));
+  {
+    hipError_t eh = hipHostMalloc((void**)&P->hbuf, 1024 * sizeof(double), hipHostMallocDefault);
+    if (eh != hipSuccess) {
+      mdsdp_status s2 = hip_fail(eh, "hipHostMalloc");
+      free_problem(P);
+      return s2;
+    }
+  }
 
   hipError_t e;
 #define CP(dst, src, bytes)                                      \
@@ -323,13 +344,13 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   if (C) CP(P->Ct, hC.data(), P->nslots * sizeof(double));
   CP(P->segs, hseg.data(), hseg.size() * sizeof(Seg));
   CP(P->seg_start, hstart.data(), hstart.size() * sizeof(int));
-  CP(P->cinf, hcinf.data(), m * sizeof(double2));
+  CP(P->cy, hcy.data(), m * sizeof(double2));
+  CP(P->invc, hinvc.data(), m * sizeof(double));
+  CP(P->bvec, b, m * sizeof(double));
   if (C) CP(P->Cavg, hCavg.data(), m * sizeof(double));
 #undef CP
-  for (int i = 0; i < 2; ++i) {
-    TRY(hipMemset(P->sS[i], 0, m * sizeof(long long)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
-    TRY(hipMemset(P->sZ[i], 0, m * sizeof(long long)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
-  }
+  TRY(hipMemset(P->sacc, 0, m * sizeof(long long)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
+  TRY(hipMemset(P->yp, 0, m * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
   TRY(hipMemset(P->scal, 0, SC_COUNT * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
   TRY(hipMemset(P->zvec, 0, n * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
   TRY(hipMemset(P->zmult, 0, n * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
@@ -361,6 +382,58 @@ extern "C" {
 mdsdp_status mdsdp_create_classmap(int32_t n, int64_t m, const int32_t* cls, const double* b, const double* C,
                                    mdsdp_problem* out) {
   return create_from_packed(n, m, cls, b, C, out);
+}
+
+mdsdp_status mdsdp_create_bqp(int32_t q, int32_t order, const double* Q, const double* c, mdsdp_problem* out) {
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  int32_t n = 0;
+  int64_t m = 0;
+  mdsdp_status st = mdsdp_bqp_sizes(q, &n, &m);
+  if (st != MDSDP_OK) return st;
+  if (order != MDSDP_ORDER_LEX && order != MDSDP_ORDER_COLEX) return einval("bad basis order");
+  if (!Q || !c) return einval("Q and c are required");
+  std::vector<int32_t> cls((size_t)n * (n + 1) / 2);
+  std::vector<double> b(m);
+  if ((st = mdsdp_bqp_classmap(q, order, cls.data())) != MDSDP_OK) return st;
+  if ((st = mdsdp_bqp_b(q, Q, c, b.data())) != MDSDP_OK) return st;
+  mdsdp_problem P = nullptr;
+  if ((st = create_from_packed(n, m, cls.data(), b.data(), nullptr, &P)) != MDSDP_OK) return st;
+  // the structured kernels stage at most 111 pair rows per set in LDS
+  if (order == MDSDP_ORDER_COLEX && q >= 1 && q <= 112) {
+    // structured class-sum kernels: work lists
+    P->bqp_q = q;
+    bqp_offsets(q, P->bqp_off);
+    std::vector<int4> items;
+    for (int cc = 2; cc <= q - 2; ++cc) {
+      const long long npi = binom(cc, 2);
+      for (int d0 = cc + 1; d0 < q; d0 += 16)
+        for (long long p0 = 0; p0 < npi; p0 += 64) items.push_back(make_int4(cc, d0, (int)p0, 0));
+    }
+    std::vector<int2> cd;
+    for (int cc = 2; cc <= q - 2; ++cc)
+      for (int dd = cc + 1; dd < q; ++dd) cd.push_back(make_int2(cc, dd));
+    // largest work first for the degree-4 symmetric pass
+    std::stable_sort(cd.begin(), cd.end(), [](const int2& x, const int2& y) { return x.x > y.x; });
+    P->bqp4a_n = (int)items.size();
+    P->bqp_ncd = (int)cd.size();
+    hipError_t e = hipSuccess;
+    if (!items.empty()) {
+      e = hipMalloc((void**)&P->bqp4a_items, items.size() * sizeof(int4));
+      if (e == hipSuccess) e = hipMemcpy(P->bqp4a_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && !cd.empty()) {
+      e = hipMalloc((void**)&P->bqp_cd, cd.size() * sizeof(int2));
+      if (e == hipSuccess) e = hipMemcpy(P->bqp_cd, cd.data(), cd.size() * sizeof(int2), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+      st = hip_fail(e, "bqp tables");
+      free_problem(P);
+      return st;
+    }
+  }
+  *out = P;
+  return MDSDP_OK;
 }
 
 mdsdp_status mdsdp_create_sparse_A(int32_t n, int64_t m, int64_t nnz, const int32_t* cls, const int32_t* row,
@@ -438,6 +511,7 @@ mdsdp_status mdsdp_cost_grad(mdsdp_problem P, int32_t p, const double* Y, double
   hipStream_t s = (hipStream_t)stream;
   if ((st = launch_stage(P, p, Y, nullptr, false, s)) != MDSDP_OK) return st;
   if ((st = launch_classsum_S(P, s)) != MDSDP_OK) return st;
+  if ((st = launch_bty(P, s)) != MDSDP_OK) return st;
   if ((st = launch_resid(P, M_GRAD, false, s)) != MDSDP_OK) return st;
   return launch_rowfinal_grad(P, p, Y, egrad, rgrad, f, s);
 }
@@ -489,6 +563,7 @@ mdsdp_status mdsdp_update_multiplier(mdsdp_problem P, int32_t p, const double* Y
   hipStream_t s = (hipStream_t)stream;
   if ((st = launch_stage(P, p, Y, nullptr, false, s)) != MDSDP_OK) return st;
   if ((st = launch_classsum_S(P, s)) != MDSDP_OK) return st;
+  if ((st = launch_bty(P, s)) != MDSDP_OK) return st;
   if (y && (st = launch_y_export(P, y, s)) != MDSDP_OK) return st;
   if ((st = launch_resid(P, M_MULT, false, s)) != MDSDP_OK) return st;
   return launch_rowfinal_mult(P, p, Y, z, kkt, s);
@@ -552,9 +627,12 @@ mdsdp_status mdsdp_export_multiplier_packed(mdsdp_problem P, double* out) {
 mdsdp_status mdsdp_enable_timing(mdsdp_problem P, int32_t on) {
   if (!P) return einval("problem is NULL");
   P->timer.on = on != 0;
-  for (auto e : P->timer.ev) (void)hipEventDestroy(e);
-  P->timer.ev.clear();
-  P->timer.names.clear();
+  for (auto& r : P->timer.recs) {
+    if (r.ev0) (void)hipEventDestroy(r.ev0);
+    if (r.ev1) (void)hipEventDestroy(r.ev1);
+  }
+  P->timer.recs.clear();
+  P->timer.open.clear();
   return MDSDP_OK;
 }
 
@@ -567,16 +645,20 @@ mdsdp_status mdsdp_kernel_times(mdsdp_problem P, double* ms_out, int32_t cap, in
   std::string names;
   int k = 0;
   auto& T = P->timer;
-  for (size_t i = 0; i + 1 < T.ev.size(); i += 2) {
+  for (auto& r : T.recs) {
+    if (!r.ev0 || !r.ev1) continue;
     float ms = 0.f;
-    MDSDP_HIP(hipEventElapsedTime(&ms, T.ev[i], T.ev[i + 1]));
+    MDSDP_HIP(hipEventElapsedTime(&ms, r.ev0, r.ev1));
     if (k < cap && ms_out) ms_out[k] = ms;
-    names += T.names[i] + ";";
+    names += r.name + ";";
     ++k;
   }
-  for (auto e : T.ev) (void)hipEventDestroy(e);
-  T.ev.clear();
-  T.names.clear();
+  for (auto& r : T.recs) {
+    if (r.ev0) (void)hipEventDestroy(r.ev0);
+    if (r.ev1) (void)hipEventDestroy(r.ev1);
+  }
+  T.recs.clear();
+  T.open.clear();
   *count = k;
   g_err = names;
   return MDSDP_OK;

@@ -8,8 +8,10 @@
 //      (Proposition prop).  16 x 16 blocks of Z come from MFMA 16x16x4 on
 //      LDS-staged 64-row slices of Y and U; every entry is added to its class
 //      with a 64-bit fixed-point atomic (integer addition is associative, so
-//      the sums are bit-reproducible whatever the scheduling).  Sums are
-//      double-buffered; the class's "owner" slot clears the other buffer.
+//      the sums are bit-reproducible whatever the scheduling); k_final_*
+//      turns them into class averages and clears the accumulator.  This is
+//      the path for any class map; BQP relaxations in colex order use the
+//      structured kernels k_bqp* instead (no class-map reads, no atomics).
 //
 //  k_resid<T, MODE>  per-entry coefficient and symmetric product pass:
 //      GRAD: r = Z - y, G = Xt + D + sigma r (Lemma lm:suboptimality), cost
@@ -32,6 +34,9 @@
 // column block, hence overlapping class ids and Y rows) land on one XCD.
 
 #include <math.h>
+
+#include <algorithm>
+#include <type_traits>
 
 #include "mdsdp_internal.hpp"
 
@@ -58,6 +63,15 @@ __device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Result layout of the 16x16x4 MFMA: lane l = 16 * lk + li holds column li;
+// its element v is row lk + 4 v for the FP64 instruction and row 4 lk + v for
+// the FP32 one (measured on gfx950).  The operand layouts are the same for
+// both: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k.
+template <typename T>
+__device__ __forceinline__ int drow(int lk, int v) {
+  return sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v;
+}
+
 struct KArgs {
   const uint32_t* cls;
   double* Xt;
@@ -68,14 +82,10 @@ struct KArgs {
   int nk;  // number of 4-wide K chunks covering p
   const void* Yp;
   const void* Up;
-  const double2* cinf;  // {D, 1/|gamma|}
+  const double2* cy;    // {D, y}
+  const double* yp;     // class averages of Y U^T + U Y^T
   const double* Cavg;   // A(C)/|gamma| or null
-  long long* sS_acc;    // S-sum buffer being accumulated
-  long long* sS_clr;    // S-sum buffer to clear
-  const long long* sS;  // S-sums to read (residual passes)
-  long long* sZ_acc;
-  long long* sZ_clr;
-  const long long* sZ;
+  long long* sacc;      // generic fixed-point accumulator
   const unsigned long long* bound;  // [ymax, umax] bit patterns
   double* scal;
   double kmax;
@@ -121,6 +131,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_stage(int n, int p, int npad, const double* __restrict__ Y,
                                                const double* __restrict__ U, T* __restrict__ Yp,
                                                T* __restrict__ Up, unsigned long long* bound) {
+  __shared__ double smax[2][16];
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   int r = idx >> 4, c = idx & 15;
   bool in = idx < npad * 16;
@@ -136,9 +147,20 @@ __global__ __launch_bounds__(256) void k_stage(int n, int p, int npad, const dou
     ny += __shfl_xor(ny, off, 16);
     nu += __shfl_xor(nu, off, 16);
   }
-  if (in && c == 0 && r < n) {
-    atomicMax(&bound[0], (unsigned long long)__double_as_longlong(sqrt(ny)));
-    if (U) atomicMax(&bound[1], (unsigned long long)__double_as_longlong(sqrt(nu)));
+  if (!bound) return;  // row-norm bound only needed by the fixed-point class sums
+  if (c == 0) {
+    smax[0][threadIdx.x >> 4] = (in && r < n) ? sqrt(ny) : 0.0;
+    smax[1][threadIdx.x >> 4] = (in && r < n) ? sqrt(nu) : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m0 = 0.0, m1 = 0.0;
+    for (int i = 0; i < 16; ++i) {
+      m0 = fmax(m0, smax[0][i]);
+      m1 = fmax(m1, smax[1][i]);
+    }
+    atomicMax(&bound[0], (unsigned long long)__double_as_longlong(m0));
+    if (U) atomicMax(&bound[1], (unsigned long long)__double_as_longlong(m1));
   }
 }
 
@@ -161,9 +183,8 @@ __global__ __launch_bounds__(256) void k_classsum(KArgs a) {
   const double ymax = bound_val(a.bound, 0);
   const double scale = ZMODE ? fx_scale(a.kmax, 2.0 * ymax * bound_val(a.bound, 1))
                              : fx_scale(a.kmax, ymax * ymax);
-  if (sidx == 0 && tid == 0) a.scal[ZMODE ? 8 : 7] = scale;
-  long long* acc_t = ZMODE ? a.sZ_acc : a.sS_acc;
-  long long* clr_t = ZMODE ? a.sZ_clr : a.sS_clr;
+  if (sidx == 0 && tid == 0) a.scal[ZMODE ? SC_SCALE_Z : SC_SCALE_S] = scale;
+  long long* acc_t = a.sacc;
   const int li = lane & 15, lk = lane >> 4;
   for (int I = sg.I0; I <= sg.I1; ++I) {
     __syncthreads();
@@ -187,15 +208,14 @@ __global__ __launch_bounds__(256) void k_classsum(KArgs a) {
           acc = mfma(ya, yb, acc);
         }
       }
-      const uint32_t* cb = a.cls + t * TSLOTS + (w * 4 + sc) * 256 + lk * 64 + li;
+      const uint32_t* cb = a.cls + t * TSLOTS + (w * 4 + sc) * 256 + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        uint32_t cw = cb[v * 16];
+        uint32_t cw = cb[drow<T>(lk, v) * 16];
         if (!(cw & 0x80000000u)) {
           uint32_t id = cw & CLS_MASK;
           long long qv = llrint(wgt * (double)acc[v] * scale);
           atomicAdd((unsigned long long*)&acc_t[id], (unsigned long long)qv);
-          if (cw & OWNER_BIT) clr_t[id] = 0;
         }
       }
     }
@@ -232,20 +252,10 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
   if (SEPARATE_U) load_rows(sUc, Up, sg.J * 64, tid);
 
   const double sigma = a.sigma;
-  double inv_sS = 1.0, inv_sZ = 1.0;
-  if (MODE == M_GRAD || MODE == M_MULT || MODE == M_HVP) {
-    const double ymax = bound_val(a.bound, 0);
-    inv_sS = 1.0 / fx_scale(a.kmax, ymax * ymax);
-    if (MODE == M_HVP) inv_sZ = 1.0 / fx_scale(a.kmax, 2.0 * ymax * bound_val(a.bound, 1));
-  }
-  if (MODE == M_HVP) {
-    // the S-sums were taken at the cost/grad point with the same Y
-    inv_sS = 1.0 / a.scal[7];
-  }
   v4 accC[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) accC[i] = v4{0, 0, 0, 0};
-  double p_r2 = 0.0, p_xz = 0.0, p_bty = 0.0, p_cx = 0.0;
+  double p_r2 = 0.0, p_xz = 0.0, p_cx = 0.0;
   T* tAw = tA[w];
   T* tBw = HAS_B ? tB[w] : tA[w];
 
@@ -258,61 +268,87 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
     const bool diag = (I == sg.J);
     const double wgt = diag ? 1.0 : 2.0;
     v4 accR = {0, 0, 0, 0};
+    // ---- batched memory phase for this wave's 16 x 64 slab of the tile ----
+    typedef typename std::conditional<sizeof(T) == 8 || MODE != M_HVP, double, float>::type XT;
+    const size_t tb = (size_t)t * TSLOTS + (size_t)(w * 4) * 256 + li;
+    uint32_t cwv[4][4];
+    XT xv[4][4];
+#pragma unroll
+    for (int sc = 0; sc < 4; ++sc)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const size_t off = tb + sc * 256 + drow<T>(lk, v) * 16;
+        cwv[sc][v] = a.cls[off];
+        if (sizeof(XT) == 8)
+          xv[sc][v] = (XT)a.Xt[off];
+        else
+          xv[sc][v] = (XT)a.Xt32[off];
+      }
+    double2 dyv[4][4];
+    double yzv[4][4];
+#pragma unroll
+    for (int sc = 0; sc < 4; ++sc)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t cw = cwv[sc][v];
+        const bool valid = !(cw & 0x80000000u);
+        const uint32_t id = valid ? (cw & CLS_MASK) : 0u;
+        dyv[sc][v] = a.cy[id];
+        if (MODE == M_HVP) yzv[sc][v] = a.yp[id];
+      }
+    // S blocks of the four sub-blocks (MFMA from LDS)
+    v4 Sbv[4];
+#pragma unroll
     for (int sc = 0; sc < 4; ++sc) {
-      v4 Sb = {0, 0, 0, 0};
+      Sbv[sc] = v4{0, 0, 0, 0};
       if (HAS_S) {
         for (int j = 0; j < a.nk; ++j) {
           const int k = 4 * j + lk;
-          Sb = mfma(rY[(w * 16 + li) * LP + k], cY[(sc * 16 + li) * LP + k], Sb);
+          Sbv[sc] = mfma(rY[(w * 16 + li) * LP + k], cY[(sc * 16 + li) * LP + k], Sbv[sc]);
         }
       }
-      const size_t base = (size_t)t * TSLOTS + (w * 4 + sc) * 256 + lk * 64 + li;
-      // D layout: element v <-> (row 4*lk + v, col li) of the sub-block
+    }
+#pragma unroll
+    for (int sc = 0; sc < 4; ++sc) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const size_t off = base + v * 16;
-        const uint32_t cw = a.cls[off];
+        const int rv = drow<T>(lk, v);
+        const size_t off = tb + sc * 256 + rv * 16;
+        const uint32_t cw = cwv[sc][v];
         const bool valid = !(cw & 0x80000000u);
-        const uint32_t id = valid ? (cw & CLS_MASK) : 0u;
         T av = 0, bv = 0;
         if (valid) {
-          const double2 ci = a.cinf[id];
+          const double2 dy = dyv[sc][v];  // {D, y}
           const double Ce = a.Ct ? a.Ct[off] : 0.0;
           if (MODE == M_GRAD || MODE == M_MULT) {
-            double y = (double)a.sS[id] * inv_sS * ci.y;
-            if (a.Cavg) y += a.Cavg[id];
-            const double Zv = (double)Sb[v] + Ce;
-            const double r = Zv - y;
-            const double x = a.Xt[off];
+            const double Zv = (double)Sbv[sc][v] + Ce;
+            const double r = Zv - dy.y;
+            const double x = (double)xv[sc][v];
             p_r2 += wgt * r * r;
             if (MODE == M_GRAD) {
               p_xz += wgt * x * Zv;
-              av = (T)(x + ci.x + sigma * r);
+              av = (T)(x + dy.x + sigma * r);
             } else {
               const double xn = x + sigma * r;
               a.Xt[off] = xn;
               a.Xt32[off] = (float)xn;
-              p_cx += wgt * Ce * (xn + ci.x);
-              av = (T)(xn + ci.x);
+              p_cx += wgt * Ce * (xn + dy.x);
+              av = (T)(xn + dy.x);
             }
-            if (cw & OWNER_BIT) p_bty += ci.x / ci.y * y;
           } else if (MODE == M_XMV) {
-            av = (T)(a.Xt[off] + ci.x);
+            av = (T)((double)xv[sc][v] + dy.x);
           } else {  // HVP
-            double y = (double)a.sS[id] * inv_sS * ci.y;
-            if (a.Cavg) y += a.Cavg[id];
-            const double yz = (double)a.sZ[id] * inv_sZ * ci.y;
-            bv = (T)(-sigma * yz);
+            bv = (T)(-sigma * yzv[sc][v]);
             if (sizeof(T) == 8) {
-              av = (T)(a.Xt[off] + (ci.x - sigma * y) + sigma * Ce);
+              av = (T)((double)xv[sc][v] + (dy.x - sigma * dy.y) + sigma * Ce);
             } else {
-              const float rS = (float)Sb[v] + (float)(Ce - y);
-              av = (T)(a.Xt32[off] + (float)ci.x + (float)sigma * rS);
+              const float rS = (float)Sbv[sc][v] + (float)(Ce - dy.y);
+              av = (T)((float)xv[sc][v] + (float)dy.x + (float)sigma * rS);
             }
           }
         }
-        tAw[(4 * lk + v) * LP + li] = av;
-        if (HAS_B) tBw[(4 * lk + v) * LP + li] = bv;
+        tAw[rv * LP + li] = av;
+        if (HAS_B) tBw[rv * LP + li] = bv;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -339,27 +375,27 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // row-side partial of this tile: rows w*16 + 4*lk + v, pcol li
-    T* rp = (T*)a.rowpart + ((size_t)t * 64 + w * 16 + 4 * lk) * 16 + li;
+    // row-side partial of this tile: rows w*16 + drow(lk, v), pcol li
+    T* rp = (T*)a.rowpart + ((size_t)t * 64 + w * 16) * 16 + li;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) rp[v * 16] = accR[v];
+    for (int v = 0; v < 4; ++v) rp[drow<T>(lk, v) * 16] = accR[v];
   }
   // column-side partial of the segment: sum the four waves (rows sub-blocks)
   __syncthreads();
   T* cred = &tA[0][0];  // reuse: need 4 waves x 4 sc x 256 values -> do sc by sc
   T* cp = (T*)a.colpart + (size_t)sidx * 64 * 16;
   for (int sc = 0; sc < 4; ++sc) {
-    // accC[sc]: lane (lk, li), v -> pcol 4*lk + v, col li
+    // accC[sc]: lane (lk, li), v -> pcol drow(lk, v), col li
     __syncthreads();
     if (w > 0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) cred[(w - 1) * 256 + (4 * lk + v) * 16 + li] = accC[sc][v];
+      for (int v = 0; v < 4; ++v) cred[(w - 1) * 256 + drow<T>(lk, v) * 16 + li] = accC[sc][v];
     }
     __syncthreads();
     if (w == 0) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int pc = 4 * lk + v;
+        const int pc = drow<T>(lk, v);
         T s = accC[sc][v];
         s += cred[0 * 256 + pc * 16 + li];
         s += cred[1 * 256 + pc * 16 + li];
@@ -369,7 +405,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
     }
   }
   if (MODE == M_GRAD || MODE == M_MULT) {
-    double vals[NWP] = {p_r2, p_xz, p_bty, p_cx};
+    double vals[NWP] = {p_r2, p_xz, 0.0, p_cx};
     for (int q = 0; q < NWP; ++q) {
       __syncthreads();
       red[tid] = vals[q];
@@ -399,8 +435,9 @@ __device__ __forceinline__ double row_sum(const RowArgs& ra, int r, int k) {
   const T* rp = (const T*)ra.rowpart;
   const T* cp = (const T*)ra.colpart;
   double s = 0.0;
+#pragma unroll 8
   for (int J = I; J < ra.nb; ++J) {
-    const long long t = (long long)J * (J + 1) / 2 + I;
+    const long long t = ((long long)J * (J + 1) >> 1) + I;
     s += (double)rp[((size_t)t * 64 + rr) * 16 + k];
   }
   for (int q = ra.seg_start[I]; q < ra.seg_start[I + 1]; ++q) s += (double)cp[((size_t)q * 64 + rr) * 16 + k];
@@ -500,7 +537,8 @@ __global__ __launch_bounds__(256) void k_row_xmv(RowArgs ra, const double* __res
 
 // scalar reduction (single block, fixed order)
 __global__ __launch_bounds__(256) void k_scalars(int mode, const double* __restrict__ wgpart, int nseg,
-                                                 const double* __restrict__ zpart, int nz, double sigma,
+                                                 const double* __restrict__ zpart, int nz,
+                                                 const double* __restrict__ btypart, int nbty, double sigma,
                                                  double* scal, double* f_out, double* kkt_out) {
   __shared__ double red[256];
   double acc[NWP + 1];
@@ -524,8 +562,16 @@ __global__ __launch_bounds__(256) void k_scalars(int mode, const double* __restr
     }
     tot[q] = red[0];
   }
+  __syncthreads();
+  red[threadIdx.x] = threadIdx.x < nbty ? btypart[threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    const double r2 = tot[0], xz = tot[1], bty = tot[2], cx = tot[3];
+    const double bty = red[0];
+    const double r2 = tot[0], xz = tot[1], cx = tot[3];
     scal[SC_R2] = r2;
     scal[SC_XZ] = xz;
     scal[SC_BTY] = bty;
@@ -548,26 +594,39 @@ __global__ __launch_bounds__(256) void k_scalars(int mode, const double* __restr
   }
 }
 
-// Gram matrices Y^T Y and Y^T U (16 x 16, FP64), two-stage fixed order.
+// Gram matrices Y^T Y and Y^T U (16 x 16, FP64) with MFMA over 4-row chunks;
+// block partials, then a fixed-order final sum.
 __global__ __launch_bounds__(256) void k_gram_part(int n, int p, const double* __restrict__ Y,
                                                    const double* __restrict__ U, double* __restrict__ part) {
-  const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
-  const int r0 = blockIdx.x * 64;
-  double syy = 0.0, syu = 0.0;
-  if (i < p && j < p) {
-    for (int r = r0; r < min(n, r0 + 64); ++r) {
-      const double yi = Y[(size_t)r * p + i];
-      syy += yi * Y[(size_t)r * p + j];
-      syu += yi * U[(size_t)r * p + j];
-    }
+  __shared__ double red[4][512];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int per = (n + gridDim.x - 1) / gridDim.x;
+  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+  v4d ayy = {0, 0, 0, 0}, ayu = {0, 0, 0, 0};
+  for (int rb = r0 + 4 * w; rb < r1; rb += 16) {
+    const int r = rb + lk;
+    const bool ok = r < r1 && li < p;
+    const double y = ok ? Y[(size_t)r * p + li] : 0.0;
+    const double u = ok ? U[(size_t)r * p + li] : 0.0;
+    // A[i][k] = Y[r_k][i] (lane i + 16 k), B[k][j] = Y[r_k][j] / U[r_k][j]
+    ayy = mfma(y, y, ayy);
+    ayu = mfma(y, u, ayu);
   }
-  part[(size_t)blockIdx.x * 512 + threadIdx.x] = syy;
-  part[(size_t)blockIdx.x * 512 + 256 + threadIdx.x] = syu;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = drow<double>(lk, v);
+    red[w][i * 16 + li] = ayy[v];
+    red[w][256 + i * 16 + li] = ayu[v];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 512; e += 256)
+    part[(size_t)blockIdx.x * 512 + e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
 }
 
 __global__ __launch_bounds__(512) void k_gram_final(int nblk, const double* __restrict__ part,
                                                     double* __restrict__ gram) {
   double s = 0.0;
+#pragma unroll 8
   for (int b = 0; b < nblk; ++b) s += part[(size_t)b * 512 + threadIdx.x];
   gram[threadIdx.x] = s;
 }
@@ -598,15 +657,10 @@ __global__ __launch_bounds__(256) void k_project(int n, int p, const double* __r
   for (int k = 0; k < p; ++k) out[(size_t)r * p + k] = U[(size_t)r * p + k] - d * Y[(size_t)r * p + k];
 }
 
-// y export: y_gamma = S-sum / scale / |gamma| (+ A(C)/|gamma|)
-__global__ __launch_bounds__(256) void k_y_export(long long m, const long long* __restrict__ sS,
-                                                  const double2* __restrict__ cinf, const double* __restrict__ Cavg,
-                                                  const double* __restrict__ scal, double* __restrict__ y) {
+// y export: the class averages of the last S-pass
+__global__ __launch_bounds__(256) void k_y_export(long long m, const double2* __restrict__ cy, double* __restrict__ y) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= m) return;
-  double v = (double)sS[g] / scal[7] * cinf[g].y;
-  if (Cavg) v += Cavg[g];
-  y[g] = v;
+  if (g < m) y[g] = cy[g].y;
 }
 
 // dense <-> tile layout for Xt
@@ -631,7 +685,7 @@ __global__ __launch_bounds__(256) void k_set_dense(int n, int nb, long long nslo
 }
 
 __global__ __launch_bounds__(256) void k_get_dense(int n, int nb, long long nslots, const double* __restrict__ Xt,
-                                                   const uint32_t* __restrict__ cls, const double2* __restrict__ cinf,
+                                                   const uint32_t* __restrict__ cls, const double2* __restrict__ cy,
                                                    int add_D, double* __restrict__ X) {
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nslots) return;
@@ -646,19 +700,18 @@ __global__ __launch_bounds__(256) void k_get_dense(int n, int nb, long long nslo
   const int c = J * 64 + (sb & 3) * 16 + (e & 15);
   if (r >= n || c >= n) return;
   double v = Xt[s];
-  if (add_D) v += cinf[cls[s] & CLS_MASK].x;
+  if (add_D) v += cy[cls[s] & CLS_MASK].x;
   X[(size_t)r * n + c] = v;
   X[(size_t)c * n + r] = v;
 }
 
 // vector helpers for the solver (deterministic two-stage dot products)
-__global__ __launch_bounds__(256) void k_dots(const double* const* __restrict__ a, const double* const* __restrict__ b,
-                                              int npairs, long long len, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_dots(DotPtrs dp, int npairs, long long len, double* __restrict__ part) {
   __shared__ double red[256];
   for (int q = 0; q < npairs; ++q) {
     double s = 0.0;
-    const double* x = a[q];
-    const double* y = b[q];
+    const double* x = dp.a[q];
+    const double* y = dp.b[q];
     for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < len; i += (long long)gridDim.x * 256)
       s += x[i] * y[i];
     red[threadIdx.x] = s;
@@ -674,11 +727,51 @@ __global__ __launch_bounds__(256) void k_dots(const double* const* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_dots_final(int npairs, int nblk, const double* __restrict__ part,
                                                     double* __restrict__ out) {
-  const int q = threadIdx.x;
-  if (q >= npairs) return;
+  __shared__ double red[256];
+  const int q = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) acc += part[(size_t)q * nblk + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = red[0];
+}
+
+// rr_new = ||r||^2 and beta = rr_new / rr_old (tCG); out[0] = rr_new, out[1] = beta
+__global__ __launch_bounds__(256) void k_rr_beta(int nblk, const double* __restrict__ part, double rr_old,
+                                                 double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    out[1] = red[0] / rr_old;
+  }
+}
+
+// h_j = <V_j, w> for j < k: one block per basis vector (fixed order)
+__global__ __launch_bounds__(256) void k_vt_w(int n, const double* __restrict__ V, const double* __restrict__ w,
+                                              double* __restrict__ h) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)q * nblk + b];
-  out[q] = s;
+  for (int i = threadIdx.x; i < n; i += 256) s += V[(size_t)j * n + i] * w[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) h[j] = red[0];
 }
 
 __global__ __launch_bounds__(256) void k_lincomb(long long len, double alpha, const double* __restrict__ x,
@@ -693,6 +786,428 @@ __global__ __launch_bounds__(256) void k_lincomb(long long len, double alpha, co
 __global__ __launch_bounds__(256) void k_fill(long long len, double v, double* out) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i < len) out[i] = v;
+}
+
+// truncated-CG update (Steihaug-Toint step), one thread per row.
+// part 1: eta += alpha d; Heta += alpha Hd; r = P_Y(r + alpha Hd); partial ||r||^2
+__global__ __launch_bounds__(256) void k_tcg_update1(int n, int p, const double* __restrict__ Y, double alpha,
+                                                     double* __restrict__ eta, double* __restrict__ Heta,
+                                                     double* __restrict__ r, const double* __restrict__ d,
+                                                     const double* __restrict__ Hd, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double rr = 0.0;
+  if (i < n) {
+    const size_t o = (size_t)i * p;
+    double rn[16];
+    double dr = 0.0;
+    for (int k = 0; k < p; ++k) {
+      eta[o + k] += alpha * d[o + k];
+      Heta[o + k] += alpha * Hd[o + k];
+      rn[k] = r[o + k] + alpha * Hd[o + k];
+      dr += rn[k] * Y[o + k];
+    }
+    for (int k = 0; k < p; ++k) {
+      rn[k] -= dr * Y[o + k];
+      r[o + k] = rn[k];
+      rr += rn[k] * rn[k];
+    }
+  }
+  red[threadIdx.x] = rr;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// part 2: d = P_Y(-r + beta d) with beta read from device memory
+__global__ __launch_bounds__(256) void k_tcg_update2(int n, int p, const double* __restrict__ Y,
+                                                     const double* __restrict__ beta_dev, const double* __restrict__ r,
+                                                     double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double beta = *beta_dev;
+  const size_t o = (size_t)i * p;
+  double dn[16];
+  double dd = 0.0;
+  for (int k = 0; k < p; ++k) {
+    dn[k] = -r[o + k] + beta * d[o + k];
+    dd += dn[k] * Y[o + k];
+  }
+  for (int k = 0; k < p; ++k) d[o + k] = dn[k] - dd * Y[o + k];
+}
+
+// Yout (n x q) = Yin (n x p) M (p x q, row-major); optional row normalisation
+__global__ __launch_bounds__(256) void k_rightmul(int n, int p, int q, const double* __restrict__ Yin,
+                                                  const double* __restrict__ M, int normalize,
+                                                  double* __restrict__ Yout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double out[16];
+  double nrm = 0.0;
+  for (int c = 0; c < q; ++c) {
+    double s = 0.0;
+    for (int k = 0; k < p; ++k) s += Yin[(size_t)i * p + k] * M[k * q + c];
+    out[c] = s;
+    nrm += s * s;
+  }
+  const double inv = (normalize && nrm > 0.0) ? 1.0 / sqrt(nrm) : 1.0;
+  for (int c = 0; c < q; ++c) Yout[(size_t)i * q + c] = out[c] * inv;
+}
+
+// U (n x p) = 0 except column col = v
+__global__ __launch_bounds__(256) void k_set_col(int n, int p, int col, const double* __restrict__ v,
+                                                 double* __restrict__ U) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < p; ++k) U[(size_t)i * p + k] = (k == col) ? v[i] : 0.0;
+}
+
+// w -= V h  (V: k column vectors of length n stored one after another)
+__global__ __launch_bounds__(256) void k_gemv_sub(int n, int k, const double* __restrict__ V,
+                                                  const double* __restrict__ h, double* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) s += V[(size_t)j * n + i] * h[j];
+  w[i] -= s;
+}
+
+// out = V s (Ritz vector)
+__global__ __launch_bounds__(256) void k_gemv(int n, int k, const double* __restrict__ V,
+                                              const double* __restrict__ sv, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) s += V[(size_t)j * n + i] * sv[j];
+  out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// generic class-sum finalisation: fixed-point sums -> class averages
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_final_S(long long m, long long* __restrict__ sacc,
+                                                 const double* __restrict__ invc, const double* __restrict__ Cavg,
+                                                 const double* __restrict__ scal, double2* __restrict__ cy) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m) return;
+  double y = (double)sacc[g] / scal[SC_SCALE_S] * invc[g];
+  if (Cavg) y += Cavg[g];
+  sacc[g] = 0;
+  cy[g].y = y;
+}
+
+__global__ __launch_bounds__(256) void k_final_Z(long long m, long long* __restrict__ sacc,
+                                                 const double* __restrict__ invc, const double* __restrict__ scal,
+                                                 double* __restrict__ yp) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m) return;
+  yp[g] = (double)sacc[g] / scal[SC_SCALE_Z] * invc[g];
+  sacc[g] = 0;
+}
+
+// b^T y over the classes that may carry b != 0 (deterministic two-stage)
+__global__ __launch_bounds__(256) void k_bty_part(long long range, const double* __restrict__ b,
+                                                  const double2* __restrict__ cy, double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (long long g = (long long)blockIdx.x * 256 + threadIdx.x; g < range; g += (long long)gridDim.x * 256)
+    acc += b[g] * cy[g].y;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// Structured class averages of the order-2 BQP moment relaxation
+// (paragraph on BQPs: basis v(x), classes by symmetric difference), colex
+// basis and colex class ids.  For the symmetric bilinear form
+//   B(alpha, beta) = Y_alpha . Y_beta                      (S-pass, Z = Y Y^T)
+//   B(alpha, beta) = Y_alpha . U_beta + U_alpha . Y_beta   (HVP, Z = Y U^T + U Y^T)
+// the ordered class sum of class gamma is twice the sum of B over the
+// unordered entry pairs of the class (plus the diagonal for gamma = {}):
+//   {a<b<c<d}: (ab|cd) + (ac|bd) + (ad|bc)        |gamma| = 6
+//   {a<b<c}  : (a|bc) + (b|ac) + (c|ab)           |gamma| = 6
+//   {i<j}    : ({}|ij) + (i|j) + sum_l (il|jl)     |gamma| = 2q
+//   {i}      : ({}|i) + sum_j (j|ij)              |gamma| = 2q
+//   {}       : sum_alpha B(alpha, alpha) / 2 ...  |gamma| = n
+// For fixed (c, d) the classes {a<b<c<d} occupy the contiguous id range
+// base4(c, d) + pi(a, b), pi(a, b) = a + C(b, 2) being the colex index of the
+// pair {a, b}.  k_bqp4a writes the (ab|cd) term (a tall GEMM of the pair rows
+// below c against the pairs {c, d}); k_bqp4b adds (ac|bd) + (ad|bc), which for
+// fixed (c, d) is the symmetric part of a c x c product of the pair rows
+// {x, c} and {x, d}, and scales by 1/3.  No class map is read, no atomics.
+// ---------------------------------------------------------------------------
+// binomials without 64-bit integer division (emulated on the GPU): x <= 362
+__device__ __forceinline__ long long c2(long long x) { return (x * (x - 1)) >> 1; }
+__device__ __forceinline__ long long c3(long long x) {
+  const int xi = (int)x;
+  return xi < 3 ? 0 : (long long)((unsigned)(xi * (xi - 1) * (xi - 2)) / 6u);
+}
+__device__ __forceinline__ long long c4(long long x) {
+  const long long t = c3(x);  // C(x,4) = C(x,3) (x - 3) / 4, exact
+  return x < 4 ? 0 : (t * (x - 3)) >> 2;
+}
+// largest c with C(c, 3) <= t, and largest b with C(b, 2) <= t
+__device__ __forceinline__ int inv_c3(long long t) {
+  int c = (int)cbrt(6.0 * (double)t) + 1;
+  while (c3(c) > t) --c;
+  while (c3(c + 1) <= t) ++c;
+  return c;
+}
+__device__ __forceinline__ int inv_c2(long long t) {
+  int b = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+  while (c2(b) > t) --b;
+  while (c2(b + 1) <= t) ++b;
+  return b;
+}
+
+struct BqpArgs {
+  int q;
+  long long off2, off3, off4;
+  const void* Yp;
+  const void* Up;
+  const int4* items;   // k_bqp4a work items
+  const int2* cd;      // (c, d) pairs
+  int ncd;
+  double* dst;         // output element g at dst[g * stride]
+  int stride;          // 2 for the .y field of cy, 1 for yp
+  double* part;        // partials (degree 0)
+};
+
+// row of the colex basis: {} -> 0, {i} -> 1 + i, {i<j} -> 1 + q + C(j,2) + i
+__device__ __forceinline__ int prow(int q, int i, int j) { return 1 + q + (int)c2(j) + i; }
+
+template <typename T, bool ZMODE>
+__global__ __launch_bounds__(256) void k_bqp4a(BqpArgs a) {
+  typedef typename V4<T>::type v4;
+  const int4 it = a.items[blockIdx.x];
+  const int c = it.x, d0 = it.y, pi0 = it.z;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int q = a.q;
+  const T* Y = (const T*)a.Yp;
+  const T* U = (const T*)a.Up;
+  const long long npi = c2(c);
+  const int pib = pi0 + 16 * w;  // this wave's 16 pairs
+  if (pib >= npi) return;
+  // A operand: rows d (pairs {c, d}); B operand: columns pi (pairs below c)
+  const int dA = d0 + li;
+  const bool dok = dA < q;
+  const int rowA = dok ? prow(q, c, dA) : 0;
+  const long long piB = pib + li;
+  const int rowB = (piB < npi) ? (1 + q + (int)piB) : 0;
+  v4 acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = 4 * j + lk;
+    const T ya = dok ? Y[(size_t)rowA * 16 + k] : (T)0;
+    const T yb = Y[(size_t)rowB * 16 + k];
+    if (ZMODE) {
+      const T ua = dok ? U[(size_t)rowA * 16 + k] : (T)0;
+      const T ub = U[(size_t)rowB * 16 + k];
+      acc = mfma(ua, yb, acc);
+      acc = mfma(ya, ub, acc);
+    } else {
+      acc = mfma(ya, yb, acc);
+    }
+  }
+  // element v: row d = d0 + drow(lk, v), column pi = pib + li
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int d = d0 + drow<T>(lk, v);
+    const long long pi = pib + li;
+    if (d < q && pi < npi) {
+      const long long g = a.off4 + c3(c) + c4(d) + pi;
+      a.dst[g * a.stride] = (double)acc[v];
+    }
+  }
+}
+
+// one workgroup per (c, d): the pair rows {x, c} and {x, d} (x < c) of Y and
+// U are staged in LDS, then the waves sweep the tiles (b-block J, a-block I),
+// I <= J, of the symmetric c x c term
+template <typename T, bool ZMODE>
+__global__ __launch_bounds__(256) void k_bqp4b(BqpArgs a) {
+  typedef typename V4<T>::type v4;
+  const int2 cdp = a.cd[blockIdx.x];
+  const int c = cdp.x, d = cdp.y;
+  const int q = a.q;
+  const T* Y = (const T*)a.Yp;
+  const T* U = (const T*)a.Up;
+  constexpr int NS = ZMODE ? 4 : 2;   // staged row sets
+  __shared__ T sm[NS][112 * LP];     // c <= 111 rows per set
+  const int tid = threadIdx.x;
+  const int rc0 = 1 + q + (int)c2(c), rd0 = 1 + q + (int)c2(d);
+  const int nrow = ((c + 15) >> 4) << 4;
+  for (int i = tid; i < nrow * 16; i += 256) {
+    const int x = i >> 4, k = i & 15;
+    const bool ok = x < c;
+    sm[0][x * LP + k] = ok ? Y[(size_t)(rc0 + x) * 16 + k] : (T)0;
+    sm[1][x * LP + k] = ok ? Y[(size_t)(rd0 + x) * 16 + k] : (T)0;
+    if (ZMODE) {
+      sm[2 % NS][x * LP + k] = ok ? U[(size_t)(rc0 + x) * 16 + k] : (T)0;
+      sm[3 % NS][x * LP + k] = ok ? U[(size_t)(rd0 + x) * 16 + k] : (T)0;
+    }
+  }
+  __syncthreads();
+  const T* Yc = sm[0];
+  const T* Yd = sm[1];
+  const T* Uc = sm[2 % NS];
+  const T* Ud = sm[3 % NS];
+  const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int nbk = (c + 15) >> 4;
+  const int ntile = nbk * (nbk + 1) / 2;
+  const long long base = a.off4 + c3(c) + c4(d);
+  for (int t = w; t < ntile; t += 4) {
+    int J = 0;
+    while ((J + 1) * (J + 2) / 2 <= t) ++J;
+    const int I = t - J * (J + 1) / 2;
+    const int rb = J * 16 + li, ra = I * 16 + li;  // A rows b, B columns a
+    v4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = 4 * j + lk;
+      if (ZMODE) {
+        // (ad|bc) = Y_bc.U_ad + U_bc.Y_ad ; (ac|bd) = Y_bd.U_ac + U_bd.Y_ac
+        acc = mfma(Yc[rb * LP + k], Ud[ra * LP + k], acc);
+        acc = mfma(Uc[rb * LP + k], Yd[ra * LP + k], acc);
+        acc = mfma(Yd[rb * LP + k], Uc[ra * LP + k], acc);
+        acc = mfma(Ud[rb * LP + k], Yc[ra * LP + k], acc);
+      } else {
+        acc = mfma(Yc[rb * LP + k], Yd[ra * LP + k], acc);
+        acc = mfma(Yd[rb * LP + k], Yc[ra * LP + k], acc);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int bb = J * 16 + drow<T>(lk, v);
+      const int aa = I * 16 + li;
+      if (aa < bb && bb < c) {
+        const long long g = base + aa + c2(bb);
+        const double t1 = a.dst[g * a.stride];
+        a.dst[g * a.stride] = (t1 + (double)acc[v]) * (1.0 / 3.0);
+      }
+    }
+  }
+}
+
+// B(r1, r2) by 16 lanes (lane k owns element k), summed in a fixed order
+template <typename T, bool ZMODE>
+__device__ __forceinline__ double bform16(const T* Y, const T* U, int r1, int r2, int k) {
+  double v;
+  if (ZMODE)
+    v = (double)Y[(size_t)r1 * 16 + k] * (double)U[(size_t)r2 * 16 + k] +
+        (double)U[(size_t)r1 * 16 + k] * (double)Y[(size_t)r2 * 16 + k];
+  else
+    v = (double)Y[(size_t)r1 * 16 + k] * (double)Y[(size_t)r2 * 16 + k];
+  return v;
+}
+
+// degree 3: 16 lanes per class {a<b<c}, id = off3 + a + C(b,2) + C(c,3)
+template <typename T, bool ZMODE>
+__global__ __launch_bounds__(256) void k_bqp3(BqpArgs a) {
+  const long long t = ((long long)blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int k = threadIdx.x & 15;
+  const int q = a.q;
+  const bool ok = t < c3(q);
+  int c = 2, b = 1, aa = 0;
+  if (ok) {
+    c = inv_c3(t);
+    const long long t2 = t - c3(c);
+    b = inv_c2(t2);
+    aa = (int)(t2 - c2(b));
+  }
+  const T* Y = (const T*)a.Yp;
+  const T* U = (const T*)a.Up;
+  double v = 0.0;
+  if (ok)
+    v = bform16<T, ZMODE>(Y, U, 1 + aa, prow(q, b, c), k) + bform16<T, ZMODE>(Y, U, 1 + b, prow(q, aa, c), k) +
+        bform16<T, ZMODE>(Y, U, 1 + c, prow(q, aa, b), k);
+  v = sum16(v);
+  if (ok && k == 0) a.dst[(a.off3 + t) * a.stride] = v * (1.0 / 3.0);
+}
+
+// degrees 2 and 1: one wave per class; 4 groups of 16 lanes split the sum
+// over the third index, combined in a fixed order
+template <typename T, bool ZMODE>
+__global__ __launch_bounds__(256) void k_bqp21(BqpArgs a) {
+  const int q = a.q;
+  const long long t = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63, k = lane & 15, g = lane >> 4;
+  const long long n2 = c2(q);
+  const T* Y = (const T*)a.Yp;
+  const T* U = (const T*)a.Up;
+  double v = 0.0;
+  long long out = -1;
+  if (t < n2) {
+    const int j = inv_c2(t);
+    const int i = (int)(t - c2(j));
+    if (g == 0) v = bform16<T, ZMODE>(Y, U, 0, prow(q, i, j), k) + bform16<T, ZMODE>(Y, U, 1 + i, 1 + j, k);
+    for (int l = g; l < q; l += 4) {
+      if (l == i || l == j) continue;
+      const int ri = l < i ? prow(q, l, i) : prow(q, i, l);
+      const int rj = l < j ? prow(q, l, j) : prow(q, j, l);
+      v += bform16<T, ZMODE>(Y, U, ri, rj, k);
+    }
+    out = a.off2 + t;
+  } else if (t < n2 + q) {
+    const int i = (int)(t - n2);
+    if (g == 0) v = bform16<T, ZMODE>(Y, U, 0, 1 + i, k);
+    for (int j = g; j < q; j += 4) {
+      if (j == i) continue;
+      v += bform16<T, ZMODE>(Y, U, 1 + j, j < i ? prow(q, j, i) : prow(q, i, j), k);
+    }
+    out = 1 + i;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (out >= 0 && lane == 0) a.dst[out * a.stride] = v / (double)q;
+}
+
+// degree 0: partial sums of B(alpha, alpha) / 2 ... per block (16 lanes per row)
+template <typename T, bool ZMODE>
+__global__ __launch_bounds__(256) void k_bqp0(BqpArgs a, int n) {
+  __shared__ double red[16];
+  const int r = (blockIdx.x * 256 + threadIdx.x) >> 4;
+  const int k = threadIdx.x & 15;
+  const T* Y = (const T*)a.Yp;
+  const T* U = (const T*)a.Up;
+  double v = (r < n) ? bform16<T, ZMODE>(Y, U, r, r, k) : 0.0;
+  v = sum16(v);
+  if (k == 0) red[threadIdx.x >> 4] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < 16; ++i) s += red[i];
+    a.part[blockIdx.x] = s;
+  }
+}
+
+// fixed-order reduction of `cnt` partials by one 256-thread block
+__device__ __forceinline__ double block_sum(const double* __restrict__ x, int cnt, double* red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += 256) acc += x[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_bqp0_final(BqpArgs a, int nblk, int n) {
+  __shared__ double red[256];
+  const double s = block_sum(a.part, nblk, red);
+  if (threadIdx.x == 0) a.dst[0] = s / (double)n;
 }
 
 // ---------------------------------------------------------------------------
@@ -713,7 +1228,9 @@ static KArgs make_args(mdsdp_problem P) {
   a.nk = (P->last_p + 3) / 4;
   a.Yp = P->Yp;
   a.Up = P->Up;
-  a.cinf = P->cinf;
+  a.cy = P->cy;
+  a.yp = P->yp;
+  a.sacc = P->sacc;
   a.Cavg = P->Cavg;
   a.bound = P->bound;
   a.scal = P->scal;
@@ -729,69 +1246,128 @@ static unsigned seg_grid(mdsdp_problem P) { return (unsigned)(8 * ((P->nseg + 7)
 
 void timer_begin(mdsdp_problem P, hipStream_t s, const char* name) {
   if (!P->timer.on) return;
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
-  hipEventRecord(e, s);
-  P->timer.ev.push_back(e);
-  P->timer.names.push_back(name);
+  Timer::Rec r;
+  r.name = name;
+  if (hipEventCreate(&r.ev0) != hipSuccess) return;
+  if (hipEventRecord(r.ev0, s) != hipSuccess) return;
+  P->timer.recs.push_back(r);
+  P->timer.open.push_back(P->timer.recs.size() - 1);
 }
 void timer_end(mdsdp_problem P, hipStream_t s) {
-  if (!P->timer.on) return;
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
-  hipEventRecord(e, s);
-  P->timer.ev.push_back(e);
-  P->timer.names.push_back("");
+  if (!P->timer.on || P->timer.open.empty()) return;
+  Timer::Rec& r = P->timer.recs[P->timer.open.back()];
+  P->timer.open.pop_back();
+  if (hipEventCreate(&r.ev1) != hipSuccess) return;
+  (void)hipEventRecord(r.ev1, s);
 }
 
 mdsdp_status launch_stage(mdsdp_problem P, int p, const double* Y, const double* U, bool fp32,
                           hipStream_t s) {
   P->last_p = p;
-  MDSDP_HIP(hipMemsetAsync(P->bound, 0, 2 * sizeof(unsigned long long), s));
+  timer_begin(P, s, "stage");
+  unsigned long long* bnd = P->bqp_q > 0 ? nullptr : P->bound;
+  if (bnd) MDSDP_HIP(hipMemsetAsync(P->bound, 0, 2 * sizeof(unsigned long long), s));
   const long long cnt = (long long)P->npad * 16;
   if (fp32)
     k_stage<float><<<blocks_for(cnt, 256), 256, 0, s>>>(P->n, p, P->npad, Y, U, (float*)P->Yp, (float*)P->Up,
-                                                         P->bound);
+                                                         bnd);
   else
     k_stage<double><<<blocks_for(cnt, 256), 256, 0, s>>>(P->n, p, P->npad, Y, U, (double*)P->Yp,
-                                                          (double*)P->Up, P->bound);
+                                                          (double*)P->Up, bnd);
+  timer_end(P, s);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+static mdsdp_status launch_bqp(mdsdp_problem P, bool zmode, bool fp32, hipStream_t s) {
+  BqpArgs b{};
+  b.q = P->bqp_q;
+  b.off2 = P->bqp_off[2];
+  b.off3 = P->bqp_off[3];
+  b.off4 = P->bqp_off[4];
+  b.Yp = P->Yp;
+  b.Up = P->Up;
+  b.items = P->bqp4a_items;
+  b.cd = P->bqp_cd;
+  b.ncd = P->bqp_ncd;
+  b.dst = zmode ? P->yp : (double*)P->cy + 1;
+  b.stride = zmode ? 1 : 2;
+  b.part = P->gpart;
+  const int q = P->bqp_q;
+  const long long n3 = (long long)q * (q - 1) * (q - 2) / 6, n2 = (long long)q * (q - 1) / 2;
+  const int nrowblk = (P->n * 16 + 255) / 256;
+#define BQP_LAUNCH(TT, ZZ)                                                                      \
+  do {                                                                                          \
+    timer_begin(P, s, "bqp4a");                                                                 \
+    if (P->bqp4a_n > 0) k_bqp4a<TT, ZZ><<<P->bqp4a_n, 256, 0, s>>>(b);                          \
+    timer_end(P, s);                                                                            \
+    timer_begin(P, s, "bqp4b");                                                                 \
+    if (P->bqp_ncd > 0) k_bqp4b<TT, ZZ><<<P->bqp_ncd, 256, 0, s>>>(b);                         \
+    timer_end(P, s);                                                                            \
+    timer_begin(P, s, "bqp3");                                                                  \
+    if (n3 > 0) k_bqp3<TT, ZZ><<<blocks_for(n3 * 16, 256), 256, 0, s>>>(b);                      \
+    timer_end(P, s);                                                                            \
+    timer_begin(P, s, "bqp21");                                                                 \
+    k_bqp21<TT, ZZ><<<blocks_for((n2 + q) * 64, 256), 256, 0, s>>>(b);                           \
+    timer_end(P, s);                                                                            \
+    timer_begin(P, s, "bqp0");                                                                  \
+    k_bqp0<TT, ZZ><<<nrowblk, 256, 0, s>>>(b, P->n);                                            \
+    k_bqp0_final<<<1, 256, 0, s>>>(b, nrowblk, P->n);                                          \
+    timer_end(P, s);                                                                            \
+  } while (0)
+  if (!zmode)
+    BQP_LAUNCH(double, false);
+  else if (fp32)
+    BQP_LAUNCH(float, true);
+  else
+    BQP_LAUNCH(double, true);
+#undef BQP_LAUNCH
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
 
 mdsdp_status launch_classsum_S(mdsdp_problem P, hipStream_t s) {
-  KArgs a = make_args(P);
-  P->spar ^= 1;
-  const int par = P->spar;
-  a.sS_acc = P->sS[par];
-  a.sS_clr = P->sS[par ^ 1];
   timer_begin(P, s, "classsum_S");
-  k_classsum<double, false><<<seg_grid(P), 256, 0, s>>>(a);
+  if (P->bqp_q > 0) {
+    mdsdp_status st = launch_bqp(P, false, false, s);
+    if (st != MDSDP_OK) return st;
+  } else {
+    KArgs a = make_args(P);
+    k_classsum<double, false><<<seg_grid(P), 256, 0, s>>>(a);
+    k_final_S<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->Cavg, P->scal, P->cy);
+  }
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
 
 mdsdp_status launch_classsum_Z(mdsdp_problem P, bool fp32, hipStream_t s) {
-  KArgs a = make_args(P);
-  P->zpar ^= 1;
-  const int par = P->zpar;
-  a.sZ_acc = P->sZ[par];
-  a.sZ_clr = P->sZ[par ^ 1];
   timer_begin(P, s, fp32 ? "classsum_Z32" : "classsum_Z64");
-  if (fp32)
-    k_classsum<float, true><<<seg_grid(P), 256, 0, s>>>(a);
-  else
-    k_classsum<double, true><<<seg_grid(P), 256, 0, s>>>(a);
+  if (P->bqp_q > 0) {
+    mdsdp_status st = launch_bqp(P, true, fp32, s);
+    if (st != MDSDP_OK) return st;
+  } else {
+    KArgs a = make_args(P);
+    if (fp32)
+      k_classsum<float, true><<<seg_grid(P), 256, 0, s>>>(a);
+    else
+      k_classsum<double, true><<<seg_grid(P), 256, 0, s>>>(a);
+    k_final_Z<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->scal, P->yp);
+  }
   timer_end(P, s);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_bty(mdsdp_problem P, hipStream_t s) {
+  const int nblk = 64;
+  k_bty_part<<<nblk, 256, 0, s>>>(P->bty_range, P->bvec, P->cy, P->gpart + 4096);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
 
 mdsdp_status launch_resid(mdsdp_problem P, int mode, bool fp32, hipStream_t s) {
   KArgs a = make_args(P);
-  a.sS = P->sS[P->spar];
-  a.sZ = P->sZ[P->zpar];
   const unsigned g = seg_grid(P);
   switch (mode) {
     case M_GRAD:
@@ -833,9 +1409,11 @@ static RowArgs row_args(mdsdp_problem P, int p) {
 }
 
 mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* U, hipStream_t s) {
-  const int nblk = (P->n + 63) / 64;
+  const int nblk = std::min(32, (P->n + 63) / 64);
+  timer_begin(P, s, "gram");
   k_gram_part<<<nblk, 256, 0, s>>>(P->n, p, Y, U, P->gpart);
   k_gram_final<<<1, 512, 0, s>>>(nblk, P->gpart, P->gram);
+  timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
@@ -845,7 +1423,8 @@ mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, doubl
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_grad");
   k_row_grad<<<blocks_for((long long)P->n * 16, 256), 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
-  k_scalars<<<1, 256, 0, s>>>(M_GRAD, P->wgpart, P->nseg, nullptr, 0, P->sigma, P->scal, f, nullptr);
+  k_scalars<<<1, 256, 0, s>>>(M_GRAD, P->wgpart, P->nseg, nullptr, 0, P->gpart + 4096, 64, P->sigma, P->scal, f,
+                              nullptr);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -871,7 +1450,8 @@ mdsdp_status launch_rowfinal_mult(mdsdp_problem P, int p, const double* Y, doubl
   RowArgs ra = row_args(P, p);
   const unsigned nblk = blocks_for((long long)P->n * 16, 256);
   k_row_mult<<<nblk, 256, 0, s>>>(ra, Y, P->zmult, z, P->zpart);
-  k_scalars<<<1, 256, 0, s>>>(M_MULT, P->wgpart, P->nseg, P->zpart, (int)nblk, P->sigma, P->scal, nullptr, kkt);
+  k_scalars<<<1, 256, 0, s>>>(M_MULT, P->wgpart, P->nseg, P->zpart, (int)nblk, P->gpart + 4096, 64, P->sigma,
+                              P->scal, nullptr, kkt);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
@@ -897,7 +1477,7 @@ mdsdp_status launch_project(int n, int p, const double* Y, const double* U, doub
 }
 
 mdsdp_status launch_y_export(mdsdp_problem P, double* y, hipStream_t s) {
-  k_y_export<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sS[P->spar], P->cinf, P->Cavg, P->scal, y);
+  k_y_export<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->cy, y);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
@@ -909,16 +1489,16 @@ mdsdp_status launch_set_dense(mdsdp_problem P, const double* X, hipStream_t s) {
 }
 
 mdsdp_status launch_get_dense(mdsdp_problem P, double* X, bool add_D, hipStream_t s) {
-  k_get_dense<<<blocks_for(P->nslots, 256), 256, 0, s>>>(P->n, P->nb, P->nslots, P->Xt, P->cls, P->cinf,
+  k_get_dense<<<blocks_for(P->nslots, 256), 256, 0, s>>>(P->n, P->nb, P->nslots, P->Xt, P->cls, P->cy,
                                                          add_D ? 1 : 0, X);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
 
-mdsdp_status vec_dots(const double* const* a, const double* const* b, int npairs, long long len, double* out_dev,
-                      double* part, int nblk, hipStream_t s) {
-  k_dots<<<nblk, 256, 0, s>>>(a, b, npairs, len, part);
-  k_dots_final<<<1, 256, 0, s>>>(npairs, nblk, part, out_dev);
+mdsdp_status vec_dots(const DotPtrs& dp, int npairs, long long len, double* out_dev, double* part, int nblk,
+                      hipStream_t s) {
+  k_dots<<<nblk, 256, 0, s>>>(dp, npairs, len, part);
+  k_dots_final<<<npairs, 256, 0, s>>>(npairs, nblk, part, out_dev);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
@@ -926,6 +1506,48 @@ mdsdp_status vec_dots(const double* const* a, const double* const* b, int npairs
 mdsdp_status vec_lincomb(long long len, double alpha, const double* x, double beta, const double* y, double* out,
                          hipStream_t s) {
   k_lincomb<<<blocks_for(len, 256), 256, 0, s>>>(len, alpha, x, beta, y, out);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_tcg_update(int n, int p, const double* Y, double alpha, double rr_old, double* eta,
+                               double* Heta, double* r, double* d, const double* Hd, double* part,
+                               double* rr_beta_dev, hipStream_t s) {
+  const unsigned nb = blocks_for(n, 256);
+  k_tcg_update1<<<nb, 256, 0, s>>>(n, p, Y, alpha, eta, Heta, r, d, Hd, part);
+  k_rr_beta<<<1, 256, 0, s>>>((int)nb, part, rr_old, rr_beta_dev);
+  k_tcg_update2<<<nb, 256, 0, s>>>(n, p, Y, rr_beta_dev + 1, r, d);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_vt_w(int n, int k, const double* V, const double* w, double* h, hipStream_t s) {
+  k_vt_w<<<k, 256, 0, s>>>(n, V, w, h);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_rightmul(int n, int p, int q, const double* Yin, const double* M, bool normalize,
+                             double* Yout, hipStream_t s) {
+  k_rightmul<<<blocks_for(n, 256), 256, 0, s>>>(n, p, q, Yin, M, normalize ? 1 : 0, Yout);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_set_col(int n, int p, int col, const double* v, double* U, hipStream_t s) {
+  k_set_col<<<blocks_for(n, 256), 256, 0, s>>>(n, p, col, v, U);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_gemv_sub(int n, int k, const double* V, const double* h, double* w, hipStream_t s) {
+  k_gemv_sub<<<blocks_for(n, 256), 256, 0, s>>>(n, k, V, h, w);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_gemv(int n, int k, const double* V, const double* sv, double* out, hipStream_t s) {
+  k_gemv<<<blocks_for(n, 256), 256, 0, s>>>(n, k, V, sv, out);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }

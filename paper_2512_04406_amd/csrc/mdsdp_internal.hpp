@@ -42,10 +42,13 @@ struct Seg {
 enum Mode { M_GRAD = 0, M_MULT = 1, M_XMV = 2, M_HVP = 3 };
 
 struct Timer {
+  struct Rec {
+    std::string name;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  };
   bool on = false;
-  std::vector<hipEvent_t> ev;
-  std::vector<std::string> names;
-  std::vector<double> ms;
+  std::vector<Rec> recs;
+  std::vector<size_t> open;  // indices of records whose end is pending
 };
 
 }  // namespace mdsdp
@@ -71,11 +74,20 @@ struct mdsdp_problem_s {
   double* Ct = nullptr;         // nslots or null
   mdsdp::Seg* segs = nullptr;   // nseg
   int* seg_start = nullptr;     // nb + 1: segments of column block J are seg_start[J]..seg_start[J+1]-1
-  double2* cinf = nullptr;      // m: {D_gamma, 1/|gamma|}
+  double2* cy = nullptr;        // m: {D_gamma, y_gamma} (y = class average of Z at the last S-pass)
+  double* yp = nullptr;         // m: class average of Y U^T + U Y^T at the last HVP
+  double* invc = nullptr;       // m: 1 / |gamma|
+  double* bvec = nullptr;       // m: b
   double* Cavg = nullptr;       // m or null: A(C)_gamma / |gamma|
-  long long* sS[2] = {nullptr, nullptr};  // fixed-point class sums of Y Y^T (double-buffered)
-  long long* sZ[2] = {nullptr, nullptr};  // fixed-point class sums of Y U^T + U Y^T
-  int spar = 0, zpar = 0;       // buffer holding the latest sums
+  long long* sacc = nullptr;    // m: fixed-point accumulator of the generic class-sum pass
+  long long bty_range = 0;      // classes [0, bty_range) may have b != 0
+  // structured BQP path (colex basis and class order), q = 0 when generic
+  int bqp_q = 0;
+  long long bqp_off[6] = {0, 0, 0, 0, 0, 0};
+  int4* bqp4a_items = nullptr;  // (c, d0, pi0, 0) work items of the (ab|cd) pass
+  int bqp4a_n = 0;
+  int2* bqp_cd = nullptr;       // (c, d) pairs, 2 <= c < d < q
+  int bqp_ncd = 0;
   // staging / workspace
   void* Yp = nullptr;           // npad x 16 (double or float)
   void* Up = nullptr;
@@ -92,7 +104,8 @@ struct mdsdp_problem_s {
   int last_p = 0;
   // solver / Lanczos workspace
   double* dotpart = nullptr;
-  const double** dotptr = nullptr;  // device array of pointers for k_dots
+  const double** dotptr = nullptr;  // unused (kept for layout stability)
+  double* hbuf = nullptr;       // pinned host buffer for scalar read-backs
   int dot_nblk = 0;
   double* work = nullptr;       // n x 16 x 8 doubles of solver scratch
   double* lz_V = nullptr;       // Lanczos basis, n x lz_cap
@@ -112,7 +125,13 @@ enum {
   SC_SUMZ = 4,     // sum z
   SC_CXZ = 5,      // <C, Xt + D> (for eta_g when C != 0)
   SC_NONFIN = 6,   // sticky non-finite flag
-  SC_COUNT = 16
+  SC_SCALE_S = 7,  // fixed-point scale of the latest S-sums
+  SC_SCALE_Z = 8,  // fixed-point scale of the latest Z'-sums
+  SC_BTYP = 9,     // b^T y partials (up to 8 slots at 40..47 are not used)
+  SC_FOUT = 16,    // solver: cost read-back
+  SC_DOTS = 17,    // solver: dot products read-back (8 slots)
+  SC_KKT = 25,     // solver: kkt read-back (4 slots)
+  SC_COUNT = 32
 };
 
 namespace mdsdp {
@@ -131,6 +150,7 @@ mdsdp_status launch_stage(mdsdp_problem P, int p, const double* Y, const double*
                           hipStream_t s);
 mdsdp_status launch_classsum_S(mdsdp_problem P, hipStream_t s);
 mdsdp_status launch_classsum_Z(mdsdp_problem P, bool fp32, hipStream_t s);
+mdsdp_status launch_bty(mdsdp_problem P, hipStream_t s);
 mdsdp_status launch_resid(mdsdp_problem P, int mode, bool fp32, hipStream_t s);
 mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* U,
                          hipStream_t s);
@@ -151,11 +171,24 @@ mdsdp_status launch_set_dense(mdsdp_problem P, const double* Xdense, hipStream_t
 mdsdp_status launch_get_dense(mdsdp_problem P, double* Xdense, bool add_D, hipStream_t s);
 
 // vector kernels used by the solver (kernels.hip)
-mdsdp_status vec_dots(const double* const* a, const double* const* b, int npairs, long long len,
-                      double* out_dev, double* part, int nblk, hipStream_t s);
+struct DotPtrs {
+  const double* a[8];
+  const double* b[8];
+};
+mdsdp_status vec_dots(const DotPtrs& dp, int npairs, long long len, double* out_dev, double* part, int nblk,
+                      hipStream_t s);
 mdsdp_status vec_lincomb(long long len, double alpha, const double* x, double beta,
                          const double* y, double* out, hipStream_t s);
 mdsdp_status vec_fill(long long len, double v, double* out, hipStream_t s);
+mdsdp_status launch_tcg_update(int n, int p, const double* Y, double alpha, double rr_old, double* eta,
+                               double* Heta, double* r, double* d, const double* Hd, double* part,
+                               double* rr_beta_dev, hipStream_t s);
+mdsdp_status launch_vt_w(int n, int k, const double* V, const double* w, double* h, hipStream_t s);
+mdsdp_status launch_rightmul(int n, int p, int q, const double* Yin, const double* M, bool normalize,
+                             double* Yout, hipStream_t s);
+mdsdp_status launch_set_col(int n, int p, int col, const double* v, double* U, hipStream_t s);
+mdsdp_status launch_gemv_sub(int n, int k, const double* V, const double* h, double* w, hipStream_t s);
+mdsdp_status launch_gemv(int n, int k, const double* V, const double* sv, double* out, hipStream_t s);
 
 void timer_begin(mdsdp_problem P, hipStream_t s, const char* name);
 void timer_end(mdsdp_problem P, hipStream_t s);

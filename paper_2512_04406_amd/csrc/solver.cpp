@@ -1,12 +1,666 @@
-// Outer loop (Algorithm alg1), RTR + truncated CG, Lanczos: filled in next.
+// Outer loop of ManiDSDP (Algorithm alg1), the Riemannian trust-region
+// subproblem solver with truncated CG, and a Lanczos eigensolver for the
+// dual certificate X = Xt + D - Diag(z).  Host C++ drives the iteration; every
+// vector operation is a kernel on the problem's stream, and the host reads
+// back only the scalars a decision needs (one synchronisation per tCG step).
+//
+// Readings of points the paper leaves open (same as the oracle's):
+//  * RTR constants rho' = 0.1, kappa = 0.1, theta = 1, Delta_bar = pi sqrt(n),
+//    Delta_0 = Delta_bar / 8 (Absil-Baker-Gallivan trust region);
+//  * inner tolerance max(gtol_min, min(gtol0, 0.1 eta_max));
+//  * carried direction: backtracking t = sqrt(n), sqrt(n)/2, ... along
+//    R_[Y,0](t [0, v]) until Psi_k decreases, then RTR;
+//  * rank rule: drop singular directions of Y below tau_rank * s_1, then add
+//    one zero column for the negative eigenvector (p <= p_max);
+//  * sigma rule eq. sec5:eq1 with ||R|| = ||Q(Z)||_F and the final ||grad||.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <utility>
+#include <vector>
+
 #include "mdsdp_internal.hpp"
+
+namespace mdsdp {
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+#define CHK(x)                         \
+  do {                                 \
+    mdsdp_status st__ = (x);           \
+    if (st__ != MDSDP_OK) return st__; \
+  } while (0)
+
+// ---- small host linear algebra ------------------------------------------------
+
+// cyclic Jacobi for a symmetric k x k matrix (k <= 16): A is overwritten,
+// eigenvalues in w, eigenvectors in the columns of V (row-major)
+void jacobi_eig(int k, double* A, double* w, double* V) {
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) V[i * k + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j) off += A[i * k + j] * A[i * k + j];
+    if (off < 1e-30) break;
+    for (int pp = 0; pp < k; ++pp)
+      for (int q = pp + 1; q < k; ++q) {
+        const double apq = A[pp * k + q];
+        if (fabs(apq) < 1e-300) continue;
+        const double app = A[pp * k + pp], aqq = A[q * k + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < k; ++r) {
+          const double arp = A[r * k + pp], arq = A[r * k + q];
+          A[r * k + pp] = c * arp - s * arq;
+          A[r * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double apr = A[pp * k + r], aqr = A[q * k + r];
+          A[pp * k + r] = c * apr - s * aqr;
+          A[q * k + r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = V[r * k + pp], vrq = V[r * k + q];
+          V[r * k + pp] = c * vrp - s * vrq;
+          V[r * k + q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  for (int i = 0; i < k; ++i) w[i] = A[i * k + i];
+}
+
+// number of eigenvalues of the symmetric tridiagonal (a, b) below x (Sturm)
+int sturm_count(int k, const double* a, const double* b, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < k; ++i) {
+    if (q == 0.0) q = 1e-300;
+    q = a[i] - x - b[i - 1] * b[i - 1] / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+// j-th smallest eigenvalue (0-based) by bisection
+double tridiag_eig(int k, const double* a, const double* b, int j) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < k ? fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  const double span = std::max(1e-300, hi - lo);
+  lo -= 1e-12 * span;
+  hi += 1e-12 * span;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(k, a, b, mid) > j)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// eigenvector of the tridiagonal for eigenvalue theta by inverse iteration
+void tridiag_evec(int k, const double* a, const double* b, double theta, std::vector<double>& s) {
+  s.assign(k, 1.0 / sqrt((double)k));
+  double scale = 0.0;
+  for (int i = 0; i < k; ++i) scale = std::max(scale, fabs(a[i]) + (i + 1 < k ? fabs(b[i]) : 0.0));
+  const double shift = theta - 1e-13 * std::max(scale, 1e-300);
+  std::vector<double> c(k), d(k), x(k);
+  for (int it = 0; it < 4; ++it) {
+    // solve (T - shift I) x = s with partial-pivoting-free Thomas (shifted below
+    // the spectrum edge the system is definite enough for the extreme pair)
+    for (int i = 0; i < k; ++i) {
+      d[i] = a[i] - shift;
+      c[i] = (i + 1 < k) ? b[i] : 0.0;
+    }
+    x = s;
+    for (int i = 1; i < k; ++i) {
+      double piv = d[i - 1];
+      if (fabs(piv) < 1e-300) piv = 1e-300;
+      const double mlt = b[i - 1] / piv;
+      d[i] -= mlt * c[i - 1];
+      x[i] -= mlt * x[i - 1];
+    }
+    double piv = d[k - 1];
+    if (fabs(piv) < 1e-300) piv = 1e-300;
+    x[k - 1] /= piv;
+    for (int i = k - 2; i >= 0; --i) {
+      double pv = d[i];
+      if (fabs(pv) < 1e-300) pv = 1e-300;
+      x[i] = (x[i] - c[i] * x[i + 1]) / pv;
+    }
+    double nrm = 0.0;
+    for (double v : x) nrm += v * v;
+    nrm = sqrt(nrm);
+    if (!(nrm > 0.0) || !std::isfinite(nrm)) break;
+    for (int i = 0; i < k; ++i) s[i] = x[i] / nrm;
+  }
+}
+
+uint64_t splitmix(uint64_t& st) {
+  uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void gaussian_fill(uint64_t seed, std::vector<double>& v) {
+  uint64_t st = seed;
+  for (size_t i = 0; i < v.size(); i += 2) {
+    const double u1 = ((splitmix(st) >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+    const double u2 = (splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+    const double r = sqrt(-2.0 * log(u1));
+    v[i] = r * cos(2.0 * M_PI * u2);
+    if (i + 1 < v.size()) v[i + 1] = r * sin(2.0 * M_PI * u2);
+  }
+}
+
+// ---- device scalar helpers ----------------------------------------------------
+
+mdsdp_status dots(mdsdp_problem P, int npairs, const double* const* a, const double* const* b, long long len,
+                  double* host, hipStream_t s) {
+  DotPtrs dp{};
+  for (int i = 0; i < npairs; ++i) {
+    dp.a[i] = a[i];
+    dp.b[i] = b[i];
+  }
+  double* out_dev = P->scal + SC_DOTS;
+  CHK(vec_dots(dp, npairs, len, out_dev, P->dotpart, P->dot_nblk, s));
+  MDSDP_HIP(hipMemcpyAsync(P->hbuf, out_dev, npairs * sizeof(double), hipMemcpyDeviceToHost, s));
+  MDSDP_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < npairs; ++i) host[i] = P->hbuf[i];
+  return MDSDP_OK;
+}
+
+// pinned read-back buffer: [0, 64) scalars, [64, 1024) small arrays
+mdsdp_status read_dev(mdsdp_problem P, const double* dev, int cnt, double* host, hipStream_t s) {
+  if (cnt > 1024 - 64) {
+    set_error("read_dev: too many values");
+    return MDSDP_EINVAL;
+  }
+  MDSDP_HIP(hipMemcpyAsync(P->hbuf + 64, dev, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+  MDSDP_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < cnt; ++i) host[i] = P->hbuf[64 + i];
+  return MDSDP_OK;
+}
+
+struct Work {
+  int n = 0;
+  double* buf = nullptr;
+  double *Ynew, *g, *gnew, *eta, *Heta, *r, *d, *Hd, *U, *tmp, *part, *rrb;
+  mdsdp_status init(int n_) {
+    n = n_;
+    const size_t vec = (size_t)n * 16;
+    hipError_t e = hipMalloc((void**)&buf, (10 * vec + 4096) * sizeof(double));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(solver work)");
+    double* p = buf;
+    Ynew = p; p += vec;
+    g = p; p += vec;
+    gnew = p; p += vec;
+    eta = p; p += vec;
+    Heta = p; p += vec;
+    r = p; p += vec;
+    d = p; p += vec;
+    Hd = p; p += vec;
+    U = p; p += vec;
+    tmp = p; p += vec;
+    part = p; p += 4000;
+    rrb = p;
+    return MDSDP_OK;
+  }
+  ~Work() {
+    if (buf) (void)hipFree(buf);
+  }
+};
+
+struct Counters {
+  long long hvps = 0, cost_grads = 0, rtr_iters = 0, eig_iters = 0;
+  double t_eval = 0, t_hvp = 0, t_eig = 0, t_update = 0;
+};
+
+// cost (and optionally Riemannian gradient) at Y; returns f on the host
+mdsdp_status eval(mdsdp_problem P, int p, const double* Y, double* rgrad, double* f, Counters& C, hipStream_t s) {
+  auto t0 = clk::now();
+  CHK(mdsdp_cost_grad(P, p, Y, P->scal + SC_FOUT, nullptr, rgrad, s));
+  CHK(read_dev(P, P->scal + SC_FOUT, 1, f, s));
+  C.cost_grads++;
+  C.t_eval += secs(t0, clk::now());
+  return MDSDP_OK;
+}
+
+// ---- truncated CG ---------------------------------------------------------------
+enum { TCG_NEG = 0, TCG_BOUND = 1, TCG_CONV = 2, TCG_MAXIT = 3 };
+
+mdsdp_status tcg(mdsdp_problem P, int p, const double* Y, const double* g, double gn, double Delta, int prec,
+                 int maxinner, Work& W, Counters& C, int* stop, hipStream_t s) {
+  // Steihaug-Toint truncated CG.  Host state at the top of step j:
+  // rr = ||r||^2, e_Pe = <eta, eta>, e_Pd = <eta, d>, d_Pd = <d, d>.
+  // The device update of step j also computes ||r_new||^2 and beta and
+  // applies d = P_Y(-r + beta d); the host reads those two scalars together
+  // with <d, Hd> of step j + 1 (one synchronisation per step).  A convergence
+  // detected there discards that last HVP; eta is the one of step j.
+  const int n = P->n;
+  const long long len = (long long)n * p;
+  const double kappa = 0.1, theta = 1.0;
+  CHK(vec_fill(len, 0.0, W.eta, s));
+  CHK(vec_fill(len, 0.0, W.Heta, s));
+  CHK(vec_lincomb(len, 1.0, g, 0.0, nullptr, W.r, s));
+  CHK(vec_lincomb(len, -1.0, g, 0.0, nullptr, W.d, s));
+  double rr = gn * gn;
+  const double tol = gn * std::min(pow(gn, theta), kappa);
+  double e_Pe = 0.0, e_Pd = 0.0, d_Pd = rr;
+  bool pending = false;
+  double e_part = 0.0, d_Pd_old = 0.0;
+  *stop = TCG_MAXIT;
+  DotPtrs dp{};
+  dp.a[0] = W.d;
+  dp.b[0] = W.Hd;
+  for (int j = 0; j < maxinner; ++j) {
+    auto t0 = clk::now();
+    CHK(mdsdp_hvp(P, p, prec, Y, W.d, W.Hd, 1, s));
+    C.hvps++;
+    CHK(vec_dots(dp, 1, len, P->scal + SC_DOTS, P->dotpart, P->dot_nblk, s));
+    MDSDP_HIP(hipMemcpyAsync(P->hbuf, P->scal + SC_DOTS, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (pending) MDSDP_HIP(hipMemcpyAsync(P->hbuf + 1, W.rrb, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MDSDP_HIP(hipStreamSynchronize(s));
+    C.t_hvp += secs(t0, clk::now());
+    const double dHd = P->hbuf[0];
+    if (pending) {
+      const double rr_new = P->hbuf[1], beta = P->hbuf[2];
+      if (sqrt(rr_new) <= tol) {
+        *stop = TCG_CONV;
+        return MDSDP_OK;
+      }
+      e_Pd = beta * e_part;
+      d_Pd = rr_new + beta * beta * d_Pd_old;
+      rr = rr_new;
+      pending = false;
+    }
+    const double alpha = (dHd != 0.0) ? rr / dHd : INFINITY;
+    const double e_Pe_new = e_Pe + 2.0 * alpha * e_Pd + alpha * alpha * d_Pd;
+    if (dHd <= 0.0 || e_Pe_new >= Delta * Delta) {
+      const double tau = (-e_Pd + sqrt(std::max(0.0, e_Pd * e_Pd + d_Pd * (Delta * Delta - e_Pe)))) / d_Pd;
+      CHK(vec_lincomb(len, tau, W.d, 1.0, W.eta, W.eta, s));
+      CHK(vec_lincomb(len, tau, W.Hd, 1.0, W.Heta, W.Heta, s));
+      *stop = dHd <= 0.0 ? TCG_NEG : TCG_BOUND;
+      return MDSDP_OK;
+    }
+    e_Pe = e_Pe_new;
+    CHK(launch_tcg_update(n, p, Y, alpha, rr, W.eta, W.Heta, W.r, W.d, W.Hd, W.part, W.rrb, s));
+    pending = true;
+    e_part = e_Pd + alpha * d_Pd;
+    d_Pd_old = d_Pd;
+  }
+  return MDSDP_OK;
+}
+
+// ---- Riemannian trust region -------------------------------------------------------
+struct RTRState {
+  double f = 0, gn = 0;
+  int iters = 0;
+};
+
+mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, int maxinner, int prec,
+                 Work& W, Counters& C, RTRState& st, hipStream_t s) {
+  const int n = P->n;
+  const long long len = (long long)n * p;
+  const double Delta_bar = M_PI * sqrt((double)n);
+  double Delta = Delta_bar / 8.0;
+  double f;
+  CHK(eval(P, p, Y, W.g, &f, C, s));
+  double gg;
+  {
+    const double* a[1] = {W.g};
+    CHK(dots(P, 1, a, a, len, &gg, s));
+  }
+  double gn = sqrt(gg);
+  int it = 0;
+  for (; it < maxiter; ++it) {
+    if (gn <= gtol) break;
+    int stop = 0;
+    CHK(tcg(P, p, Y, W.g, gn, Delta, prec, maxinner, W, C, &stop, s));
+    CHK(launch_retract(n, p, Y, W.eta, 1.0, W.Ynew, s));
+    double fnew;
+    CHK(eval(P, p, W.Ynew, W.gnew, &fnew, C, s));
+    double d3[3];
+    {
+      const double* a[3] = {W.g, W.eta, W.gnew};
+      const double* b[3] = {W.eta, W.Heta, W.gnew};
+      CHK(dots(P, 3, a, b, len, d3, s));
+    }
+    const double model_dec = -(d3[0] + 0.5 * d3[1]);
+    const double reg = std::max(1.0, fabs(f)) * 2.220446049250313e-16 * 1e3;
+    const double rho = (f - fnew + reg) / (model_dec + reg);
+    if (rho < 0.25)
+      Delta /= 4.0;
+    else if (rho > 0.75 && (stop == TCG_NEG || stop == TCG_BOUND))
+      Delta = std::min(2.0 * Delta, Delta_bar);
+    if (rho > 0.1 && std::isfinite(fnew)) {
+      std::swap(Y, W.Ynew);
+      std::swap(W.g, W.gnew);
+      f = fnew;
+      gn = sqrt(d3[2]);
+    } else {
+      // restore the cached class sums / z of the current point
+      double fcur;
+      CHK(eval(P, p, Y, W.g, &fcur, C, s));
+    }
+    C.rtr_iters++;
+  }
+  st.f = f;
+  st.gn = gn;
+  st.iters = it;
+  return MDSDP_OK;
+}
+
+}  // namespace
+
+// ---- Lanczos ----------------------------------------------------------------------
+static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t seed, double* lmin, double* lmax,
+                            double* evec, int* iters, bool* converged, hipStream_t s) {
+  const int n = P->n;
+  maxit = std::max(2, std::min(maxit, n));
+  if (P->lz_cap < maxit + 1) {
+    if (P->lz_V) (void)hipFree(P->lz_V);
+    P->lz_V = nullptr;
+    MDSDP_HIP(hipMalloc((void**)&P->lz_V, (size_t)n * (maxit + 1) * sizeof(double)));
+    P->lz_cap = maxit + 1;
+    if (!P->lz_w) MDSDP_HIP(hipMalloc((void**)&P->lz_w, (size_t)n * sizeof(double)));
+    if (P->lz_h) (void)hipFree(P->lz_h);
+    MDSDP_HIP(hipMalloc((void**)&P->lz_h, (size_t)(2 * maxit + 8) * sizeof(double)));
+  }
+  double* V = P->lz_V;
+  double* w = P->lz_w;
+  double* h = P->lz_h;
+  std::vector<double> v0(n);
+  gaussian_fill(seed ^ 0x5DEECE66Dull, v0);
+  double nrm = 0.0;
+  for (double x : v0) nrm += x * x;
+  nrm = sqrt(nrm);
+  for (double& x : v0) x /= nrm;
+  MDSDP_HIP(hipMemcpyAsync(V, v0.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  MDSDP_HIP(hipStreamSynchronize(s));
+  std::vector<double> al, be;
+  std::vector<double> sv;
+  double th_min = 0, th_max = 0;
+  int k = 0;
+  *converged = false;
+  for (int j = 0; j < maxit; ++j) {
+    double* vj = V + (size_t)j * n;
+    CHK(mdsdp_certificate_matvec(P, 1, vj, w, s));
+    // full reorthogonalisation, twice (classical Gram-Schmidt with refinement)
+    CHK(launch_vt_w(n, j + 1, V, w, h, s));
+    CHK(launch_gemv_sub(n, j + 1, V, h, w, s));
+    CHK(launch_vt_w(n, j + 1, V, w, h + maxit + 2, s));
+    CHK(launch_gemv_sub(n, j + 1, V, h + maxit + 2, w, s));
+    CHK(launch_vt_w(n, 1, w, w, h + 2 * maxit + 6, s));
+    double hj[3];
+    MDSDP_HIP(hipMemcpyAsync(P->hbuf, h + j, sizeof(double), hipMemcpyDeviceToHost, s));
+    MDSDP_HIP(hipMemcpyAsync(P->hbuf + 1, h + maxit + 2 + j, sizeof(double), hipMemcpyDeviceToHost, s));
+    MDSDP_HIP(hipMemcpyAsync(P->hbuf + 2, h + 2 * maxit + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    MDSDP_HIP(hipStreamSynchronize(s));
+    hj[0] = P->hbuf[0];
+    hj[1] = P->hbuf[1];
+    hj[2] = P->hbuf[2];
+    al.push_back(hj[0] + hj[1]);
+    const double bj = sqrt(std::max(0.0, hj[2]));
+    k = j + 1;
+    th_min = tridiag_eig(k, al.data(), be.data(), 0);
+    th_max = tridiag_eig(k, al.data(), be.data(), k - 1);
+    tridiag_evec(k, al.data(), be.data(), th_min, sv);
+    const double resid = bj * fabs(sv[k - 1]);
+    if (k >= 3 && resid <= tol * (1.0 + fabs(th_max))) {
+      *converged = true;
+      break;
+    }
+    if (bj <= 1e-14 * (1.0 + fabs(th_max))) {
+      *converged = true;  // invariant subspace
+      break;
+    }
+    be.push_back(bj);
+    CHK(vec_lincomb(n, 1.0 / bj, w, 0.0, nullptr, V + (size_t)(j + 1) * n, s));
+  }
+  *lmin = th_min;
+  *lmax = th_max;
+  *iters = k;
+  if (evec) {
+    // Ritz vector V s for the smallest Ritz value
+    MDSDP_HIP(hipMemcpyAsync(h, sv.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    CHK(launch_gemv(n, k, V, h, evec, s));
+    MDSDP_HIP(hipStreamSynchronize(s));
+  }
+  return MDSDP_OK;
+}
+
+}  // namespace mdsdp
+
+using namespace mdsdp;
+
 extern "C" {
-void mdsdp_default_options(mdsdp_options* o) { (void)o; }
-mdsdp_status mdsdp_min_eigpair(mdsdp_problem, double, int32_t, uint64_t, double*, double*, double*, int32_t*, void*) {
-  return MDSDP_EUNSUPPORTED;
+
+void mdsdp_default_options(mdsdp_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->tol = 1e-8;
+  o->max_outer = 200;
+  o->sigma0 = 1.0;
+  o->sigma_min = 1e-3;
+  o->sigma_max = 1e6;
+  o->gamma = 2.0;
+  o->kappa1 = 0.1;
+  o->kappa2 = 10.0;
+  o->p_max = 16;
+  o->tau_rank = 1e-4;
+  o->gtol0 = 1e-2;
+  o->gtol_min = 1e-10;
+  o->rtr_maxiter = 50;
+  o->tcg_maxinner = 200;
+  o->hvp_prec = MDSDP_FP64;
+  o->polish_fp64 = 1;
+  o->polish_eta = 1e-6;
+  o->eig_tol = 1e-10;
+  o->eig_maxit = 300;
+  o->time_limit_s = 0.0;
+  o->verbose = 0;
+  o->seed = 1;
 }
-mdsdp_status mdsdp_solve(mdsdp_problem, const mdsdp_options*, int32_t, double*, mdsdp_result*, double*, int32_t,
-                         void*) {
-  return MDSDP_EUNSUPPORTED;
+
+mdsdp_status mdsdp_min_eigpair(mdsdp_problem P, double tol, int32_t maxit, uint64_t seed, double* lambda_min,
+                               double* lambda_max, double* evec, int32_t* iters, void* stream) {
+  if (!P || !lambda_min || !lambda_max) {
+    set_error("NULL argument");
+    return MDSDP_EINVAL;
+  }
+  if (maxit < 2 || !(tol > 0.0)) {
+    set_error("maxit must be >= 2 and tol > 0");
+    return MDSDP_EINVAL;
+  }
+  bool conv = false;
+  int it = 0;
+  mdsdp_status st = lanczos(P, tol, maxit, seed, lambda_min, lambda_max, evec, &it, &conv, (hipStream_t)stream);
+  if (iters) *iters = it;
+  if (st != MDSDP_OK) return st;
+  if (!conv) {
+    set_error("Lanczos reached maxit before the residual tolerance");
+    return MDSDP_ENOCONV;
+  }
+  return MDSDP_OK;
 }
+
+mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, double* Ybuf, mdsdp_result* res,
+                         double* hist, int32_t hist_cap, void* stream) {
+  if (!P || !opt || !Ybuf || !res) {
+    set_error("NULL argument");
+    return MDSDP_EINVAL;
+  }
+  if (opt->p_max < 1 || opt->p_max > 16 || p0 < 1 || p0 > opt->p_max) {
+    set_error("need 1 <= p0 <= p_max <= 16");
+    return MDSDP_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int n = P->n;
+  const auto t_start = clk::now();
+  memset(res, 0, sizeof(*res));
+  Work W;
+  CHK(W.init(n));
+  Counters C;
+  int p = p0;
+  // the caller's buffer holds Y; we alternate between it and W.Ynew, so keep
+  // a pointer and copy back at the end.
+  double* Y = Ybuf;
+  // normalise rows of the start point
+  CHK(launch_retract(n, p, Y, Y, 0.0, Y, s));
+  CHK(mdsdp_set_multiplier(P, nullptr, opt->sigma0, s));
+  double sigma = opt->sigma0;
+  double eta_max = 1.0;
+  bool carry = false;
+  int p_maxr = p;
+  double eta[3] = {INFINITY, INFINITY, INFINITY};
+  double value = 0.0;
+  int k = 0;
+  mdsdp_status final_status = MDSDP_ENOCONV;
+  double* evec = W.tmp;
+  for (k = 0; k < opt->max_outer; ++k) {
+    CHK(mdsdp_set_sigma(P, sigma));
+    const int prec = (opt->polish_fp64 && eta_max < opt->polish_eta) ? MDSDP_FP64 : opt->hvp_prec;
+    if (carry) {
+      // backtracking along the carried negative-curvature direction
+      double f0;
+      CHK(eval(P, p, Y, nullptr, &f0, C, s));
+      double t = sqrt((double)n);
+      while (t > 1e-8) {
+        CHK(launch_retract(n, p, Y, W.U, t, W.Ynew, s));
+        double ft;
+        CHK(eval(P, p, W.Ynew, nullptr, &ft, C, s));
+        if (ft < f0) {
+          std::swap(Y, W.Ynew);
+          break;
+        }
+        t *= 0.5;
+      }
+    }
+    const double gtol = std::max(opt->gtol_min, std::min(opt->gtol0, 0.1 * eta_max));
+    RTRState rs;
+    CHK(rtr(P, p, Y, gtol, opt->rtr_maxiter, opt->tcg_maxinner, prec, W, C, rs, s));
+    // multiplier update (Algorithm alg1 steps 5-8)
+    auto tu = clk::now();
+    CHK(mdsdp_update_multiplier(P, p, Y, nullptr, nullptr, P->scal + SC_KKT, s));
+    double kk[4];
+    CHK(read_dev(P, P->scal + SC_KKT, 4, kk, s));
+    C.t_update += secs(tu, clk::now());
+    // certificate spectrum
+    auto te = clk::now();
+    double lmin = 0, lmax = 0;
+    int eit = 0;
+    bool conv = false;
+    CHK(lanczos(P, opt->eig_tol, opt->eig_maxit, opt->seed + (uint64_t)k, &lmin, &lmax, evec, &eit, &conv, s));
+    C.eig_iters += eit;
+    C.t_eig += secs(te, clk::now());
+    const double normR = kk[0], bty = kk[1], sumz = kk[2], cx = kk[3];
+    eta[0] = normR / (1.0 + P->normC);
+    eta[1] = std::max(0.0, -lmin) / (1.0 + fabs(lmax));
+    const double prim = cx + sumz;
+    eta[2] = fabs(prim - bty) / (1.0 + fabs(prim) + fabs(bty));
+    eta_max = std::max(eta[0], std::max(eta[1], eta[2]));
+    value = bty;
+    if (hist && k < hist_cap) {
+      double* hrow = hist + (size_t)k * 8;
+      hrow[0] = k;
+      hrow[1] = p;
+      hrow[2] = sigma;
+      hrow[3] = eta[0];
+      hrow[4] = eta[1];
+      hrow[5] = eta[2];
+      hrow[6] = value;
+      hrow[7] = (double)C.hvps;
+    }
+    if (opt->verbose)
+      fprintf(stderr, "[mdsdp] k=%d p=%d sigma=%.3g eta=(%.2e %.2e %.2e) value=%.10f gnorm=%.2e rtr=%d hvps=%lld eig=%d\n",
+              k, p, sigma, eta[0], eta[1], eta[2], value, rs.gn, rs.iters, C.hvps, eit);
+    if (eta_max <= opt->tol) {
+      final_status = MDSDP_OK;
+      ++k;
+      break;
+    }
+    if (opt->time_limit_s > 0 && secs(t_start, clk::now()) > opt->time_limit_s) {
+      ++k;
+      break;
+    }
+    // rank update: SVD of Y through its Gram matrix (p x p)
+    CHK(launch_gram(P, p, Y, Y, s));
+    double G[256];
+    CHK(read_dev(P, P->gram, 256, G, s));
+    double A[256], wv[16], Vv[256];
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) A[i * p + j] = G[i * 16 + j];
+    jacobi_eig(p, A, wv, Vv);
+    std::vector<int> idx(p);
+    for (int i = 0; i < p; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return wv[x] > wv[y]; });
+    const double s1 = sqrt(std::max(0.0, wv[idx[0]]));
+    int r = 0;
+    for (int i = 0; i < p; ++i)
+      if (sqrt(std::max(0.0, wv[idx[i]])) > opt->tau_rank * s1) ++r;
+    r = std::max(1, r);
+    const bool neg = lmin < -1e-12 * (1.0 + fabs(lmax));
+    const int dadd = (neg && r + 1 <= opt->p_max) ? 1 : 0;
+    const int pnew = r + dadd;
+    // M = [V_r, 0] (p x pnew)
+    double M[256];
+    for (int i = 0; i < p; ++i)
+      for (int c = 0; c < pnew; ++c) M[i * pnew + c] = (c < r) ? Vv[i * p + idx[c]] : 0.0;
+    MDSDP_HIP(hipMemcpyAsync(P->gpart, M, p * pnew * sizeof(double), hipMemcpyHostToDevice, s));
+    CHK(launch_rightmul(n, p, pnew, Y, P->gpart, true, W.Ynew, s));
+    MDSDP_HIP(hipStreamSynchronize(s));
+    std::swap(Y, W.Ynew);
+    p = pnew;
+    p_maxr = std::max(p_maxr, p);
+    carry = false;
+    if (dadd) {
+      CHK(launch_set_col(n, p, p - 1, evec, W.U, s));
+      carry = true;
+    }
+    // sigma rule, eq. sec5:eq1
+    const double ratio = normR / (1.0 + P->normb);
+    if (ratio < opt->kappa1 * rs.gn)
+      sigma = std::max(sigma / opt->gamma, opt->sigma_min);
+    else if (ratio > opt->kappa2 * rs.gn)
+      sigma = std::min(opt->gamma * sigma, opt->sigma_max);
+  }
+  MDSDP_HIP(hipStreamSynchronize(s));
+  if (Y != Ybuf) MDSDP_HIP(hipMemcpy(Ybuf, Y, (size_t)n * p * sizeof(double), hipMemcpyDeviceToDevice));
+  res->status = final_status;
+  res->outer_iters = k;
+  res->rtr_iters = C.rtr_iters;
+  res->hvps = C.hvps;
+  res->cost_grads = C.cost_grads;
+  res->eig_iters = C.eig_iters;
+  res->p_final = p;
+  res->p_max_reached = p_maxr;
+  res->value = value;
+  res->eta_p = eta[0];
+  res->eta_d = eta[1];
+  res->eta_g = eta[2];
+  res->sigma = sigma;
+  res->seconds = secs(t_start, clk::now());
+  res->t_eval = C.t_eval;
+  res->t_hvp = C.t_hvp;
+  res->t_eig = C.t_eig;
+  res->t_update = C.t_update;
+  return final_status == MDSDP_OK ? MDSDP_OK : MDSDP_ENOCONV;
 }
+
+}  // extern "C"

@@ -122,10 +122,19 @@ class Problem:
         return cls(h)
 
     @classmethod
-    def bqp(cls, Q: np.ndarray, c: np.ndarray, order: int = ORDER_COLEX):
+    def bqp(cls, Q: np.ndarray, c: np.ndarray, order: int = ORDER_COLEX, structured: bool = True):
+        """Order-2 BQP relaxation.  structured=True (colex order) uses the
+        class-map-free class-sum kernels; False goes through the generic
+        class-map path."""
         q = c.size
-        n, _ = bqp_sizes(q)
-        return cls.from_classmap(n, bqp_classmap(q, order), bqp_b(Q, c))
+        if not structured:
+            n, _ = bqp_sizes(q)
+            return cls.from_classmap(n, bqp_classmap(q, order), bqp_b(Q, c))
+        Qc = np.ascontiguousarray(Q, dtype=np.float64)
+        cc = np.ascontiguousarray(c, dtype=np.float64)
+        h = C.c_void_p()
+        call("mdsdp_create_bqp", q, order, _ptr(Qc), _ptr(cc), C.byref(h))
+        return cls(h)
 
     def close(self):
         if self._h:

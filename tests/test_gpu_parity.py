@@ -27,19 +27,19 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _case(q, p, seed=0, sigma=1.7):
+def _case(q, p, seed=0, sigma=1.7, structured=True):
     from paper_2512_04406_amd.problem import ORDER_COLEX, Problem
 
     Q, c = bqp_instance(q, seed)
     rel = bqp.build_relaxation(Q, c, "colex")
-    print(f"[case] q={q} n={rel.n} m={rel.m} p={p} seed={seed}", flush=True)
+    print(f"[case] q={q} n={rel.n} m={rel.m} p={p} seed={seed} structured={structured}", flush=True)
     W = gaussian(rel.n, rel.n, 1000 + seed)
     Xt = Q_op(0.1 * (W + W.T), rel.cls, rel.counts)
     Y = gaussian(rel.n, p, 2000 + seed)
     Y /= np.linalg.norm(Y, axis=1, keepdims=True)
     U = proj_tangent(Y, gaussian(rel.n, p, 3000 + seed))
     sub = Subproblem(rel.cls, rel.counts, rel.b, Xt, sigma)
-    prob = Problem.bqp(Q, c, ORDER_COLEX)
+    prob = Problem.bqp(Q, c, ORDER_COLEX, structured=structured)
     prob.set_multiplier(torch.from_numpy(Xt).cuda(), sigma)
     return rel, sub, prob, Xt, Y, U, sigma
 
@@ -49,8 +49,9 @@ def _t(a):
 
 
 @pytest.mark.parametrize("q,p", CASES)
-def test_cost_grad_parity(q, p):
-    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+@pytest.mark.parametrize("structured", [True, False])
+def test_cost_grad_parity(q, p, structured):
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p, structured=structured)
     f, eg, rg = prob.cost_grad(_t(Y))
     torch.cuda.synchronize()
     f_ref = sub.cost(Y)
@@ -60,10 +61,11 @@ def test_cost_grad_parity(q, p):
 
 
 @pytest.mark.parametrize("q,p", CASES)
-def test_hvp_parity_fp64(q, p):
+@pytest.mark.parametrize("structured", [True, False])
+def test_hvp_parity_fp64(q, p, structured):
     from paper_2512_04406_amd.problem import FP64
 
-    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p, structured=structured)
     Yt, Ut = _t(Y), _t(U)
     prob.cost_grad(Yt)
     Hr = prob.hvp(Yt, Ut, FP64, riemannian=True)
@@ -74,10 +76,11 @@ def test_hvp_parity_fp64(q, p):
 
 
 @pytest.mark.parametrize("q,p", CASES)
-def test_hvp_parity_fp32_tiles(q, p):
+@pytest.mark.parametrize("structured", [True, False])
+def test_hvp_parity_fp32_tiles(q, p, structured):
     from paper_2512_04406_amd.problem import FP32
 
-    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p, structured=structured)
     Yt, Ut = _t(Y), _t(U)
     prob.cost_grad(Yt)
     Hr = prob.hvp(Yt, Ut, FP32, riemannian=True)
@@ -88,16 +91,18 @@ def test_hvp_parity_fp32_tiles(q, p):
 
 
 @pytest.mark.parametrize("q,p", CASES[:6])
-def test_class_average_parity(q, p):
-    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+@pytest.mark.parametrize("structured", [True, False])
+def test_class_average_parity(q, p, structured):
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p, structured=structured)
     y = prob.class_average(_t(Y)).cpu().numpy()
     y_ref = class_average(Y @ Y.T, rel.cls, rel.counts)
     assert np.max(np.abs(y - y_ref)) <= 1e-12
 
 
 @pytest.mark.parametrize("q,p", [(6, 3), (12, 5), (30, 16), (40, 4)])
-def test_update_multiplier_and_certificate_parity(q, p):
-    rel, sub, prob, Xt, Y, U, sigma = _case(q, p)
+@pytest.mark.parametrize("structured", [True, False])
+def test_update_multiplier_and_certificate_parity(q, p, structured):
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p, structured=structured)
     Yt = _t(Y)
     y, z, kkt = prob.update_multiplier(Yt)
     torch.cuda.synchronize()
@@ -126,10 +131,11 @@ def test_update_multiplier_and_certificate_parity(q, p):
     assert _rel(dC, Xt1 + D) <= 1e-13
 
 
-def test_determinism_bitwise():
+@pytest.mark.parametrize("structured", [True, False])
+def test_determinism_bitwise(structured):
     from paper_2512_04406_amd.problem import FP32, FP64
 
-    rel, sub, prob, Xt, Y, U, sigma = _case(30, 16)
+    rel, sub, prob, Xt, Y, U, sigma = _case(30, 16, structured=structured)
     Yt, Ut = _t(Y), _t(U)
     outs = []
     for _ in range(3):
@@ -151,10 +157,11 @@ def test_retract_and_project_parity():
     Y /= np.linalg.norm(Y, axis=1, keepdims=True)
     V = gaussian(n, p, 2)
     out = torch.empty(n, p, dtype=torch.float64, device="cuda")
-    _lib.call("mdsdp_retract", n, p, _ptr(_t(Y)), _ptr(_t(V)), 0.3, _ptr(out), _stream())
+    Yt, Vt = _t(Y), _t(V)  # keep the device buffers alive across the async calls
+    _lib.call("mdsdp_retract", n, p, _ptr(Yt), _ptr(Vt), 0.3, _ptr(out), _stream())
     ref = (Y + 0.3 * V) / np.linalg.norm(Y + 0.3 * V, axis=1, keepdims=True)
     assert _rel(out.cpu().numpy(), ref) <= 1e-14
-    _lib.call("mdsdp_project_tangent", n, p, _ptr(_t(Y)), _ptr(_t(V)), _ptr(out), _stream())
+    _lib.call("mdsdp_project_tangent", n, p, _ptr(Yt), _ptr(Vt), _ptr(out), _stream())
     assert _rel(out.cpu().numpy(), proj_tangent(Y, V)) <= 1e-14
 
 
@@ -182,3 +189,28 @@ def test_nonzero_C_parity():
     assert abs(f.item() - sub.cost(Y)) <= 1e-10 * (1 + abs(sub.cost(Y)))
     assert _rel(rg.cpu().numpy(), sub.rgrad(Y)) <= 1e-10
     assert _rel(H.cpu().numpy(), sub.rhess(Y, U)) <= 1e-10
+
+
+@pytest.mark.parametrize("q,p", [(4, 3), (9, 16), (25, 5)])
+def test_structured_matches_generic_class_sums(q, p):
+    """The class-map-free BQP kernels and the generic fixed-point class map
+    path give the same class averages (both are within rounding of the
+    oracle); HVP class averages compared through the HVP output."""
+    from paper_2512_04406_amd.problem import FP64, ORDER_COLEX, Problem
+
+    Q, c = bqp_instance(q, 8)
+    a = Problem.bqp(Q, c, ORDER_COLEX, structured=True)
+    b = Problem.bqp(Q, c, ORDER_COLEX, structured=False)
+    n = a.n
+    Y = gaussian(n, p, 9)
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    U = gaussian(n, p, 10)
+    Yt, Ut = _t(Y), _t(U)
+    ya, yb = a.class_average(Yt), b.class_average(Yt)
+    torch.cuda.synchronize()
+    assert float((ya - yb).abs().max()) <= 1e-13
+    for P in (a, b):
+        P.cost_grad(Yt)
+    ha, hb = a.hvp(Yt, Ut, FP64), b.hvp(Yt, Ut, FP64)
+    torch.cuda.synchronize()
+    assert float((ha - hb).norm() / hb.norm()) <= 1e-12

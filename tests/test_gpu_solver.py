@@ -1,0 +1,94 @@
+"""GPU end-to-end checks of the outer loop (Algorithm alg1 on the HIP path).
+
+* Lanczos certificate eigenpair vs LAPACK on the dense oracle certificate;
+* full solves (dense BQP, q = 10, p0 = 2, FP64 and FP32-tile HVPs): eta_max
+  <= 1e-8, value = brute-force minimum (rank-one case) = oracle value;
+* q = 20: value equals the brute-force minimum, FP64 and mixed agree to 1e-8.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import alm, bqp, brute
+from oracle.operators import D_matrix, Q_op
+from synth import bqp_instance, gaussian
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("q,p", [(6, 2), (12, 4), (20, 3)])
+def test_min_eigpair_matches_dense(q, p):
+    from paper_2512_04406_amd.problem import ORDER_COLEX, Problem
+
+    Q, c = bqp_instance(q, 1)
+    rel = bqp.build_relaxation(Q, c, "colex")
+    print(f"[eig] q={q} n={rel.n}", flush=True)
+    W = gaussian(rel.n, rel.n, 5)
+    Xt = Q_op(0.2 * (W + W.T), rel.cls, rel.counts)
+    sigma = 1.3
+    Y = gaussian(rel.n, p, 6)
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    prob = Problem.bqp(Q, c, ORDER_COLEX)
+    prob.set_multiplier(_t(Xt), sigma)
+    Yt = _t(Y)
+    prob.update_multiplier(Yt)
+    Xt1 = Xt + sigma * Q_op(Y @ Y.T, rel.cls, rel.counts)
+    D = D_matrix(rel.b, rel.cls, rel.counts)
+    z = np.einsum("ij,ij->i", (Xt1 + D) @ Y, Y)
+    X = Xt1 + D - np.diag(z)
+    w, V = np.linalg.eigh(X)
+    lmin, lmax, v, it, conv = prob.min_eigpair(tol=1e-11, maxit=min(rel.n, 300))
+    scale = 1 + abs(w[-1])
+    assert conv
+    assert abs(lmin - w[0]) <= 1e-9 * scale
+    assert abs(lmax - w[-1]) <= 1e-9 * scale
+    vv = v.cpu().numpy()
+    if w[1] - w[0] > 1e-3 * scale:
+        assert abs(abs(vv @ V[:, 0]) - 1.0) <= 1e-8
+
+
+def _solve(q, seed, prec, p0=2, tol=1e-8):
+    from paper_2512_04406_amd.problem import ORDER_COLEX, Problem
+
+    Q, c = bqp_instance(q, seed)
+    prob = Problem.bqp(Q, c, ORDER_COLEX)
+    opts = prob.default_options()
+    opts.tol = tol
+    opts.hvp_prec = prec
+    opts.p_max = 16
+    n = prob.n
+    Y0 = gaussian(n, p0, 100 + seed)
+    print(f"[solve] q={q} seed={seed} prec={prec} n={n}", flush=True)
+    res = prob.solve(_t(Y0), opts)
+    print(f"   value={res.value:.10f} eta={res.eta} outer={res.outer_iters} hvps={res.hvps} p={res.p_final} "
+          f"t={res.seconds:.2f}s", flush=True)
+    return Q, c, res
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_q10_matches_brute_force(seed, prec):
+    Q, c, res = _solve(10, seed, prec)
+    fmin, _ = brute.brute_force_min(Q, c)
+    assert res.status == 0
+    assert max(res.eta) <= 1e-8
+    assert abs(res.value - fmin) <= 1e-8 * (1 + abs(fmin))
+    # independent certificate from the oracle on the returned iterate
+    rel = bqp.build_relaxation(Q, c, "colex")
+    orc = alm.solve(rel.cls, rel.counts, rel.b, gaussian(rel.n, 2, 100 + seed))
+    assert abs(res.value - orc.value) <= 1e-8 * (1 + abs(orc.value))
+
+
+def test_solve_q20_fp64_and_mixed_agree_with_brute_force():
+    Q, c, r64 = _solve(20, 0, 0)
+    _, _, r32 = _solve(20, 0, 1)
+    fmin, _ = brute.brute_force_min(Q, c)
+    for r in (r64, r32):
+        assert r.status == 0 and max(r.eta) <= 1e-8
+        assert abs(r.value - fmin) <= 1e-8 * (1 + abs(fmin))
+    assert abs(r64.value - r32.value) <= 1e-8 * (1 + abs(fmin))
