@@ -142,7 +142,14 @@ def main() -> int:
     alg = _alg_bytes_hvp_resid(ne, m, hvp_prec == FP32)
     achieved = alg / resid_s / 1e9
     if args.profile_hvp_only:
-        print(json.dumps({"hvp_us": hvp_dt * 1e6, "kernels_us": kern_us}))
+        # calibration for HBM byte counters: a plain device copy of 256 MiB
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"hvp_us": hvp_dt * 1e6, "kernels_us": kern_us, "copy_bytes_each_way": src.numel() * 8,
+                          "alg_bytes_resid": alg, "ne": ne, "m": m}))
         return 0
 
     # ---- time to KKT <= 1e-8 (the timed steps) ----
