@@ -1,19 +1,21 @@
 #!/usr/bin/env python3
-"""Benchmark of the ManiDSDP subproblem hot path on one MI355X.
+"""Benchmark of the ManiDSDP hot path on one MI355X.
 
 Workload: dense BQP, q = 100 (n = 5051, m = 4,087,976 classes), Q symmetric
-with iid N(0,1) off-diagonal entries and zero diagonal, c iid N(0,1), seed 0;
-order-2 moment relaxation; Burer-Monteiro rank p = 16.  Synthetic data.
+with iid N(0,1) off-diagonal entries and zero diagonal, c iid N(0,1) (seed 0);
+order-2 moment relaxation, colex basis; Burer-Monteiro start p0 = 16
+(= ceil(ln m)).  Synthetic data, resident in HBM before any timed region.
 
-A step is one full run of Algorithm alg1 (ManiDSDP) to eta_max <= 1e-8:
-cost/gradient passes, truncated-CG HVPs, retractions, multiplier updates,
-certificate eigensolves and KKT residuals, all on the GPU.  The timed region
-is `--steps` such solves from seeded starts (inputs resident in HBM).
-`value` = HVPs per second over the timed region (metric: HVPs/s and time to
-KKT <= 1e-8); `time_to_kkt_s` is the mean solve time.  Also reported:
-isolated Riemannian HVP throughput at a fixed point, the roofline of the
-dominant kernel (HIP events on its launch stream), the FP64 plain-path solve
-for the mixed-vs-FP64 speedup, and the FP64 oracle timed on the host CPU.
+A step is one outer iteration of Algorithm alg1: the RTR subproblem solve
+(cost/gradient passes, truncated-CG HVPs, retractions), the multiplier update,
+the Lanczos certificate eigensolve, the KKT residuals and the rank/sigma
+updates.  `--warmup` outer iterations run first (untimed), then `--steps`
+outer iterations continue the same run (timed).  `value` = HVPs per second
+over the timed steps.  Also reported: the isolated Riemannian HVP throughput
+at a fixed point (FP32 tiles and FP64), the roofline of the dominant kernel
+(HIP events on its launch stream), the time to eta_max <= 1e-8 of a capped
+full solve in mixed precision and in FP64, and the FP64 oracle timed on the
+host CPU on a bounded sample.
 """
 
 from __future__ import annotations
@@ -34,9 +36,9 @@ HBM_PEAK_GBS = 8000.0
 def _alg_bytes_hvp_resid(ne: int, m: int, fp32: bool) -> float:
     """Algorithmic HBM bytes of one HVP residual/product pass: the class id
     (4 B) and the multiplier (8 B FP64 or 4 B FP32 shadow) of every packed
-    entry, plus the class coefficient and the HVP class average of every class
-    (2 x 8 B), each read once."""
-    return ne * (4 + (4 if fp32 else 8)) + 16.0 * m
+    entry, plus the {D, y} pair and the HVP class average of every class
+    (3 x 8 B), each read once."""
+    return ne * (4 + (4 if fp32 else 8)) + 24.0 * m
 
 
 def cpu_baseline(q: int, p: int, budget_s: float) -> dict:
@@ -75,22 +77,24 @@ def cpu_baseline(q: int, p: int, budget_s: float) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed outer iterations")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed outer iterations before the timed ones")
     ap.add_argument("--q", type=int, default=100)
-    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--p", type=int, default=16, help="factor width of the isolated HVP and start rank p0")
+    ap.add_argument("--p-max", type=int, default=0, help="rank cap of the solver (0 = library default)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
-    ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--hvp-iters", type=int, default=200)
+    ap.add_argument("--kkt-time-limit-s", type=float, default=90.0,
+                    help="cap of each full time-to-KKT solve (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
-    ap.add_argument("--time-limit-s", type=float, default=600.0)
     ap.add_argument("--profile-hvp-only", action="store_true",
                     help="only the isolated HVP loop (for rocprofv3 runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (no collectives); use --gpus 1", file=sys.stderr)
+        print("bench.py: this implementation runs on exactly one GPU (no collectives); use --gpus 1",
+              file=sys.stderr)
         return 2
 
     import numpy as np
@@ -107,6 +111,7 @@ def main() -> int:
     n, m = prob.n, prob.m
     ne = n * (n + 1) // 2
     hvp_prec = FP32 if args.prec == "mixed" else FP64
+    print(f"[bench] q={q} n={n} m={m} p={p} prec={args.prec}", file=sys.stderr, flush=True)
 
     # ---- isolated HVP throughput at a fixed point (realistic multiplier) ----
     Y = torch.from_numpy(gaussian(n, p, 1)).to(dev)
@@ -119,14 +124,19 @@ def main() -> int:
         prob.update_multiplier(Yk)
     prob.cost_grad(Y)
     HU = torch.empty_like(U)
-    for _ in range(10):
-        prob.hvp(Y, U, hvp_prec, out=HU)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.hvp_iters):
-        prob.hvp(Y, U, hvp_prec, out=HU)
-    torch.cuda.synchronize()
-    hvp_dt = (time.perf_counter() - t0) / args.hvp_iters
+
+    def hvp_rate(prec):
+        for _ in range(10):
+            prob.hvp(Y, U, prec, out=HU)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.hvp_iters):
+            prob.hvp(Y, U, prec, out=HU)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.hvp_iters
+
+    hvp_dt = hvp_rate(hvp_prec)
+    hvp64_dt = hvp_rate(FP64) if hvp_prec != FP64 else hvp_dt
     # per-kernel durations with HIP events on the launch stream
     prob.enable_timing(True)
     for _ in range(20):
@@ -141,6 +151,8 @@ def main() -> int:
     resid_s = kern_us.get(resid_name, float("nan")) * 1e-6
     alg = _alg_bytes_hvp_resid(ne, m, hvp_prec == FP32)
     achieved = alg / resid_s / 1e9
+    print(f"[bench] isolated HVP {hvp_dt * 1e6:.1f} us ({args.prec}), {hvp64_dt * 1e6:.1f} us (fp64)",
+          file=sys.stderr, flush=True)
     if args.profile_hvp_only:
         # calibration for HBM byte counters: a plain device copy of 256 MiB
         src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
@@ -152,58 +164,69 @@ def main() -> int:
                           "alg_bytes_resid": alg, "ne": ne, "m": m}))
         return 0
 
-    # ---- time to KKT <= 1e-8 (the timed steps) ----
-    def one_solve(seed: int, prec: int):
-        opts = prob.default_options()
-        opts.hvp_prec = prec
-        opts.p_max = p
-        opts.time_limit_s = args.time_limit_s
-        Y0 = torch.from_numpy(gaussian(n, p, 100 + seed)).to(dev)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        r = prob.solve(Y0, opts)
-        torch.cuda.synchronize()
-        return r, time.perf_counter() - t
+    def options(prec, **kw):
+        o = prob.default_options()
+        o.hvp_prec = prec
+        if args.p_max > 0:
+            o.p_max = args.p_max
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
 
-    for w in range(args.warmup):
-        one_solve(1000 + w, hvp_prec)
+    Y0 = torch.from_numpy(gaussian(n, p, 100 + args.seed)).to(dev)
+
+    # ---- steps: outer iterations of Algorithm alg1 ----
+    r_w = prob.solve(Y0, options(hvp_prec, max_outer=max(1, args.warmup)))
     torch.cuda.synchronize()
+    print(f"[bench] warmup done: {r_w.outer_iters} outer, eta={max(r_w.eta):.2e}", file=sys.stderr, flush=True)
     t_start = time.perf_counter()
-    runs = [one_solve(args.seed + k, hvp_prec) for k in range(args.steps)]
+    r_t = prob.solve(r_w.Y.contiguous(), options(hvp_prec, max_outer=args.steps, resume=1, sigma0=r_w.sigma))
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-    hvps = sum(r.hvps for r, _ in runs)
-    converged = all(r.status == 0 for r, _ in runs)
-    fp64_info = None
-    if not args.no_fp64_compare and hvp_prec != FP64:
-        r64, t64 = one_solve(args.seed, FP64)
-        fp64_info = {"time_to_kkt_s": t64, "status": r64.status, "value": r64.value, "eta_max": max(r64.eta),
-                     "hvps": r64.hvps, "speedup_mixed_vs_fp64": t64 / runs[0][1]}
-    r0 = runs[0][0]
+    steps_done = r_t.outer_iters
+    print(f"[bench] timed {steps_done} outer iterations in {total:.2f} s, {r_t.hvps} HVPs, "
+          f"eta={max(r_t.eta):.2e}", file=sys.stderr, flush=True)
+
+    # ---- time to eta_max <= 1e-8 (capped full solves) ----
+    kkt = None
+    if args.kkt_time_limit_s > 0:
+        kkt = {}
+        for name, prec in (("mixed", FP32), ("fp64", FP64)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = prob.solve(Y0, options(prec, time_limit_s=args.kkt_time_limit_s))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            kkt[name] = {"converged": r.status == 0, "seconds": dt, "eta_max": max(r.eta), "value": r.value,
+                         "outer_iters": r.outer_iters, "hvps": r.hvps, "p_final": r.p_final,
+                         "p_max_reached": r.p_max_reached, "time_cap_s": args.kkt_time_limit_s}
+            print(f"[bench] time-to-KKT {name}: {dt:.1f} s converged={r.status == 0} eta={max(r.eta):.2e}",
+                  file=sys.stderr, flush=True)
+        if kkt["mixed"]["converged"] and kkt["fp64"]["converged"]:
+            kkt["speedup_mixed_vs_fp64"] = kkt["fp64"]["seconds"] / kkt["mixed"]["seconds"]
+
     out = {
         "metric": "HVPs/s + time to KKT<=1e-8, mixed vs FP64, dense BQP q=100 (n=5051)",
-        "value": hvps / total,
+        "value": r_t.hvps / total,
         "unit": "HVP/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * total / args.steps,
+        "steps": steps_done,
+        "warmup": r_w.outer_iters,
+        "ms_per_step": 1e3 * total / max(1, steps_done),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 tiles (HVP) + f64 (class sums, gradients, multiplier, KKT)" if hvp_prec == FP32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"dense BQP q={q} n={n} m={m} p<={p}, Q,c ~ N(0,1) seed {args.seed}, "
-                               "order-2 moment relaxation, ManiDSDP to eta_max<=1e-8",
+        "config": {"workload": f"dense BQP q={q} n={n} m={m}, Q,c ~ N(0,1) seed {args.seed}, order-2 moment "
+                               f"relaxation, ManiDSDP outer iterations from p0={p}",
                    "global_batch": 1, "seq_len": n, "parallelism": "single GPU"},
-        "time_to_kkt_s": total / args.steps,
-        "converged": converged,
-        "solve": {"value": r0.value, "eta": list(r0.eta), "outer_iters": r0.outer_iters, "rtr_iters": r0.rtr_iters,
-                  "hvps": r0.hvps, "cost_grads": r0.cost_grads, "eig_iters": r0.eig_iters,
-                  "p_final": r0.p_final, "p_max_reached": r0.p_max_reached, "phases_s": r0.phases},
-        "fp64_plain": fp64_info,
+        "timed_steps": {"hvps": r_t.hvps, "seconds": total, "eta_max_after": max(r_t.eta), "p_final": r_t.p_final,
+                        "sigma": r_t.sigma, "phases_s": r_t.phases},
+        "time_to_kkt": kkt,
         "hvp_isolated_per_s": 1.0 / hvp_dt,
         "hvp_isolated_us": hvp_dt * 1e6,
+        "hvp_fp64_isolated_us": hvp64_dt * 1e6,
         "hvp_kernels_us": kern_us,
         "roofline": {"bound": "hbm", "kernel": resid_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,

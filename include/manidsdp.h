@@ -178,9 +178,13 @@ typedef struct {
   double tol;          /* stop when eta_max <= tol (eq. res); default 1e-8 */
   int32_t max_outer;   /* default 200 */
   double sigma0, sigma_min, sigma_max, gamma, kappa1, kappa2; /* eq. sec5:eq1 */
-  int32_t p_max;       /* <= 16 */
+  int32_t p_max;       /* largest factor width, 1..64 */
+  int32_t n_neg;       /* negative-curvature directions added per outer step (Theorem sec5:thm1) */
   double tau_rank;     /* drop singular directions below tau_rank * s_1 */
-  double gtol0, gtol_min;  /* inner tolerance max(gtol_min, min(gtol0, 0.1 eta)) */
+  double gtol0, gtol_min;  /* inner tolerance max(gtol_min, min(gtol0, 0.1 eta, gtol_decay * previous)) */
+  double gtol_decay;   /* in (0, 1]; 1 = tolerance follows eta alone */
+  double gtol_ratio;   /* > 0: also cap the tolerance at gtol_ratio ||R|| / (1 + ||b||), the primal
+                          measure of the sigma rule (eq. sec5:eq1); <= 0: no such cap */
   int32_t rtr_maxiter, tcg_maxinner;
   int32_t hvp_prec;    /* mdsdp_prec for tCG HVPs */
   int32_t polish_fp64; /* switch HVPs to FP64 once eta_max < polish_eta */
@@ -188,8 +192,10 @@ typedef struct {
   double eig_tol;
   int32_t eig_maxit;
   double time_limit_s; /* 0 = none */
-  int32_t verbose;
+  int32_t verbose;     /* 0 quiet; 1 one stderr line per outer iteration; 2 also one per RTR step */
   uint64_t seed;
+  int32_t resume;      /* 0: start from Xt = 0, sigma = sigma0; 1: continue from the problem's current
+                          multiplier Xt with sigma = sigma0 (e.g. the sigma a previous solve returned) */
 } mdsdp_options;
 
 typedef struct {

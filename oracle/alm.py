@@ -24,7 +24,10 @@ Readings of points the paper leaves open (each also listed in the design doc):
   after each subproblem, drop singular directions of Y below tau_rank * s_1
   (Y <- Y V_r, rows renormalised), then append one zero column per carried
   eigenvector (at most n_neg of them, p <= p_max).
-* inner tolerance: RTR stops at ||grad|| <= max(gtol_min, min(gtol0, 0.1 eta_max^k)).
+* inner tolerance: RTR stops at ||grad|| <= max(gtol_min, min(gtol0, 0.1 eta_max^k,
+  gtol_decay * previous tolerance, gtol_ratio ||R^k|| / (1 + ||b||))); the decay keeps
+  the tolerances of an inexact ALM going to zero when the residuals stall, the
+  ratio term ties the tolerance to the primal measure of the sigma rule.
 * sigma constants: sigma_0 = 1, sigma_min = 1e-3, sigma_max = 1e6, gamma = 2,
   kappa_1 = 0.1, kappa_2 = 10 (the paper states none).
 * eigenvector sign: the largest-magnitude component is made positive.
@@ -59,10 +62,12 @@ class ALMOptions:
     kappa1: float = 0.1
     kappa2: float = 10.0
     p_max: int = 64
-    n_neg: int = 1
+    n_neg: int = 4
     tau_rank: float = 1e-4
     gtol0: float = 1e-2
     gtol_min: float = 1e-10
+    gtol_decay: float = 1.0
+    gtol_ratio: float = 0.0
     rtr_maxiter: int = 50
     neg_tol: float = 1e-12
 
@@ -123,6 +128,8 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
     D = D_matrix(b, cls, counts)
     U = None
     eta_max = 1.0
+    gtol = opts.gtol0 / opts.gtol_decay
+    prim_ratio = None
     hist = []
     normb = float(np.linalg.norm(b))
     y = z = X = None
@@ -131,7 +138,10 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
         sub = Subproblem(cls, counts, b, Xt, sigma, C)
         if U is not None:
             Y = _escape(sub, Y, U)
-        gtol = max(opts.gtol_min, min(opts.gtol0, 0.1 * eta_max))
+        g = min(opts.gtol0, 0.1 * eta_max, opts.gtol_decay * gtol)
+        if opts.gtol_ratio > 0.0 and prim_ratio is not None:
+            g = min(g, opts.gtol_ratio * prim_ratio)
+        gtol = max(opts.gtol_min, g)
         res = rtr(sub, Y, gtol, maxiter=opts.rtr_maxiter)
         Y = res.Y
         S = Y @ Y.T
@@ -171,6 +181,7 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
             U = None
         # sigma rule, eq. sec5:eq1
         ratio = float(np.linalg.norm(Rq)) / (1.0 + normb)
+        prim_ratio = ratio
         if ratio < opts.kappa1 * res.gradnorm:
             sigma = max(sigma / opts.gamma, opts.sigma_min)
         elif ratio > opts.kappa2 * res.gradnorm:

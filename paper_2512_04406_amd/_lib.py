@@ -29,10 +29,12 @@ class MdsdpError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("tol", _f64), ("max_outer", _i32), ("sigma0", _f64), ("sigma_min", _f64),
                 ("sigma_max", _f64), ("gamma", _f64), ("kappa1", _f64), ("kappa2", _f64),
-                ("p_max", _i32), ("tau_rank", _f64), ("gtol0", _f64), ("gtol_min", _f64),
+                ("p_max", _i32), ("n_neg", _i32), ("tau_rank", _f64), ("gtol0", _f64), ("gtol_min", _f64),
+                ("gtol_decay", _f64), ("gtol_ratio", _f64),
                 ("rtr_maxiter", _i32), ("tcg_maxinner", _i32), ("hvp_prec", _i32),
                 ("polish_fp64", _i32), ("polish_eta", _f64), ("eig_tol", _f64), ("eig_maxit", _i32),
-                ("time_limit_s", _f64), ("verbose", _i32), ("seed", _u64)]
+                ("time_limit_s", _f64), ("verbose", _i32), ("seed", _u64),
+                ("resume", _i32)]
 
 
 class Result(C.Structure):

@@ -307,24 +307,23 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   TRY(dalloc(&P->bvec, m));
   TRY(dalloc(&P->sacc, m));
   if (C) TRY(dalloc(&P->Cavg, m));
-  TRY(dalloc((double**)&P->Yp, (size_t)P->npad * 16));
-  TRY(dalloc((double**)&P->Up, (size_t)P->npad * 16));
+  TRY(dalloc((double**)&P->Yp, (size_t)P->npad * PMAX));
+  TRY(dalloc((double**)&P->Up, (size_t)P->npad * PMAX));
   TRY(dalloc(&P->zvec, n));
   TRY(dalloc(&P->zmult, n));
-  TRY(dalloc(&P->rowpart, (size_t)P->ntiles * 64 * 16));
-  TRY(dalloc(&P->colpart, (size_t)P->nseg * 64 * 16));
+  TRY(dalloc(&P->rowpart, (size_t)P->ntiles * 64 * PMAX));
+  TRY(dalloc(&P->colpart, (size_t)P->nseg * 64 * PMAX));
   TRY(dalloc(&P->wgpart, (size_t)P->nseg * 4));
-  TRY(dalloc(&P->zpart, (size_t)(n * 16 + 255) / 256 + 1));
-  TRY(dalloc(&P->gram, 512));
-  TRY(dalloc(&P->gpart, std::max((size_t)((n + 63) / 64) * 512, (size_t)8192)));
+  TRY(dalloc(&P->zpart, (size_t)(n * PMAX + 255) / 256 + 1));
+  TRY(dalloc(&P->gram, 8192));
+  TRY(dalloc(&P->gpart, GP_SIZE));
   TRY(dalloc(&P->scal, SC_COUNT));
   TRY(dalloc(&P->bound, 2));
   P->dot_nblk = 256;
   TRY(dalloc(&P->dotpart, (size_t)P->dot_nblk * 8));
   TRY(dalloc((double**)&P->dotptr, 16));
-  TRY(dalloc(&P->work, (size_t)n * 16 * 12));
   {
-    hipError_t eh = hipHostMalloc((void**)&P->hbuf, 1024 * sizeof(double), hipHostMallocDefault);
+    hipError_t eh = hipHostMalloc((void**)&P->hbuf, 8192 * sizeof(double), hipHostMallocDefault);
     if (eh != hipSuccess) {
       mdsdp_status s2 = hip_fail(eh, "hipHostMalloc");
       free_problem(P);
@@ -368,8 +367,8 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
 
 static mdsdp_status check_p(mdsdp_problem P, int p) {
   if (!P) return einval("problem is NULL");
-  if (p < 1 || p > 16) {
-    set_error("p must be in [1, 16]");
+  if (p < 1 || p > PMAX) {
+    set_error("p must be in [1, 64]");
     return p < 1 ? MDSDP_EINVAL : MDSDP_EUNSUPPORTED;
   }
   return MDSDP_OK;

@@ -115,47 +115,45 @@ __device__ __forceinline__ int seg_of_block(int b, int per, int nseg) {
   return s < nseg ? s : -1;
 }
 
-template <typename T>
+// 64 rows of a staged factor (row pitch PW) into LDS (row pitch PW + 1)
+template <int PW, typename T>
 __device__ __forceinline__ void load_rows(T* sdst, const T* src, int row0, int tid) {
-  // 64 rows x 16 cols, padded source (npad x 16), LDS pitch LP
-  for (int i = tid; i < 64 * 16; i += 256) {
-    int r = i >> 4, c = i & 15;
-    sdst[r * LP + c] = src[(size_t)(row0 + r) * 16 + c];
+  for (int i = tid; i < 64 * PW; i += 256) {
+    const int r = i / PW, c = i % PW;
+    sdst[r * (PW + 1) + c] = src[(size_t)(row0 + r) * PW + c];
   }
 }
 
 // ---------------------------------------------------------------------------
-// staging: FP64 n x p (ld = p) -> padded npad x 16 in T; max row norms
+// staging: FP64 n x p (ld = p) -> zero-padded npad x pw in T; max row norms
+// (the latter only for the fixed-point class sums of generic class maps)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_stage(int n, int p, int npad, const double* __restrict__ Y,
+__global__ __launch_bounds__(256) void k_stage(int n, int p, int npad, int pw, const double* __restrict__ Y,
                                                const double* __restrict__ U, T* __restrict__ Yp,
                                                T* __restrict__ Up, unsigned long long* bound) {
-  __shared__ double smax[2][16];
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  int r = idx >> 4, c = idx & 15;
-  bool in = idx < npad * 16;
-  double y = (in && r < n && c < p) ? Y[(size_t)r * p + c] : 0.0;
-  double u = (U && in && r < n && c < p) ? U[(size_t)r * p + c] : 0.0;
+  __shared__ double smax[2][256];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = idx / pw, c = idx % pw;
+  const bool in = idx < npad * pw;
+  const double y = (in && r < n && c < p) ? Y[(size_t)r * p + c] : 0.0;
+  const double u = (U && in && r < n && c < p) ? U[(size_t)r * p + c] : 0.0;
   if (in) {
     Yp[idx] = (T)y;
     if (U) Up[idx] = (T)u;
   }
+  if (!bound) return;
   double ny = y * y, nu = u * u;
-#pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) {
-    ny += __shfl_xor(ny, off, 16);
-    nu += __shfl_xor(nu, off, 16);
+  for (int off = pw >> 1; off >= 1; off >>= 1) {
+    ny += __shfl_xor(ny, off, pw);
+    nu += __shfl_xor(nu, off, pw);
   }
-  if (!bound) return;  // row-norm bound only needed by the fixed-point class sums
-  if (c == 0) {
-    smax[0][threadIdx.x >> 4] = (in && r < n) ? sqrt(ny) : 0.0;
-    smax[1][threadIdx.x >> 4] = (in && r < n) ? sqrt(nu) : 0.0;
-  }
+  smax[0][threadIdx.x] = (in && r < n) ? sqrt(ny) : 0.0;
+  smax[1][threadIdx.x] = (in && r < n) ? sqrt(nu) : 0.0;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m0 = 0.0, m1 = 0.0;
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < 256; i += pw) {
       m0 = fmax(m0, smax[0][i]);
       m1 = fmax(m1, smax[1][i]);
     }
@@ -167,43 +165,36 @@ __global__ __launch_bounds__(256) void k_stage(int n, int p, int npad, const dou
 // ---------------------------------------------------------------------------
 // class sums
 // ---------------------------------------------------------------------------
-template <typename T, bool ZMODE>
+template <typename T, bool ZMODE, int PW>
 __global__ __launch_bounds__(256) void k_classsum(KArgs a) {
   typedef typename V4<T>::type v4;
+  constexpr int NK = PW / 4;
   const int sidx = seg_of_block(blockIdx.x, a.seg_per_xcd, a.nseg);
   if (sidx < 0) return;
   const Seg sg = a.segs[sidx];
-  __shared__ T sYc[64 * LP], sYr[64 * LP];
-  __shared__ T sUc[ZMODE ? 64 * LP : 1], sUr[ZMODE ? 64 * LP : 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const T* Yp = (const T*)a.Yp;
   const T* Up = (const T*)a.Up;
-  load_rows(sYc, Yp, sg.J * 64, tid);
-  if (ZMODE) load_rows(sUc, Up, sg.J * 64, tid);
   const double ymax = bound_val(a.bound, 0);
   const double scale = ZMODE ? fx_scale(a.kmax, 2.0 * ymax * bound_val(a.bound, 1))
                              : fx_scale(a.kmax, ymax * ymax);
   if (sidx == 0 && tid == 0) a.scal[ZMODE ? SC_SCALE_Z : SC_SCALE_S] = scale;
   long long* acc_t = a.sacc;
   const int li = lane & 15, lk = lane >> 4;
+  const int nk = min(NK, a.nk);
   for (int I = sg.I0; I <= sg.I1; ++I) {
-    __syncthreads();
-    load_rows(sYr, Yp, I * 64, tid);
-    if (ZMODE) load_rows(sUr, Up, I * 64, tid);
-    __syncthreads();
     const long long t = (long long)sg.J * (sg.J + 1) / 2 + I;
     const double wgt = (I == sg.J) ? 1.0 : 2.0;
+    const size_t ra = (size_t)(I * 64 + w * 16 + li) * PW;
     for (int sc = 0; sc < 4; ++sc) {
+      const size_t rb = (size_t)(sg.J * 64 + sc * 16 + li) * PW;
       v4 acc = {0, 0, 0, 0};
-      for (int j = 0; j < a.nk; ++j) {
+      for (int j = 0; j < nk; ++j) {
         const int k = 4 * j + lk;
-        T ya = sYr[(w * 16 + li) * LP + k];
-        T yb = sYc[(sc * 16 + li) * LP + k];
+        const T ya = Yp[ra + k], yb = Yp[rb + k];
         if (ZMODE) {
-          T ub = sUc[(sc * 16 + li) * LP + k];
-          T ua = sUr[(w * 16 + li) * LP + k];
-          acc = mfma(ya, ub, acc);
-          acc = mfma(ua, yb, acc);
+          acc = mfma(ya, Up[rb + k], acc);
+          acc = mfma(Up[ra + k], yb, acc);
         } else {
           acc = mfma(ya, yb, acc);
         }
@@ -211,10 +202,10 @@ __global__ __launch_bounds__(256) void k_classsum(KArgs a) {
       const uint32_t* cb = a.cls + t * TSLOTS + (w * 4 + sc) * 256 + li;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        uint32_t cw = cb[drow<T>(lk, v) * 16];
+        const uint32_t cw = cb[drow<T>(lk, v) * 16];
         if (!(cw & 0x80000000u)) {
-          uint32_t id = cw & CLS_MASK;
-          long long qv = llrint(wgt * (double)acc[v] * scale);
+          const uint32_t id = cw & CLS_MASK;
+          const long long qv = llrint(wgt * (double)acc[v] * scale);
           atomicAdd((unsigned long long*)&acc_t[id], (unsigned long long)qv);
         }
       }
@@ -225,21 +216,51 @@ __global__ __launch_bounds__(256) void k_classsum(KArgs a) {
 // ---------------------------------------------------------------------------
 // residual / product pass
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T, int MODE, int PW>
+struct ResidLds {
+  static constexpr bool NEED_Y = (MODE != M_XMV);
+  static constexpr bool SEPARATE_U = (MODE == M_HVP || MODE == M_XMV);
+  static constexpr bool HAS_B = (MODE == M_HVP);
+  static constexpr int LPW = PW + 1;
+  static constexpr size_t slab = 64 * LPW;  // one 64-row slice
+  static constexpr size_t nslab = (NEED_Y ? 2 : 0) + (SEPARATE_U ? 2 : 0);
+  static constexpr size_t tbuf = 16 * LP;    // one 16 x 16 transpose buffer
+  static constexpr size_t bytes = (nslab * slab + (HAS_B ? 8 : 4) * tbuf) * sizeof(T) + 256 * sizeof(double);
+};
+
+template <typename T, int MODE, int PW>
 __global__ __launch_bounds__(256) void k_resid(KArgs a) {
   typedef typename V4<T>::type v4;
+  typedef ResidLds<T, MODE, PW> L;
   constexpr bool HAS_S = (MODE == M_GRAD || MODE == M_MULT || (MODE == M_HVP && sizeof(T) == 4));
-  constexpr bool HAS_B = (MODE == M_HVP);
-  constexpr bool SEPARATE_U = (MODE == M_HVP || MODE == M_XMV);
-  constexpr bool NEED_Y = (MODE != M_XMV);
+  constexpr bool HAS_B = L::HAS_B;
+  constexpr bool SEPARATE_U = L::SEPARATE_U;
+  constexpr bool NEED_Y = L::NEED_Y;
+  constexpr int NC = PW / 16, LPW = L::LPW;
   const int sidx = seg_of_block(blockIdx.x, a.seg_per_xcd, a.nseg);
   if (sidx < 0) return;
   const Seg sg = a.segs[sidx];
-  __shared__ T sYc[NEED_Y ? 64 * LP : 1], sYr[NEED_Y ? 64 * LP : 1];
-  __shared__ T sUc[SEPARATE_U ? 64 * LP : 1], sUr[SEPARATE_U ? 64 * LP : 1];
-  __shared__ T tA[4][16 * LP];
-  __shared__ T tB[HAS_B ? 4 : 1][HAS_B ? 16 * LP : 1];
-  __shared__ double red[256];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* red = (double*)smem_raw;
+  T* sp = (T*)(smem_raw + 256 * sizeof(double));
+  T* sYc = nullptr;
+  T* sYr = nullptr;
+  T* sUc = nullptr;
+  T* sUr = nullptr;
+  if (NEED_Y) {
+    sYc = sp;
+    sp += L::slab;
+    sYr = sp;
+    sp += L::slab;
+  }
+  if (SEPARATE_U) {
+    sUc = sp;
+    sp += L::slab;
+    sUr = sp;
+    sp += L::slab;
+  }
+  T* tA = sp;                               // 4 waves x (16 x LP)
+  T* tB = HAS_B ? sp + 4 * L::tbuf : sp;    // 4 more for the B coefficients
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const T* Yp = (const T*)a.Yp;
@@ -248,26 +269,31 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
   const T* rY = sYr;
   const T* cU = SEPARATE_U ? sUc : sYc;
   const T* rU = SEPARATE_U ? sUr : sYr;
-  if (NEED_Y) load_rows(sYc, Yp, sg.J * 64, tid);
-  if (SEPARATE_U) load_rows(sUc, Up, sg.J * 64, tid);
+  if (NEED_Y) load_rows<PW>(sYc, Yp, sg.J * 64, tid);
+  if (SEPARATE_U) load_rows<PW>(sUc, Up, sg.J * 64, tid);
 
   const double sigma = a.sigma;
-  v4 accC[4];
+  const int nk = min(PW / 4, a.nk);
+  v4 accC[4][NC];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) accC[i] = v4{0, 0, 0, 0};
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) accC[i][c] = v4{0, 0, 0, 0};
   double p_r2 = 0.0, p_xz = 0.0, p_cx = 0.0;
-  T* tAw = tA[w];
-  T* tBw = HAS_B ? tB[w] : tA[w];
+  T* tAw = tA + w * L::tbuf;
+  T* tBw = tB + w * L::tbuf;
 
   for (int I = sg.I0; I <= sg.I1; ++I) {
     __syncthreads();
-    if (NEED_Y) load_rows(sYr, Yp, I * 64, tid);
-    if (SEPARATE_U) load_rows(sUr, Up, I * 64, tid);
+    if (NEED_Y) load_rows<PW>(sYr, Yp, I * 64, tid);
+    if (SEPARATE_U) load_rows<PW>(sUr, Up, I * 64, tid);
     __syncthreads();
     const long long t = (long long)sg.J * (sg.J + 1) / 2 + I;
     const bool diag = (I == sg.J);
     const double wgt = diag ? 1.0 : 2.0;
-    v4 accR = {0, 0, 0, 0};
+    v4 accR[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) accR[c] = v4{0, 0, 0, 0};
     // ---- batched memory phase for this wave's 16 x 64 slab of the tile ----
     typedef typename std::conditional<sizeof(T) == 8 || MODE != M_HVP, double, float>::type XT;
     const size_t tb = (size_t)t * TSLOTS + (size_t)(w * 4) * 256 + li;
@@ -296,15 +322,15 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
         dyv[sc][v] = a.cy[id];
         if (MODE == M_HVP) yzv[sc][v] = a.yp[id];
       }
-    // S blocks of the four sub-blocks (MFMA from LDS)
+    // S blocks of the four sub-blocks (MFMA from LDS, K = p)
     v4 Sbv[4];
 #pragma unroll
     for (int sc = 0; sc < 4; ++sc) {
       Sbv[sc] = v4{0, 0, 0, 0};
       if (HAS_S) {
-        for (int j = 0; j < a.nk; ++j) {
+        for (int j = 0; j < nk; ++j) {
           const int k = 4 * j + lk;
-          Sbv[sc] = mfma(rY[(w * 16 + li) * LP + k], cY[(sc * 16 + li) * LP + k], Sbv[sc]);
+          Sbv[sc] = mfma(rY[(w * 16 + li) * LPW + k], cY[(sc * 16 + li) * LPW + k], Sbv[sc]);
         }
       }
     }
@@ -358,63 +384,71 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
       for (int j = 0; j < 4; ++j) {
         const T a1 = tAw[li * LP + 4 * j + lk];
         const T a2 = tAw[(4 * j + lk) * LP + li];
-        const T uc = cU[(sc * 16 + 4 * j + lk) * LP + li];
-        const T ur = rU[(w * 16 + 4 * j + lk) * LP + li];
-        accR = mfma(a1, uc, accR);
-        if (!diag) accC[sc] = mfma(ur, a2, accC[sc]);
+        T b1 = 0, b2 = 0;
         if (HAS_B) {
-          const T b1 = tBw[li * LP + 4 * j + lk];
-          const T b2 = tBw[(4 * j + lk) * LP + li];
-          const T yc = cY[(sc * 16 + 4 * j + lk) * LP + li];
-          const T yr = rY[(w * 16 + 4 * j + lk) * LP + li];
-          accR = mfma(b1, yc, accR);
-          if (!diag) accC[sc] = mfma(yr, b2, accC[sc]);
+          b1 = tBw[li * LP + 4 * j + lk];
+          b2 = tBw[(4 * j + lk) * LP + li];
+        }
+        const int rc = (sc * 16 + 4 * j + lk) * LPW + li;
+        const int rr = (w * 16 + 4 * j + lk) * LPW + li;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          accR[c] = mfma(a1, cU[rc + 16 * c], accR[c]);
+          if (!diag) accC[sc][c] = mfma(rU[rr + 16 * c], a2, accC[sc][c]);
+          if (HAS_B) {
+            accR[c] = mfma(b1, cY[rc + 16 * c], accR[c]);
+            if (!diag) accC[sc][c] = mfma(rY[rr + 16 * c], b2, accC[sc][c]);
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // row-side partial of this tile: rows w*16 + drow(lk, v), pcol li
-    T* rp = (T*)a.rowpart + ((size_t)t * 64 + w * 16) * 16 + li;
+    // row-side partial of this tile: rows w*16 + drow(lk, v), columns c*16 + li
+    T* rp = (T*)a.rowpart + ((size_t)t * 64 + w * 16) * PW + li;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) rp[drow<T>(lk, v) * 16] = accR[v];
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) rp[drow<T>(lk, v) * PW + 16 * c] = accR[c][v];
   }
-  // column-side partial of the segment: sum the four waves (rows sub-blocks)
-  __syncthreads();
-  T* cred = &tA[0][0];  // reuse: need 4 waves x 4 sc x 256 values -> do sc by sc
-  T* cp = (T*)a.colpart + (size_t)sidx * 64 * 16;
+  // column-side partial of the segment: sum the four waves (row sub-blocks)
+  T* cred = tA;  // 3 x 256 values (the transpose buffers are free now)
+  T* cp = (T*)a.colpart + (size_t)sidx * 64 * PW;
   for (int sc = 0; sc < 4; ++sc) {
-    // accC[sc]: lane (lk, li), v -> pcol drow(lk, v), col li
-    __syncthreads();
-    if (w > 0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) cred[(w - 1) * 256 + drow<T>(lk, v) * 16 + li] = accC[sc][v];
-    }
-    __syncthreads();
-    if (w == 0) {
+    for (int c = 0; c < NC; ++c) {
+      // accC[sc][c]: lane (lk, li), v -> pcol c*16 + drow(lk, v), col li
+      __syncthreads();
+      if (w > 0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int pc = drow<T>(lk, v);
-        T s = accC[sc][v];
-        s += cred[0 * 256 + pc * 16 + li];
-        s += cred[1 * 256 + pc * 16 + li];
-        s += cred[2 * 256 + pc * 16 + li];
-        cp[(sc * 16 + li) * 16 + pc] = s;
+        for (int v = 0; v < 4; ++v) cred[(w - 1) * 256 + drow<T>(lk, v) * 16 + li] = accC[sc][c][v];
+      }
+      __syncthreads();
+      if (w == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int pc = drow<T>(lk, v);
+          T sum = accC[sc][c][v];
+          sum += cred[0 * 256 + pc * 16 + li];
+          sum += cred[1 * 256 + pc * 16 + li];
+          sum += cred[2 * 256 + pc * 16 + li];
+          cp[(sc * 16 + li) * PW + c * 16 + pc] = sum;
+        }
       }
     }
   }
   if (MODE == M_GRAD || MODE == M_MULT) {
     double vals[NWP] = {p_r2, p_xz, 0.0, p_cx};
-    for (int q = 0; q < NWP; ++q) {
+    for (int qq = 0; qq < NWP; ++qq) {
       __syncthreads();
-      red[tid] = vals[q];
+      red[tid] = vals[qq];
       __syncthreads();
-      for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
+      for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
         __syncthreads();
       }
-      if (tid == 0) a.wgpart[(size_t)sidx * NWP + q] = red[0];
+      if (tid == 0) a.wgpart[(size_t)sidx * NWP + qq] = red[0];
     }
   }
 }
@@ -423,7 +457,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
 // row finalisers: thread per (row, pcol); 16 lanes per row
 // ---------------------------------------------------------------------------
 struct RowArgs {
-  int n, p, nb, nseg;
+  int n, p, pw, nb, nseg;
   const int* seg_start;  // nb + 1
   const void* rowpart;
   const void* colpart;
@@ -434,14 +468,21 @@ __device__ __forceinline__ double row_sum(const RowArgs& ra, int r, int k) {
   const int I = r >> 6, rr = r & 63;
   const T* rp = (const T*)ra.rowpart;
   const T* cp = (const T*)ra.colpart;
+  const int pw = ra.pw;
   double s = 0.0;
 #pragma unroll 8
   for (int J = I; J < ra.nb; ++J) {
     const long long t = ((long long)J * (J + 1) >> 1) + I;
-    s += (double)rp[((size_t)t * 64 + rr) * 16 + k];
+    s += (double)rp[((size_t)t * 64 + rr) * pw + k];
   }
-  for (int q = ra.seg_start[I]; q < ra.seg_start[I + 1]; ++q) s += (double)cp[((size_t)q * 64 + rr) * 16 + k];
+  for (int q = ra.seg_start[I]; q < ra.seg_start[I + 1]; ++q) s += (double)cp[((size_t)q * 64 + rr) * pw + k];
   return s;
+}
+
+// sum over the pw lanes of one row (pw = 16, 32 or 64), fixed butterfly order
+__device__ __forceinline__ double sum_row(double v, int pw) {
+  for (int off = pw >> 1; off >= 1; off >>= 1) v += __shfl_xor(v, off, pw);
+  return v;
 }
 
 __device__ __forceinline__ double sum16(double v) {
@@ -450,17 +491,17 @@ __device__ __forceinline__ double sum16(double v) {
   return v;
 }
 
+// threads: one per (row, column) of the pw-padded factor
 __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __restrict__ Y,
                                                   double* __restrict__ egrad, double* __restrict__ rgrad,
                                                   double* __restrict__ zvec) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx >> 4, k = idx & 15;
+  const int r = idx / ra.pw, k = idx % ra.pw;
   const bool in = r < ra.n;
   const bool kin = in && k < ra.p;
-  double gy = in ? row_sum<double>(ra, r, k) : 0.0;
-  double y = kin ? Y[(size_t)r * ra.p + k] : 0.0;
-  if (!kin) gy = 0.0;
-  const double z = sum16(gy * y);
+  double gy = kin ? row_sum<double>(ra, r, k) : 0.0;
+  const double y = kin ? Y[(size_t)r * ra.p + k] : 0.0;
+  const double z = sum_row(gy * y, ra.pw);
   if (in && k == 0) zvec[r] = z;
   if (kin) {
     if (egrad) egrad[(size_t)r * ra.p + k] = 2.0 * gy;
@@ -474,29 +515,30 @@ __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __res
                                                  const double* __restrict__ zvec, double sigma, int fp32, int riem,
                                                  double* __restrict__ HU) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx >> 4, k = idx & 15;
+  const int pw = ra.pw;
+  const int r = idx / pw, k = idx % pw;
   const bool in = r < ra.n;
   const bool kin = in && k < ra.p;
-  double h = in ? row_sum<T>(ra, r, k) : 0.0;
+  double h = kin ? row_sum<T>(ra, r, k) : 0.0;
   // low-rank terms: sigma [Y (Y^T U + U^T Y) + U (Y^T Y)] (FP64 tiles) or
   // sigma [Y (U^T Y) + U (Y^T Y)] (FP32 tiles carry S U entry-wise)
   const double* YtY = gram;
-  const double* YtU = gram + 256;
+  const double* YtU = gram + 4096;
   double lr = 0.0;
-  if (in) {
+  if (kin) {
     for (int i = 0; i < ra.p; ++i) {
       const double yi = Y[(size_t)r * ra.p + i];
       const double ui = U[(size_t)r * ra.p + i];
-      double w1 = YtU[k * 16 + i];
-      if (!fp32) w1 += YtU[i * 16 + k];
-      lr += yi * w1 + ui * YtY[i * 16 + k];
+      double w1 = YtU[k * pw + i];
+      if (!fp32) w1 += YtU[i * pw + k];
+      lr += yi * w1 + ui * YtY[i * pw + k];
     }
   }
   double Ht = kin ? 2.0 * (h + sigma * lr) : 0.0;
   const double y = kin ? Y[(size_t)r * ra.p + k] : 0.0;
   const double u = kin ? U[(size_t)r * ra.p + k] : 0.0;
   if (riem) {
-    const double d = sum16(Ht * y);
+    const double d = sum_row(Ht * y, pw);
     Ht = Ht - d * y - 2.0 * (in ? zvec[r] : 0.0) * u;
   }
   if (kin) HU[(size_t)r * ra.p + k] = Ht;
@@ -507,20 +549,20 @@ __global__ __launch_bounds__(256) void k_row_mult(RowArgs ra, const double* __re
                                                   double* __restrict__ zpart) {
   __shared__ double red[256];
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx >> 4, k = idx & 15;
+  const int r = idx / ra.pw, k = idx % ra.pw;
   const bool in = r < ra.n;
   const bool kin = in && k < ra.p;
-  double o = kin ? row_sum<double>(ra, r, k) : 0.0;
+  const double o = kin ? row_sum<double>(ra, r, k) : 0.0;
   const double y = kin ? Y[(size_t)r * ra.p + k] : 0.0;
-  const double z = sum16(o * y);
+  const double z = sum_row(o * y, ra.pw);
   if (in && k == 0) {
     zmult[r] = z;
     if (zout) zout[r] = z;
   }
   red[threadIdx.x] = (in && k == 0) ? z : 0.0;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) zpart[blockIdx.x] = red[0];
@@ -529,7 +571,7 @@ __global__ __launch_bounds__(256) void k_row_mult(RowArgs ra, const double* __re
 __global__ __launch_bounds__(256) void k_row_xmv(RowArgs ra, const double* __restrict__ V,
                                                  const double* __restrict__ zmult, double* __restrict__ XV) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx >> 4, k = idx & 15;
+  const int r = idx / ra.pw, k = idx % ra.pw;
   if (r >= ra.n || k >= ra.p) return;
   const double o = row_sum<double>(ra, r, k);
   XV[(size_t)r * ra.p + k] = o - zmult[r] * V[(size_t)r * ra.p + k];
@@ -594,41 +636,72 @@ __global__ __launch_bounds__(256) void k_scalars(int mode, const double* __restr
   }
 }
 
-// Gram matrices Y^T Y and Y^T U (16 x 16, FP64) with MFMA over 4-row chunks;
-// block partials, then a fixed-order final sum.
+// Gram matrices Y^T Y and Y^T U (pw x pw, FP64, row pitch pw) with MFMA over
+// 4-row chunks.  The NC x NC grid of 16 x 16 block pairs is spread over the
+// four waves (NC = 4: wave w owns block row i = w; NC = 2: one pair per wave);
+// for NC = 1 the waves split the rows instead.  Every (block, row group)
+// writes its own partial; a fixed-order final sum follows.
+template <int PW>
+struct GramSplit {
+  static constexpr int NC = PW / 16;
+  static constexpr int NPAIR = NC * NC;
+  static constexpr int RS = NPAIR >= 4 ? 1 : 4 / NPAIR;   // row groups
+  static constexpr int PPW = NPAIR >= 4 ? NPAIR / 4 : 1;  // pairs per wave
+};
+
+template <int PW>
 __global__ __launch_bounds__(256) void k_gram_part(int n, int p, const double* __restrict__ Y,
                                                    const double* __restrict__ U, double* __restrict__ part) {
-  __shared__ double red[4][512];
+  typedef GramSplit<PW> GS;
+  constexpr int NC = GS::NC, RS = GS::RS, PPW = GS::PPW;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const int per = (n + gridDim.x - 1) / gridDim.x;
   const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
-  v4d ayy = {0, 0, 0, 0}, ayu = {0, 0, 0, 0};
-  for (int rb = r0 + 4 * w; rb < r1; rb += 16) {
-    const int r = rb + lk;
-    const bool ok = r < r1 && li < p;
-    const double y = ok ? Y[(size_t)r * p + li] : 0.0;
-    const double u = ok ? U[(size_t)r * p + li] : 0.0;
-    // A[i][k] = Y[r_k][i] (lane i + 16 k), B[k][j] = Y[r_k][j] / U[r_k][j]
-    ayy = mfma(y, y, ayy);
-    ayu = mfma(y, u, ayu);
-  }
+  const int rg = w % RS, pbase = (w / RS) * PPW;
+  v4d ayy[PPW], ayu[PPW];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int i = drow<double>(lk, v);
-    red[w][i * 16 + li] = ayy[v];
-    red[w][256 + i * 16 + li] = ayu[v];
+  for (int q = 0; q < PPW; ++q) {
+    ayy[q] = v4d{0, 0, 0, 0};
+    ayu[q] = v4d{0, 0, 0, 0};
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 512; e += 256)
-    part[(size_t)blockIdx.x * 512 + e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+  for (int rb = r0 + 4 * rg; rb < r1; rb += 4 * RS) {
+    const int r = rb + lk;
+    const bool rok = r < r1;
+    // A[i][k] = Y[r_k][i] (lane i + 16 k), B[k][j] = Y[r_k][j] / U[r_k][j]
+#pragma unroll
+    for (int q = 0; q < PPW; ++q) {
+      const int pr = pbase + q, bi = pr / NC, bj = pr % NC;
+      const int ci = 16 * bi + li, cj = 16 * bj + li;
+      const double yi = (rok && ci < p) ? Y[(size_t)r * p + ci] : 0.0;
+      const double yj = (rok && cj < p) ? Y[(size_t)r * p + cj] : 0.0;
+      const double uj = (rok && cj < p) ? U[(size_t)r * p + cj] : 0.0;
+      ayy[q] = mfma(yi, yj, ayy[q]);
+      ayu[q] = mfma(yi, uj, ayu[q]);
+    }
+  }
+  double* out = part + ((size_t)blockIdx.x * RS + rg) * 2 * PW * PW;
+#pragma unroll
+  for (int q = 0; q < PPW; ++q) {
+    const int pr = pbase + q, bi = pr / NC, bj = pr % NC;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = drow<double>(lk, v);
+      out[(16 * bi + rr) * PW + 16 * bj + li] = ayy[q][v];
+      out[PW * PW + (16 * bi + rr) * PW + 16 * bj + li] = ayu[q][v];
+    }
+  }
 }
 
-__global__ __launch_bounds__(512) void k_gram_final(int nblk, const double* __restrict__ part,
-                                                    double* __restrict__ gram) {
+__global__ __launch_bounds__(256) void k_gram_final(int nblk, int len, const double* __restrict__ part,
+                                                    double* __restrict__ gram, int pw) {
+  // part: nblk x (2 pw^2); gram: Y^T Y at [0, pw^2), Y^T U at [4096, 4096 + pw^2)
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= len) return;
   double s = 0.0;
 #pragma unroll 8
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * 512 + threadIdx.x];
-  gram[threadIdx.x] = s;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * len + e];
+  const int pw2 = pw * pw;
+  gram[e < pw2 ? e : 4096 + (e - pw2)] = s;
 }
 
 // retraction and tangent projection: one thread per row, any p
@@ -799,7 +872,7 @@ __global__ __launch_bounds__(256) void k_tcg_update1(int n, int p, const double*
   double rr = 0.0;
   if (i < n) {
     const size_t o = (size_t)i * p;
-    double rn[16];
+    double rn[64];
     double dr = 0.0;
     for (int k = 0; k < p; ++k) {
       eta[o + k] += alpha * d[o + k];
@@ -830,7 +903,7 @@ __global__ __launch_bounds__(256) void k_tcg_update2(int n, int p, const double*
   if (i >= n) return;
   const double beta = *beta_dev;
   const size_t o = (size_t)i * p;
-  double dn[16];
+  double dn[64];
   double dd = 0.0;
   for (int k = 0; k < p; ++k) {
     dn[k] = -r[o + k] + beta * d[o + k];
@@ -845,7 +918,7 @@ __global__ __launch_bounds__(256) void k_rightmul(int n, int p, int q, const dou
                                                   double* __restrict__ Yout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double out[16];
+  double out[64];
   double nrm = 0.0;
   for (int c = 0; c < q; ++c) {
     double s = 0.0;
@@ -857,12 +930,15 @@ __global__ __launch_bounds__(256) void k_rightmul(int n, int p, int q, const dou
   for (int c = 0; c < q; ++c) Yout[(size_t)i * q + c] = out[c] * inv;
 }
 
-// U (n x p) = 0 except column col = v
+// column `col` of U (n x p) = v; with zero_rest the other columns are cleared
 __global__ __launch_bounds__(256) void k_set_col(int n, int p, int col, const double* __restrict__ v,
-                                                 double* __restrict__ U) {
+                                                 double* __restrict__ U, int zero_rest) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int k = 0; k < p; ++k) U[(size_t)i * p + k] = (k == col) ? v[i] : 0.0;
+  if (zero_rest)
+    for (int k = 0; k < p; ++k) U[(size_t)i * p + k] = (k == col) ? v[i] : 0.0;
+  else
+    U[(size_t)i * p + col] = v[i];
 }
 
 // w -= V h  (V: k column vectors of length n stored one after another)
@@ -970,6 +1046,7 @@ __device__ __forceinline__ int inv_c2(long long t) {
 
 struct BqpArgs {
   int q;
+  int nk;              // 4-wide K chunks covering p
   long long off2, off3, off4;
   const void* Yp;
   const void* Up;
@@ -984,7 +1061,7 @@ struct BqpArgs {
 // row of the colex basis: {} -> 0, {i} -> 1 + i, {i<j} -> 1 + q + C(j,2) + i
 __device__ __forceinline__ int prow(int q, int i, int j) { return 1 + q + (int)c2(j) + i; }
 
-template <typename T, bool ZMODE>
+template <typename T, bool ZMODE, int PW>
 __global__ __launch_bounds__(256) void k_bqp4a(BqpArgs a) {
   typedef typename V4<T>::type v4;
   const int4 it = a.items[blockIdx.x];
@@ -999,18 +1076,18 @@ __global__ __launch_bounds__(256) void k_bqp4a(BqpArgs a) {
   // A operand: rows d (pairs {c, d}); B operand: columns pi (pairs below c)
   const int dA = d0 + li;
   const bool dok = dA < q;
-  const int rowA = dok ? prow(q, c, dA) : 0;
+  const size_t rowA = (size_t)(dok ? prow(q, c, dA) : 0) * PW;
   const long long piB = pib + li;
-  const int rowB = (piB < npi) ? (1 + q + (int)piB) : 0;
+  const size_t rowB = (size_t)((piB < npi) ? (1 + q + (int)piB) : 0) * PW;
+  const int nk = min(PW / 4, a.nk);
   v4 acc = {0, 0, 0, 0};
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < nk; ++j) {
     const int k = 4 * j + lk;
-    const T ya = dok ? Y[(size_t)rowA * 16 + k] : (T)0;
-    const T yb = Y[(size_t)rowB * 16 + k];
+    const T ya = dok ? Y[rowA + k] : (T)0;
+    const T yb = Y[rowB + k];
     if (ZMODE) {
-      const T ua = dok ? U[(size_t)rowA * 16 + k] : (T)0;
-      const T ub = U[(size_t)rowB * 16 + k];
+      const T ua = dok ? U[rowA + k] : (T)0;
+      const T ub = U[rowB + k];
       acc = mfma(ua, yb, acc);
       acc = mfma(ya, ub, acc);
     } else {
@@ -1032,58 +1109,76 @@ __global__ __launch_bounds__(256) void k_bqp4a(BqpArgs a) {
 // one workgroup per (c, d): the pair rows {x, c} and {x, d} (x < c) of Y and
 // U are staged in LDS, then the waves sweep the tiles (b-block J, a-block I),
 // I <= J, of the symmetric c x c term
-template <typename T, bool ZMODE>
+template <typename T, bool ZMODE, int PW>
 __global__ __launch_bounds__(256) void k_bqp4b(BqpArgs a) {
   typedef typename V4<T>::type v4;
+  constexpr int NS = ZMODE ? 4 : 2;   // staged row sets
+  constexpr int MAXT = 7;            // tiles per wave (c <= 111 -> at most 28 tiles)
   const int2 cdp = a.cd[blockIdx.x];
   const int c = cdp.x, d = cdp.y;
   const int q = a.q;
   const T* Y = (const T*)a.Yp;
   const T* U = (const T*)a.Up;
-  constexpr int NS = ZMODE ? 4 : 2;   // staged row sets
-  __shared__ T sm[NS][112 * LP];     // c <= 111 rows per set
+  __shared__ T sm[NS][112 * LP];     // one 16-column chunk of c <= 111 rows per set
   const int tid = threadIdx.x;
   const int rc0 = 1 + q + (int)c2(c), rd0 = 1 + q + (int)c2(d);
   const int nrow = ((c + 15) >> 4) << 4;
-  for (int i = tid; i < nrow * 16; i += 256) {
-    const int x = i >> 4, k = i & 15;
-    const bool ok = x < c;
-    sm[0][x * LP + k] = ok ? Y[(size_t)(rc0 + x) * 16 + k] : (T)0;
-    sm[1][x * LP + k] = ok ? Y[(size_t)(rd0 + x) * 16 + k] : (T)0;
-    if (ZMODE) {
-      sm[2 % NS][x * LP + k] = ok ? U[(size_t)(rc0 + x) * 16 + k] : (T)0;
-      sm[3 % NS][x * LP + k] = ok ? U[(size_t)(rd0 + x) * 16 + k] : (T)0;
-    }
-  }
-  __syncthreads();
-  const T* Yc = sm[0];
-  const T* Yd = sm[1];
-  const T* Uc = sm[2 % NS];
-  const T* Ud = sm[3 % NS];
   const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
   const int nbk = (c + 15) >> 4;
   const int ntile = nbk * (nbk + 1) / 2;
+  v4 acc[MAXT];
+#pragma unroll
+  for (int i = 0; i < MAXT; ++i) acc[i] = v4{0, 0, 0, 0};
+  const int nchunk = (min(PW / 4, a.nk) + 3) / 4;
+  for (int kc = 0; kc < nchunk; ++kc) {
+    __syncthreads();
+    for (int i = tid; i < nrow * 16; i += 256) {
+      const int x = i >> 4, k = i & 15, kk = 16 * kc + k;
+      const bool ok = x < c;
+      sm[0][x * LP + k] = ok ? Y[(size_t)(rc0 + x) * PW + kk] : (T)0;
+      sm[1][x * LP + k] = ok ? Y[(size_t)(rd0 + x) * PW + kk] : (T)0;
+      if (ZMODE) {
+        sm[2 % NS][x * LP + k] = ok ? U[(size_t)(rc0 + x) * PW + kk] : (T)0;
+        sm[3 % NS][x * LP + k] = ok ? U[(size_t)(rd0 + x) * PW + kk] : (T)0;
+      }
+    }
+    __syncthreads();
+    const T* Yc = sm[0];
+    const T* Yd = sm[1];
+    const T* Uc = sm[2 % NS];
+    const T* Ud = sm[3 % NS];
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) {
+      const int t = w + 4 * ti;
+      if (t >= ntile) break;
+      int J = 0;
+      while ((J + 1) * (J + 2) / 2 <= t) ++J;
+      const int I = t - J * (J + 1) / 2;
+      const int rb = J * 16 + li, ra = I * 16 + li;  // A rows b, B columns a
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 4 * j + lk;
+        if (ZMODE) {
+          // (ad|bc) = Y_bc.U_ad + U_bc.Y_ad ; (ac|bd) = Y_bd.U_ac + U_bd.Y_ac
+          acc[ti] = mfma(Yc[rb * LP + k], Ud[ra * LP + k], acc[ti]);
+          acc[ti] = mfma(Uc[rb * LP + k], Yd[ra * LP + k], acc[ti]);
+          acc[ti] = mfma(Yd[rb * LP + k], Uc[ra * LP + k], acc[ti]);
+          acc[ti] = mfma(Ud[rb * LP + k], Yc[ra * LP + k], acc[ti]);
+        } else {
+          acc[ti] = mfma(Yc[rb * LP + k], Yd[ra * LP + k], acc[ti]);
+          acc[ti] = mfma(Yd[rb * LP + k], Yc[ra * LP + k], acc[ti]);
+        }
+      }
+    }
+  }
   const long long base = a.off4 + c3(c) + c4(d);
-  for (int t = w; t < ntile; t += 4) {
+#pragma unroll
+  for (int ti = 0; ti < MAXT; ++ti) {
+    const int t = w + 4 * ti;
+    if (t >= ntile) break;
     int J = 0;
     while ((J + 1) * (J + 2) / 2 <= t) ++J;
     const int I = t - J * (J + 1) / 2;
-    const int rb = J * 16 + li, ra = I * 16 + li;  // A rows b, B columns a
-    v4 acc = {0, 0, 0, 0};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = 4 * j + lk;
-      if (ZMODE) {
-        // (ad|bc) = Y_bc.U_ad + U_bc.Y_ad ; (ac|bd) = Y_bd.U_ac + U_bd.Y_ac
-        acc = mfma(Yc[rb * LP + k], Ud[ra * LP + k], acc);
-        acc = mfma(Uc[rb * LP + k], Yd[ra * LP + k], acc);
-        acc = mfma(Yd[rb * LP + k], Uc[ra * LP + k], acc);
-        acc = mfma(Ud[rb * LP + k], Yc[ra * LP + k], acc);
-      } else {
-        acc = mfma(Yc[rb * LP + k], Yd[ra * LP + k], acc);
-        acc = mfma(Yd[rb * LP + k], Yc[ra * LP + k], acc);
-      }
-    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int bb = J * 16 + drow<T>(lk, v);
@@ -1091,26 +1186,30 @@ __global__ __launch_bounds__(256) void k_bqp4b(BqpArgs a) {
       if (aa < bb && bb < c) {
         const long long g = base + aa + c2(bb);
         const double t1 = a.dst[g * a.stride];
-        a.dst[g * a.stride] = (t1 + (double)acc[v]) * (1.0 / 3.0);
+        a.dst[g * a.stride] = (t1 + (double)acc[ti][v]) * (1.0 / 3.0);
       }
     }
   }
 }
 
-// B(r1, r2) by 16 lanes (lane k owns element k), summed in a fixed order
-template <typename T, bool ZMODE>
+// B(r1, r2) by 16 lanes (lane k owns elements k, k + 16, ...), summed by the
+// caller in a fixed order
+template <typename T, bool ZMODE, int PW>
 __device__ __forceinline__ double bform16(const T* Y, const T* U, int r1, int r2, int k) {
-  double v;
-  if (ZMODE)
-    v = (double)Y[(size_t)r1 * 16 + k] * (double)U[(size_t)r2 * 16 + k] +
-        (double)U[(size_t)r1 * 16 + k] * (double)Y[(size_t)r2 * 16 + k];
-  else
-    v = (double)Y[(size_t)r1 * 16 + k] * (double)Y[(size_t)r2 * 16 + k];
+  double v = 0.0;
+#pragma unroll
+  for (int c = 0; c < PW / 16; ++c) {
+    const size_t o1 = (size_t)r1 * PW + 16 * c + k, o2 = (size_t)r2 * PW + 16 * c + k;
+    if (ZMODE)
+      v += (double)Y[o1] * (double)U[o2] + (double)U[o1] * (double)Y[o2];
+    else
+      v += (double)Y[o1] * (double)Y[o2];
+  }
   return v;
 }
 
 // degree 3: 16 lanes per class {a<b<c}, id = off3 + a + C(b,2) + C(c,3)
-template <typename T, bool ZMODE>
+template <typename T, bool ZMODE, int PW>
 __global__ __launch_bounds__(256) void k_bqp3(BqpArgs a) {
   const long long t = ((long long)blockIdx.x * 256 + threadIdx.x) >> 4;
   const int k = threadIdx.x & 15;
@@ -1127,15 +1226,15 @@ __global__ __launch_bounds__(256) void k_bqp3(BqpArgs a) {
   const T* U = (const T*)a.Up;
   double v = 0.0;
   if (ok)
-    v = bform16<T, ZMODE>(Y, U, 1 + aa, prow(q, b, c), k) + bform16<T, ZMODE>(Y, U, 1 + b, prow(q, aa, c), k) +
-        bform16<T, ZMODE>(Y, U, 1 + c, prow(q, aa, b), k);
+    v = bform16<T, ZMODE, PW>(Y, U, 1 + aa, prow(q, b, c), k) + bform16<T, ZMODE, PW>(Y, U, 1 + b, prow(q, aa, c), k) +
+        bform16<T, ZMODE, PW>(Y, U, 1 + c, prow(q, aa, b), k);
   v = sum16(v);
   if (ok && k == 0) a.dst[(a.off3 + t) * a.stride] = v * (1.0 / 3.0);
 }
 
 // degrees 2 and 1: one wave per class; 4 groups of 16 lanes split the sum
 // over the third index, combined in a fixed order
-template <typename T, bool ZMODE>
+template <typename T, bool ZMODE, int PW>
 __global__ __launch_bounds__(256) void k_bqp21(BqpArgs a) {
   const int q = a.q;
   const long long t = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
@@ -1148,20 +1247,20 @@ __global__ __launch_bounds__(256) void k_bqp21(BqpArgs a) {
   if (t < n2) {
     const int j = inv_c2(t);
     const int i = (int)(t - c2(j));
-    if (g == 0) v = bform16<T, ZMODE>(Y, U, 0, prow(q, i, j), k) + bform16<T, ZMODE>(Y, U, 1 + i, 1 + j, k);
+    if (g == 0) v = bform16<T, ZMODE, PW>(Y, U, 0, prow(q, i, j), k) + bform16<T, ZMODE, PW>(Y, U, 1 + i, 1 + j, k);
     for (int l = g; l < q; l += 4) {
       if (l == i || l == j) continue;
       const int ri = l < i ? prow(q, l, i) : prow(q, i, l);
       const int rj = l < j ? prow(q, l, j) : prow(q, j, l);
-      v += bform16<T, ZMODE>(Y, U, ri, rj, k);
+      v += bform16<T, ZMODE, PW>(Y, U, ri, rj, k);
     }
     out = a.off2 + t;
   } else if (t < n2 + q) {
     const int i = (int)(t - n2);
-    if (g == 0) v = bform16<T, ZMODE>(Y, U, 0, 1 + i, k);
+    if (g == 0) v = bform16<T, ZMODE, PW>(Y, U, 0, 1 + i, k);
     for (int j = g; j < q; j += 4) {
       if (j == i) continue;
-      v += bform16<T, ZMODE>(Y, U, 1 + j, j < i ? prow(q, j, i) : prow(q, i, j), k);
+      v += bform16<T, ZMODE, PW>(Y, U, 1 + j, j < i ? prow(q, j, i) : prow(q, i, j), k);
     }
     out = 1 + i;
   }
@@ -1171,14 +1270,14 @@ __global__ __launch_bounds__(256) void k_bqp21(BqpArgs a) {
 }
 
 // degree 0: partial sums of B(alpha, alpha) / 2 ... per block (16 lanes per row)
-template <typename T, bool ZMODE>
+template <typename T, bool ZMODE, int PW>
 __global__ __launch_bounds__(256) void k_bqp0(BqpArgs a, int n) {
   __shared__ double red[16];
   const int r = (blockIdx.x * 256 + threadIdx.x) >> 4;
   const int k = threadIdx.x & 15;
   const T* Y = (const T*)a.Yp;
   const T* U = (const T*)a.Up;
-  double v = (r < n) ? bform16<T, ZMODE>(Y, U, r, r, k) : 0.0;
+  double v = (r < n) ? bform16<T, ZMODE, PW>(Y, U, r, r, k) : 0.0;
   v = sum16(v);
   if (k == 0) red[threadIdx.x >> 4] = v;
   __syncthreads();
@@ -1244,6 +1343,23 @@ static KArgs make_args(mdsdp_problem P) {
 
 static unsigned seg_grid(mdsdp_problem P) { return (unsigned)(8 * ((P->nseg + 7) / 8)); }
 
+// factor width of the staged tiles: 16, 32 or 64 columns
+int pw_of(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : 64); }
+
+#define PW_DISPATCH(pw, ...)      \
+  do {                            \
+    if ((pw) == 16) {             \
+      constexpr int PWV = 16;     \
+      __VA_ARGS__;                \
+    } else if ((pw) == 32) {      \
+      constexpr int PWV = 32;     \
+      __VA_ARGS__;                \
+    } else {                      \
+      constexpr int PWV = 64;     \
+      __VA_ARGS__;                \
+    }                             \
+  } while (0)
+
 void timer_begin(mdsdp_problem P, hipStream_t s, const char* name) {
   if (!P->timer.on) return;
   Timer::Rec r;
@@ -1264,15 +1380,16 @@ void timer_end(mdsdp_problem P, hipStream_t s) {
 mdsdp_status launch_stage(mdsdp_problem P, int p, const double* Y, const double* U, bool fp32,
                           hipStream_t s) {
   P->last_p = p;
+  P->pw = pw_of(p);
   timer_begin(P, s, "stage");
   unsigned long long* bnd = P->bqp_q > 0 ? nullptr : P->bound;
   if (bnd) MDSDP_HIP(hipMemsetAsync(P->bound, 0, 2 * sizeof(unsigned long long), s));
-  const long long cnt = (long long)P->npad * 16;
+  const long long cnt = (long long)P->npad * P->pw;
   if (fp32)
-    k_stage<float><<<blocks_for(cnt, 256), 256, 0, s>>>(P->n, p, P->npad, Y, U, (float*)P->Yp, (float*)P->Up,
-                                                         bnd);
+    k_stage<float><<<blocks_for(cnt, 256), 256, 0, s>>>(P->n, p, P->npad, P->pw, Y, U, (float*)P->Yp,
+                                                         (float*)P->Up, bnd);
   else
-    k_stage<double><<<blocks_for(cnt, 256), 256, 0, s>>>(P->n, p, P->npad, Y, U, (double*)P->Yp,
+    k_stage<double><<<blocks_for(cnt, 256), 256, 0, s>>>(P->n, p, P->npad, P->pw, Y, U, (double*)P->Yp,
                                                           (double*)P->Up, bnd);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
@@ -1292,35 +1409,36 @@ static mdsdp_status launch_bqp(mdsdp_problem P, bool zmode, bool fp32, hipStream
   b.ncd = P->bqp_ncd;
   b.dst = zmode ? P->yp : (double*)P->cy + 1;
   b.stride = zmode ? 1 : 2;
-  b.part = P->gpart;
+  b.part = P->gpart + GP_BQP0;
+  b.nk = (P->last_p + 3) / 4;
   const int q = P->bqp_q;
   const long long n3 = (long long)q * (q - 1) * (q - 2) / 6, n2 = (long long)q * (q - 1) / 2;
   const int nrowblk = (P->n * 16 + 255) / 256;
-#define BQP_LAUNCH(TT, ZZ)                                                                      \
+#define BQP_LAUNCH(TT, ZZ, PWX)                                                                 \
   do {                                                                                          \
     timer_begin(P, s, "bqp4a");                                                                 \
-    if (P->bqp4a_n > 0) k_bqp4a<TT, ZZ><<<P->bqp4a_n, 256, 0, s>>>(b);                          \
+    if (P->bqp4a_n > 0) k_bqp4a<TT, ZZ, PWX><<<P->bqp4a_n, 256, 0, s>>>(b);                     \
     timer_end(P, s);                                                                            \
     timer_begin(P, s, "bqp4b");                                                                 \
-    if (P->bqp_ncd > 0) k_bqp4b<TT, ZZ><<<P->bqp_ncd, 256, 0, s>>>(b);                         \
+    if (P->bqp_ncd > 0) k_bqp4b<TT, ZZ, PWX><<<P->bqp_ncd, 256, 0, s>>>(b);                    \
     timer_end(P, s);                                                                            \
     timer_begin(P, s, "bqp3");                                                                  \
-    if (n3 > 0) k_bqp3<TT, ZZ><<<blocks_for(n3 * 16, 256), 256, 0, s>>>(b);                      \
+    if (n3 > 0) k_bqp3<TT, ZZ, PWX><<<blocks_for(n3 * 16, 256), 256, 0, s>>>(b);                 \
     timer_end(P, s);                                                                            \
     timer_begin(P, s, "bqp21");                                                                 \
-    k_bqp21<TT, ZZ><<<blocks_for((n2 + q) * 64, 256), 256, 0, s>>>(b);                           \
+    k_bqp21<TT, ZZ, PWX><<<blocks_for((n2 + q) * 64, 256), 256, 0, s>>>(b);                      \
     timer_end(P, s);                                                                            \
     timer_begin(P, s, "bqp0");                                                                  \
-    k_bqp0<TT, ZZ><<<nrowblk, 256, 0, s>>>(b, P->n);                                            \
+    k_bqp0<TT, ZZ, PWX><<<nrowblk, 256, 0, s>>>(b, P->n);                                       \
     k_bqp0_final<<<1, 256, 0, s>>>(b, nrowblk, P->n);                                          \
     timer_end(P, s);                                                                            \
   } while (0)
   if (!zmode)
-    BQP_LAUNCH(double, false);
+    PW_DISPATCH(P->pw, BQP_LAUNCH(double, false, PWV));
   else if (fp32)
-    BQP_LAUNCH(float, true);
+    PW_DISPATCH(P->pw, BQP_LAUNCH(float, true, PWV));
   else
-    BQP_LAUNCH(double, true);
+    PW_DISPATCH(P->pw, BQP_LAUNCH(double, true, PWV));
 #undef BQP_LAUNCH
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -1333,7 +1451,7 @@ mdsdp_status launch_classsum_S(mdsdp_problem P, hipStream_t s) {
     if (st != MDSDP_OK) return st;
   } else {
     KArgs a = make_args(P);
-    k_classsum<double, false><<<seg_grid(P), 256, 0, s>>>(a);
+    PW_DISPATCH(P->pw, (k_classsum<double, false, PWV><<<seg_grid(P), 256, 0, s>>>(a)));
     k_final_S<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->Cavg, P->scal, P->cy);
   }
   timer_end(P, s);
@@ -1349,9 +1467,9 @@ mdsdp_status launch_classsum_Z(mdsdp_problem P, bool fp32, hipStream_t s) {
   } else {
     KArgs a = make_args(P);
     if (fp32)
-      k_classsum<float, true><<<seg_grid(P), 256, 0, s>>>(a);
+      PW_DISPATCH(P->pw, (k_classsum<float, true, PWV><<<seg_grid(P), 256, 0, s>>>(a)));
     else
-      k_classsum<double, true><<<seg_grid(P), 256, 0, s>>>(a);
+      PW_DISPATCH(P->pw, (k_classsum<double, true, PWV><<<seg_grid(P), 256, 0, s>>>(a)));
     k_final_Z<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->scal, P->yp);
   }
   timer_end(P, s);
@@ -1361,37 +1479,53 @@ mdsdp_status launch_classsum_Z(mdsdp_problem P, bool fp32, hipStream_t s) {
 
 mdsdp_status launch_bty(mdsdp_problem P, hipStream_t s) {
   const int nblk = 64;
-  k_bty_part<<<nblk, 256, 0, s>>>(P->bty_range, P->bvec, P->cy, P->gpart + 4096);
+  k_bty_part<<<nblk, 256, 0, s>>>(P->bty_range, P->bvec, P->cy, P->gpart + GP_BTY);
   MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+template <typename T, int MODE, int PW>
+static mdsdp_status resid_go(mdsdp_problem P, const KArgs& a, unsigned g, hipStream_t s) {
+  typedef ResidLds<T, MODE, PW> L;
+  static bool attr_set[64] = {};
+  const int dev = P->device & 63;
+  if (L::bytes > 65536 && !attr_set[dev]) {
+    MDSDP_HIP(hipFuncSetAttribute((const void*)k_resid<T, MODE, PW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)L::bytes));
+    attr_set[dev] = true;
+  }
+  k_resid<T, MODE, PW><<<g, 256, L::bytes, s>>>(a);
   return MDSDP_OK;
 }
 
 mdsdp_status launch_resid(mdsdp_problem P, int mode, bool fp32, hipStream_t s) {
   KArgs a = make_args(P);
   const unsigned g = seg_grid(P);
+  mdsdp_status st = MDSDP_OK;
   switch (mode) {
     case M_GRAD:
       timer_begin(P, s, "resid_grad");
-      k_resid<double, M_GRAD><<<g, 256, 0, s>>>(a);
+      PW_DISPATCH(P->pw, st = (resid_go<double, M_GRAD, PWV>(P, a, g, s)));
       break;
     case M_MULT:
       timer_begin(P, s, "resid_mult");
-      k_resid<double, M_MULT><<<g, 256, 0, s>>>(a);
+      PW_DISPATCH(P->pw, st = (resid_go<double, M_MULT, PWV>(P, a, g, s)));
       break;
     case M_XMV:
       timer_begin(P, s, "resid_xmv");
-      k_resid<double, M_XMV><<<g, 256, 0, s>>>(a);
+      PW_DISPATCH(P->pw, st = (resid_go<double, M_XMV, PWV>(P, a, g, s)));
       break;
     default:
       if (fp32) {
         timer_begin(P, s, "resid_hvp32");
-        k_resid<float, M_HVP><<<g, 256, 0, s>>>(a);
+        PW_DISPATCH(P->pw, st = (resid_go<float, M_HVP, PWV>(P, a, g, s)));
       } else {
         timer_begin(P, s, "resid_hvp64");
-        k_resid<double, M_HVP><<<g, 256, 0, s>>>(a);
+        PW_DISPATCH(P->pw, st = (resid_go<double, M_HVP, PWV>(P, a, g, s)));
       }
   }
   timer_end(P, s);
+  if (st != MDSDP_OK) return st;
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
@@ -1400,6 +1534,7 @@ static RowArgs row_args(mdsdp_problem P, int p) {
   RowArgs ra;
   ra.n = P->n;
   ra.p = p;
+  ra.pw = P->pw;
   ra.nb = P->nb;
   ra.nseg = P->nseg;
   ra.seg_start = P->seg_start;
@@ -1411,8 +1546,16 @@ static RowArgs row_args(mdsdp_problem P, int p) {
 mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* U, hipStream_t s) {
   const int nblk = std::min(32, (P->n + 63) / 64);
   timer_begin(P, s, "gram");
-  k_gram_part<<<nblk, 256, 0, s>>>(P->n, p, Y, U, P->gpart);
-  k_gram_final<<<1, 512, 0, s>>>(nblk, P->gpart, P->gram);
+  // the Gram width follows p itself (not the last staged width)
+  const int gpw = pw_of(p);
+  P->gram_pw = gpw;
+  const int len = 2 * gpw * gpw;
+  int nparts = nblk;
+  PW_DISPATCH(gpw, {
+    k_gram_part<PWV><<<nblk, 256, 0, s>>>(P->n, p, Y, U, P->gpart + GP_GRAM);
+    nparts = nblk * GramSplit<PWV>::RS;
+  });
+  k_gram_final<<<(len + 255) / 256, 256, 0, s>>>(nparts, len, P->gpart + GP_GRAM, P->gram, gpw);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -1422,8 +1565,8 @@ mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, doubl
                                   double* f, hipStream_t s) {
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_grad");
-  k_row_grad<<<blocks_for((long long)P->n * 16, 256), 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
-  k_scalars<<<1, 256, 0, s>>>(M_GRAD, P->wgpart, P->nseg, nullptr, 0, P->gpart + 4096, 64, P->sigma, P->scal, f,
+  k_row_grad<<<blocks_for((long long)P->n * P->pw, 256), 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
+  k_scalars<<<1, 256, 0, s>>>(M_GRAD, P->wgpart, P->nseg, nullptr, 0, P->gpart + GP_BTY, 64, P->sigma, P->scal, f,
                               nullptr);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
@@ -1435,10 +1578,10 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_hvp");
   if (fp32)
-    k_row_hvp<float><<<blocks_for((long long)P->n * 16, 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec, P->sigma,
+    k_row_hvp<float><<<blocks_for((long long)P->n * P->pw, 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec, P->sigma,
                                                                             1, riem, HU);
   else
-    k_row_hvp<double><<<blocks_for((long long)P->n * 16, 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec,
+    k_row_hvp<double><<<blocks_for((long long)P->n * P->pw, 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec,
                                                                              P->sigma, 0, riem, HU);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
@@ -1448,9 +1591,9 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
 mdsdp_status launch_rowfinal_mult(mdsdp_problem P, int p, const double* Y, double* z, double* kkt,
                                   hipStream_t s) {
   RowArgs ra = row_args(P, p);
-  const unsigned nblk = blocks_for((long long)P->n * 16, 256);
+  const unsigned nblk = blocks_for((long long)P->n * P->pw, 256);
   k_row_mult<<<nblk, 256, 0, s>>>(ra, Y, P->zmult, z, P->zpart);
-  k_scalars<<<1, 256, 0, s>>>(M_MULT, P->wgpart, P->nseg, P->zpart, (int)nblk, P->gpart + 4096, 64, P->sigma,
+  k_scalars<<<1, 256, 0, s>>>(M_MULT, P->wgpart, P->nseg, P->zpart, (int)nblk, P->gpart + GP_BTY, 64, P->sigma,
                               P->scal, nullptr, kkt);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -1458,7 +1601,7 @@ mdsdp_status launch_rowfinal_mult(mdsdp_problem P, int p, const double* Y, doubl
 
 mdsdp_status launch_rowfinal_xmv(mdsdp_problem P, int k, const double* V, double* XV, hipStream_t s) {
   RowArgs ra = row_args(P, k);
-  k_row_xmv<<<blocks_for((long long)P->n * 16, 256), 256, 0, s>>>(ra, V, P->zmult, XV);
+  k_row_xmv<<<blocks_for((long long)P->n * P->pw, 256), 256, 0, s>>>(ra, V, P->zmult, XV);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
@@ -1534,8 +1677,8 @@ mdsdp_status launch_rightmul(int n, int p, int q, const double* Yin, const doubl
   return MDSDP_OK;
 }
 
-mdsdp_status launch_set_col(int n, int p, int col, const double* v, double* U, hipStream_t s) {
-  k_set_col<<<blocks_for(n, 256), 256, 0, s>>>(n, p, col, v, U);
+mdsdp_status launch_set_col(int n, int p, int col, const double* v, double* U, hipStream_t s, bool zero_rest) {
+  k_set_col<<<blocks_for(n, 256), 256, 0, s>>>(n, p, col, v, U, zero_rest ? 1 : 0);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }

@@ -29,11 +29,19 @@ namespace mdsdp {
 
 constexpr int TS = 64;          // tile side
 constexpr int SB = 16;          // MFMA sub-block side
-constexpr int PP = 16;          // padded factor width (p <= 16)
+constexpr int PMAX = 64;        // largest factor width (p <= 64)
 constexpr int TSLOTS = TS * TS;  // slots per tile
 constexpr int LP = 17;          // LDS row pitch (elements) for 16-wide rows
 constexpr uint32_t CLS_MASK = 0x3FFFFFFFu;
 constexpr uint32_t OWNER_BIT = 0x40000000u;
+
+// carve of the `gpart` scratch (doubles): Gram partials (<= 32 blocks of
+// 2 x 64 x 64), b^T y partials, degree-0 BQP partials, host-built p x p matrix
+constexpr size_t GP_GRAM = 0;
+constexpr size_t GP_BTY = 262144;
+constexpr size_t GP_BQP0 = GP_BTY + 64;
+constexpr size_t GP_M = GP_BQP0 + 4096;
+constexpr size_t GP_SIZE = GP_M + PMAX * PMAX;
 
 struct Seg {
   int J, I0, I1;  // column block J, row blocks I0..I1 inclusive
@@ -102,6 +110,8 @@ struct mdsdp_problem_s {
   double* scal = nullptr;       // device scalars (SC_*), [7] = S-sum scale, [8] = Z-sum scale
   unsigned long long* bound = nullptr;  // max row norms of Y, U (bit patterns)
   int last_p = 0;
+  int pw = 16;         // staged factor width for last_p: 16, 32 or 64
+  int gram_pw = 16;    // row pitch of the last Gram matrices written to `gram`
   // solver / Lanczos workspace
   double* dotpart = nullptr;
   const double** dotptr = nullptr;  // unused (kept for layout stability)
@@ -146,6 +156,7 @@ mdsdp_status hip_fail(hipError_t e, const char* what);
   } while (0)
 
 // kernel launchers (kernels.hip)
+int pw_of(int p);
 mdsdp_status launch_stage(mdsdp_problem P, int p, const double* Y, const double* U, bool fp32,
                           hipStream_t s);
 mdsdp_status launch_classsum_S(mdsdp_problem P, hipStream_t s);
@@ -186,7 +197,8 @@ mdsdp_status launch_tcg_update(int n, int p, const double* Y, double alpha, doub
 mdsdp_status launch_vt_w(int n, int k, const double* V, const double* w, double* h, hipStream_t s);
 mdsdp_status launch_rightmul(int n, int p, int q, const double* Yin, const double* M, bool normalize,
                              double* Yout, hipStream_t s);
-mdsdp_status launch_set_col(int n, int p, int col, const double* v, double* U, hipStream_t s);
+mdsdp_status launch_set_col(int n, int p, int col, const double* v, double* U, hipStream_t s,
+                           bool zero_rest = true);
 mdsdp_status launch_gemv_sub(int n, int k, const double* V, const double* h, double* w, hipStream_t s);
 mdsdp_status launch_gemv(int n, int k, const double* V, const double* sv, double* out, hipStream_t s);
 

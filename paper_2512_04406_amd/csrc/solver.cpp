@@ -7,7 +7,7 @@
 // Readings of points the paper leaves open (same as the oracle's):
 //  * RTR constants rho' = 0.1, kappa = 0.1, theta = 1, Delta_bar = pi sqrt(n),
 //    Delta_0 = Delta_bar / 8 (Absil-Baker-Gallivan trust region);
-//  * inner tolerance max(gtol_min, min(gtol0, 0.1 eta_max));
+//  * inner tolerance max(gtol_min, min(gtol0, 0.1 eta_max, gtol_decay * previous tolerance));
 //  * carried direction: backtracking t = sqrt(n), sqrt(n)/2, ... along
 //    R_[Y,0](t [0, v]) until Psi_k decreases, then RTR;
 //  * rank rule: drop singular directions of Y below tau_rank * s_1, then add
@@ -39,7 +39,7 @@ double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration
 
 // ---- small host linear algebra ------------------------------------------------
 
-// cyclic Jacobi for a symmetric k x k matrix (k <= 16): A is overwritten,
+// cyclic Jacobi for a symmetric k x k matrix (k <= 64): A is overwritten,
 // eigenvalues in w, eigenvectors in the columns of V (row-major)
 void jacobi_eig(int k, double* A, double* w, double* V) {
   for (int i = 0; i < k; ++i)
@@ -185,9 +185,9 @@ mdsdp_status dots(mdsdp_problem P, int npairs, const double* const* a, const dou
   return MDSDP_OK;
 }
 
-// pinned read-back buffer: [0, 64) scalars, [64, 1024) small arrays
+// pinned read-back buffer: [0, 64) scalars, [64, 8192) small arrays
 mdsdp_status read_dev(mdsdp_problem P, const double* dev, int cnt, double* host, hipStream_t s) {
-  if (cnt > 1024 - 64) {
+  if (cnt > 8192 - 64) {
     set_error("read_dev: too many values");
     return MDSDP_EINVAL;
   }
@@ -203,7 +203,7 @@ struct Work {
   double *Ynew, *g, *gnew, *eta, *Heta, *r, *d, *Hd, *U, *tmp, *part, *rrb;
   mdsdp_status init(int n_) {
     n = n_;
-    const size_t vec = (size_t)n * 16;
+    const size_t vec = (size_t)n * PMAX;
     hipError_t e = hipMalloc((void**)&buf, (10 * vec + 4096) * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(solver work)");
     double* p = buf;
@@ -314,7 +314,7 @@ struct RTRState {
 };
 
 mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, int maxinner, int prec,
-                 Work& W, Counters& C, RTRState& st, hipStream_t s) {
+                 Work& W, Counters& C, RTRState& st, hipStream_t s, int verbose = 0) {
   const int n = P->n;
   const long long len = (long long)n * p;
   const double Delta_bar = M_PI * sqrt((double)n);
@@ -331,6 +331,8 @@ mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, i
   for (; it < maxiter; ++it) {
     if (gn <= gtol) break;
     int stop = 0;
+    const long long hv0 = C.hvps;
+    const double Delta_used = Delta;
     CHK(tcg(P, p, Y, W.g, gn, Delta, prec, maxinner, W, C, &stop, s));
     CHK(launch_retract(n, p, Y, W.eta, 1.0, W.Ynew, s));
     double fnew;
@@ -348,6 +350,9 @@ mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, i
       Delta /= 4.0;
     else if (rho > 0.75 && (stop == TCG_NEG || stop == TCG_BOUND))
       Delta = std::min(2.0 * Delta, Delta_bar);
+    if (verbose >= 2)
+      fprintf(stderr, "  [rtr] it=%d f=%.12e gn=%.3e Delta=%.3e rho=%.3e stop=%d inner=%lld %s\n", it, f, gn,
+              Delta_used, rho, stop, C.hvps - hv0, (rho > 0.1 && std::isfinite(fnew)) ? "acc" : "REJ");
     if (rho > 0.1 && std::isfinite(fnew)) {
       std::swap(Y, W.Ynew);
       std::swap(W.g, W.gnew);
@@ -369,8 +374,14 @@ mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, i
 }  // namespace
 
 // ---- Lanczos ----------------------------------------------------------------------
+// Lanczos with full reorthogonalisation on the certificate X = Xt + D - Diag z.
+// Returns the extreme Ritz values; `evec` (nullable) receives up to `nvec`
+// Ritz vectors (each n doubles, consecutive) of the smallest Ritz values; the
+// first is always written, the others only for Ritz values below
+// -neg_rel (1 + |theta_max|).  *nfound counts the vectors written.
 static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t seed, double* lmin, double* lmax,
-                            double* evec, int* iters, bool* converged, hipStream_t s) {
+                            double* evec, int* iters, bool* converged, hipStream_t s, int nvec = 1,
+                            double neg_rel = 0.0, int* nfound = nullptr) {
   const int n = P->n;
   maxit = std::max(2, std::min(maxit, n));
   if (P->lz_cap < maxit + 1) {
@@ -436,12 +447,20 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
   *lmin = th_min;
   *lmax = th_max;
   *iters = k;
-  if (evec) {
-    // Ritz vector V s for the smallest Ritz value
-    MDSDP_HIP(hipMemcpyAsync(h, sv.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
-    CHK(launch_gemv(n, k, V, h, evec, s));
-    MDSDP_HIP(hipStreamSynchronize(s));
+  int found = 0;
+  if (evec && nvec >= 1) {
+    // Ritz vectors V s_i for the smallest Ritz values (the first always)
+    for (int i = 0; i < std::min(nvec, k); ++i) {
+      const double th = i == 0 ? th_min : tridiag_eig(k, al.data(), be.data(), i);
+      if (i > 0 && !(th < -neg_rel * (1.0 + fabs(th_max)))) break;
+      if (i > 0) tridiag_evec(k, al.data(), be.data(), th, sv);
+      MDSDP_HIP(hipMemcpyAsync(h, sv.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+      CHK(launch_gemv(n, k, V, h, evec + (size_t)i * n, s));
+      MDSDP_HIP(hipStreamSynchronize(s));
+      ++found;
+    }
   }
+  if (nfound) *nfound = found;
   return MDSDP_OK;
 }
 
@@ -462,10 +481,13 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->gamma = 2.0;
   o->kappa1 = 0.1;
   o->kappa2 = 10.0;
-  o->p_max = 16;
+  o->p_max = 64;
+  o->n_neg = 4;
   o->tau_rank = 1e-4;
   o->gtol0 = 1e-2;
   o->gtol_min = 1e-10;
+  o->gtol_decay = 1.0;
+  o->gtol_ratio = 0.0;
   o->rtr_maxiter = 50;
   o->tcg_maxinner = 200;
   o->hvp_prec = MDSDP_FP64;
@@ -506,8 +528,16 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     set_error("NULL argument");
     return MDSDP_EINVAL;
   }
-  if (opt->p_max < 1 || opt->p_max > 16 || p0 < 1 || p0 > opt->p_max) {
-    set_error("need 1 <= p0 <= p_max <= 16");
+  if (opt->p_max < 1 || opt->p_max > PMAX || p0 < 1 || p0 > opt->p_max) {
+    set_error("need 1 <= p0 <= p_max <= 64");
+    return MDSDP_EINVAL;
+  }
+  if (!(opt->gtol_decay > 0.0 && opt->gtol_decay <= 1.0)) {
+    set_error("need 0 < gtol_decay <= 1");
+    return MDSDP_EINVAL;
+  }
+  if (opt->n_neg < 0 || opt->n_neg > PMAX) {
+    set_error("need 0 <= n_neg <= 64");
     return MDSDP_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -523,7 +553,10 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   double* Y = Ybuf;
   // normalise rows of the start point
   CHK(launch_retract(n, p, Y, Y, 0.0, Y, s));
-  CHK(mdsdp_set_multiplier(P, nullptr, opt->sigma0, s));
+  if (opt->resume)
+    CHK(mdsdp_set_sigma(P, opt->sigma0));
+  else
+    CHK(mdsdp_set_multiplier(P, nullptr, opt->sigma0, s));
   double sigma = opt->sigma0;
   double eta_max = 1.0;
   bool carry = false;
@@ -533,6 +566,8 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   int k = 0;
   mdsdp_status final_status = MDSDP_ENOCONV;
   double* evec = W.tmp;
+  double gtol = opt->gtol0 / opt->gtol_decay;
+  double prim_ratio = INFINITY;  // ||R|| / (1 + ||b||) of the last outer step
   for (k = 0; k < opt->max_outer; ++k) {
     CHK(mdsdp_set_sigma(P, sigma));
     const int prec = (opt->polish_fp64 && eta_max < opt->polish_eta) ? MDSDP_FP64 : opt->hvp_prec;
@@ -552,9 +587,13 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
         t *= 0.5;
       }
     }
-    const double gtol = std::max(opt->gtol_min, std::min(opt->gtol0, 0.1 * eta_max));
+    {
+      double g = std::min(std::min(opt->gtol0, 0.1 * eta_max), opt->gtol_decay * gtol);
+      if (opt->gtol_ratio > 0.0 && std::isfinite(prim_ratio)) g = std::min(g, opt->gtol_ratio * prim_ratio);
+      gtol = std::max(opt->gtol_min, g);
+    }
     RTRState rs;
-    CHK(rtr(P, p, Y, gtol, opt->rtr_maxiter, opt->tcg_maxinner, prec, W, C, rs, s));
+    CHK(rtr(P, p, Y, gtol, opt->rtr_maxiter, opt->tcg_maxinner, prec, W, C, rs, s, opt->verbose));
     // multiplier update (Algorithm alg1 steps 5-8)
     auto tu = clk::now();
     CHK(mdsdp_update_multiplier(P, p, Y, nullptr, nullptr, P->scal + SC_KKT, s));
@@ -566,7 +605,9 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     double lmin = 0, lmax = 0;
     int eit = 0;
     bool conv = false;
-    CHK(lanczos(P, opt->eig_tol, opt->eig_maxit, opt->seed + (uint64_t)k, &lmin, &lmax, evec, &eit, &conv, s));
+    int nfound = 0;
+    CHK(lanczos(P, opt->eig_tol, opt->eig_maxit, opt->seed + (uint64_t)k, &lmin, &lmax, evec, &eit, &conv, s,
+                std::max(1, opt->n_neg), 1e-12, &nfound));
     C.eig_iters += eit;
     C.t_eig += secs(te, clk::now());
     const double normR = kk[0], bty = kk[1], sumz = kk[2], cx = kk[3];
@@ -601,12 +642,12 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     }
     // rank update: SVD of Y through its Gram matrix (p x p)
     CHK(launch_gram(P, p, Y, Y, s));
-    double G[256];
-    CHK(read_dev(P, P->gram, 256, G, s));
-    double A[256], wv[16], Vv[256];
+    const int pw = P->gram_pw;
+    std::vector<double> G((size_t)pw * pw), A((size_t)p * p), wv(p), Vv((size_t)p * p);
+    CHK(read_dev(P, P->gram, pw * pw, G.data(), s));
     for (int i = 0; i < p; ++i)
-      for (int j = 0; j < p; ++j) A[i * p + j] = G[i * 16 + j];
-    jacobi_eig(p, A, wv, Vv);
+      for (int j = 0; j < p; ++j) A[i * p + j] = G[(size_t)i * pw + j];
+    jacobi_eig(p, A.data(), wv.data(), Vv.data());
     std::vector<int> idx(p);
     for (int i = 0; i < p; ++i) idx[i] = i;
     std::sort(idx.begin(), idx.end(), [&](int x, int y) { return wv[x] > wv[y]; });
@@ -616,25 +657,30 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
       if (sqrt(std::max(0.0, wv[idx[i]])) > opt->tau_rank * s1) ++r;
     r = std::max(1, r);
     const bool neg = lmin < -1e-12 * (1.0 + fabs(lmax));
-    const int dadd = (neg && r + 1 <= opt->p_max) ? 1 : 0;
+    // negative-curvature directions: Ritz vectors of the negative Ritz values
+    int nneg = 0;
+    if (neg && opt->n_neg > 0) nneg = std::min(nfound, opt->n_neg);
+    const int dadd = std::max(0, std::min(nneg, opt->p_max - r));
     const int pnew = r + dadd;
     // M = [V_r, 0] (p x pnew)
-    double M[256];
+    std::vector<double> M((size_t)p * pnew);
     for (int i = 0; i < p; ++i)
-      for (int c = 0; c < pnew; ++c) M[i * pnew + c] = (c < r) ? Vv[i * p + idx[c]] : 0.0;
-    MDSDP_HIP(hipMemcpyAsync(P->gpart, M, p * pnew * sizeof(double), hipMemcpyHostToDevice, s));
-    CHK(launch_rightmul(n, p, pnew, Y, P->gpart, true, W.Ynew, s));
+      for (int c = 0; c < pnew; ++c) M[(size_t)i * pnew + c] = (c < r) ? Vv[i * p + idx[c]] : 0.0;
+    MDSDP_HIP(hipMemcpyAsync(P->gpart + GP_M, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    CHK(launch_rightmul(n, p, pnew, Y, P->gpart + GP_M, true, W.Ynew, s));
     MDSDP_HIP(hipStreamSynchronize(s));
     std::swap(Y, W.Ynew);
     p = pnew;
     p_maxr = std::max(p_maxr, p);
     carry = false;
     if (dadd) {
-      CHK(launch_set_col(n, p, p - 1, evec, W.U, s));
+      // U = [0, v_1, ..., v_dadd]: launch_set_col zeroes the other columns on the first call only
+      for (int j = 0; j < dadd; ++j) CHK(launch_set_col(n, p, r + j, evec + (size_t)j * n, W.U, s, j == 0));
       carry = true;
     }
     // sigma rule, eq. sec5:eq1
     const double ratio = normR / (1.0 + P->normb);
+    prim_ratio = ratio;
     if (ratio < opt->kappa1 * rs.gn)
       sigma = std::max(sigma / opt->gamma, opt->sigma_min);
     else if (ratio > opt->kappa2 * rs.gn)

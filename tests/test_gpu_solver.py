@@ -3,7 +3,10 @@
 * Lanczos certificate eigenpair vs LAPACK on the dense oracle certificate;
 * full solves (dense BQP, q = 10, p0 = 2, FP64 and FP32-tile HVPs): eta_max
   <= 1e-8, value = brute-force minimum (rank-one case) = oracle value;
-* q = 20: value equals the brute-force minimum, FP64 and mixed agree to 1e-8.
+* q = 20: value equals the brute-force minimum, FP64 and mixed agree to 1e-8;
+* q = 30 (n = 466, rank cap 64): the returned factor and multiplier satisfy
+  eta_max <= 1e-8 when the oracle recomputes the residuals (eq. res) from
+  them with dense LAPACK.
 """
 
 import numpy as np
@@ -52,7 +55,7 @@ def test_min_eigpair_matches_dense(q, p):
         assert abs(abs(vv @ V[:, 0]) - 1.0) <= 1e-8
 
 
-def _solve(q, seed, prec, p0=2, tol=1e-8):
+def _solve(q, seed, prec, p0=2, tol=1e-8, keep=False):
     from paper_2512_04406_amd.problem import ORDER_COLEX, Problem
 
     Q, c = bqp_instance(q, seed)
@@ -60,13 +63,14 @@ def _solve(q, seed, prec, p0=2, tol=1e-8):
     opts = prob.default_options()
     opts.tol = tol
     opts.hvp_prec = prec
-    opts.p_max = 16
     n = prob.n
     Y0 = gaussian(n, p0, 100 + seed)
     print(f"[solve] q={q} seed={seed} prec={prec} n={n}", flush=True)
     res = prob.solve(_t(Y0), opts)
     print(f"   value={res.value:.10f} eta={res.eta} outer={res.outer_iters} hvps={res.hvps} p={res.p_final} "
           f"t={res.seconds:.2f}s", flush=True)
+    if keep:
+        return Q, c, res, prob
     return Q, c, res
 
 
@@ -92,3 +96,27 @@ def test_solve_q20_fp64_and_mixed_agree_with_brute_force():
         assert r.status == 0 and max(r.eta) <= 1e-8
         assert abs(r.value - fmin) <= 1e-8 * (1 + abs(fmin))
     assert abs(r64.value - r32.value) <= 1e-8 * (1 + abs(fmin))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_q30_certified_by_oracle(prec):
+    Q, c, res, prob = _solve(30, 0, prec, p0=4, keep=True)
+    assert res.status == 0 and max(res.eta) <= 1e-8
+    rel = bqp.build_relaxation(Q, c, "colex")
+    Y = res.Y.cpu().numpy()
+    Xt = prob.get_multiplier().cpu().numpy()
+    S = Y @ Y.T
+    y = rel_class_average(S, rel)
+    D = D_matrix(rel.b, rel.cls, rel.counts)
+    z = np.einsum("ij,ij->i", (Xt + D) @ Y, Y)
+    X = Xt + D - np.diag(z)
+    eta = alm.kkt_residuals(S, y, X, z, rel.b, rel.cls)
+    print(f"   oracle eta={eta}", flush=True)
+    assert max(eta) <= 2e-8
+    assert abs(float(rel.b @ y) - res.value) <= 1e-10 * (1 + abs(res.value))
+
+
+def rel_class_average(S, rel):
+    from oracle.operators import class_average
+
+    return class_average(S, rel.cls, rel.counts)
