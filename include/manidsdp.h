@@ -35,7 +35,8 @@
  *    become valid when the stream reaches them.
  *  - Argument errors are detected synchronously (MDSDP_EINVAL) before any work
  *    is enqueued.  A problem handle must not be used from two streams at once.
- *  - p may be 1..16 for cost/gradient/HVP (MFMA tiles are 16 wide).
+ *  - p may be 1..128 for every call that takes a factor width (staged in
+ *    widths 16, 32, 64 or 128: MFMA tiles are 16 wide).
  */
 #ifndef MANIDSDP_H
 #define MANIDSDP_H
@@ -55,7 +56,7 @@ typedef enum {
   MDSDP_EHIP = -3,        /* a HIP runtime call failed */
   MDSDP_ENOTORTH = -4,    /* sparse A supports overlap: AA* not diagonal */
   MDSDP_ENONFINITE = -5,  /* NaN/Inf met in an input or a reduction */
-  MDSDP_EUNSUPPORTED = -6,/* e.g. p > 16, no gfx950 device */
+  MDSDP_EUNSUPPORTED = -6,/* e.g. no gfx950 device */
   MDSDP_ENOCONV = -7      /* iteration limit reached before the tolerance */
 } mdsdp_status;
 
@@ -157,7 +158,7 @@ mdsdp_status mdsdp_project_tangent(int32_t n, int32_t p, const double* Y_dev,
 mdsdp_status mdsdp_update_multiplier(mdsdp_problem prob, int32_t p, const double* Y_dev,
                                      double* y_dev, double* z_dev, double* kkt_dev, void* stream);
 /* X v = (Xt + D) v - z o v for k vectors (columns of V, n x k row-major,
- * k <= 16), with z from the last update_multiplier.  FP64. */
+ * k <= 128), with z from the last update_multiplier.  FP64. */
 mdsdp_status mdsdp_certificate_matvec(mdsdp_problem prob, int32_t k, const double* V_dev,
                                       double* XV_dev, void* stream);
 /* Smallest eigenpair and largest eigenvalue of X = Xt + D - Diag(z) by
@@ -178,7 +179,7 @@ typedef struct {
   double tol;          /* stop when eta_max <= tol (eq. res); default 1e-8 */
   int32_t max_outer;   /* default 200 */
   double sigma0, sigma_min, sigma_max, gamma, kappa1, kappa2; /* eq. sec5:eq1 */
-  int32_t p_max;       /* largest factor width, 1..64 */
+  int32_t p_max;       /* largest factor width, 1..128 */
   int32_t n_neg;       /* negative-curvature directions added per outer step (Theorem sec5:thm1) */
   double tau_rank;     /* drop singular directions below tau_rank * s_1 */
   double gtol0, gtol_min;  /* inner tolerance max(gtol_min, min(gtol0, 0.1 eta, gtol_decay * previous)) */

@@ -315,7 +315,7 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   TRY(dalloc(&P->colpart, (size_t)P->nseg * 64 * PMAX));
   TRY(dalloc(&P->wgpart, (size_t)P->nseg * 4));
   TRY(dalloc(&P->zpart, (size_t)(n * PMAX + 255) / 256 + 1));
-  TRY(dalloc(&P->gram, 8192));
+  TRY(dalloc(&P->gram, 2 * GRAM_U));
   TRY(dalloc(&P->gpart, GP_SIZE));
   TRY(dalloc(&P->scal, SC_COUNT));
   TRY(dalloc(&P->bound, 2));
@@ -323,7 +323,7 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   TRY(dalloc(&P->dotpart, (size_t)P->dot_nblk * 8));
   TRY(dalloc((double**)&P->dotptr, 16));
   {
-    hipError_t eh = hipHostMalloc((void**)&P->hbuf, 8192 * sizeof(double), hipHostMallocDefault);
+    hipError_t eh = hipHostMalloc((void**)&P->hbuf, HBUF_LEN * sizeof(double), hipHostMallocDefault);
     if (eh != hipSuccess) {
       mdsdp_status s2 = hip_fail(eh, "hipHostMalloc");
       free_problem(P);
@@ -368,7 +368,7 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
 static mdsdp_status check_p(mdsdp_problem P, int p) {
   if (!P) return einval("problem is NULL");
   if (p < 1 || p > PMAX) {
-    set_error("p must be in [1, 64]");
+    set_error("p must be in [1, 128]");
     return p < 1 ? MDSDP_EINVAL : MDSDP_EUNSUPPORTED;
   }
   return MDSDP_OK;

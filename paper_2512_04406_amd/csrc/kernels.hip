@@ -115,12 +115,13 @@ __device__ __forceinline__ int seg_of_block(int b, int per, int nseg) {
   return s < nseg ? s : -1;
 }
 
-// 64 rows of a staged factor (row pitch PW) into LDS (row pitch PW + 1)
-template <int PW, typename T>
-__device__ __forceinline__ void load_rows(T* sdst, const T* src, int row0, int tid) {
-  for (int i = tid; i < 64 * PW; i += 256) {
-    const int r = i / PW, c = i % PW;
-    sdst[r * (PW + 1) + c] = src[(size_t)(row0 + r) * PW + c];
+// 64 rows x W columns (from column col0) of a staged factor with row pitch SP
+// into LDS (row pitch W + 1)
+template <int W, int SP, typename T>
+__device__ __forceinline__ void load_rows(T* sdst, const T* src, int row0, int col0, int tid) {
+  for (int i = tid; i < 64 * W; i += 256) {
+    const int r = i / W, c = i % W;
+    sdst[r * (W + 1) + c] = src[(size_t)(row0 + r) * SP + col0 + c];
   }
 }
 
@@ -132,28 +133,34 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_stage(int n, int p, int npad, int pw, const double* __restrict__ Y,
                                                const double* __restrict__ U, T* __restrict__ Yp,
                                                T* __restrict__ Up, unsigned long long* bound) {
+  // lanes per row L = min(pw, 64); each lane stages pw / L columns
   __shared__ double smax[2][256];
+  const int L = pw < 64 ? pw : 64;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx / pw, c = idx % pw;
-  const bool in = idx < npad * pw;
-  const double y = (in && r < n && c < p) ? Y[(size_t)r * p + c] : 0.0;
-  const double u = (U && in && r < n && c < p) ? U[(size_t)r * p + c] : 0.0;
-  if (in) {
-    Yp[idx] = (T)y;
-    if (U) Up[idx] = (T)u;
+  const int r = idx / L, c0 = idx % L;
+  const bool in = r < npad;
+  double ny = 0.0, nu = 0.0;
+  for (int c = c0; c < pw; c += L) {
+    const double y = (in && r < n && c < p) ? Y[(size_t)r * p + c] : 0.0;
+    const double u = (U && in && r < n && c < p) ? U[(size_t)r * p + c] : 0.0;
+    if (in) {
+      Yp[(size_t)r * pw + c] = (T)y;
+      if (U) Up[(size_t)r * pw + c] = (T)u;
+    }
+    ny += y * y;
+    nu += u * u;
   }
   if (!bound) return;
-  double ny = y * y, nu = u * u;
-  for (int off = pw >> 1; off >= 1; off >>= 1) {
-    ny += __shfl_xor(ny, off, pw);
-    nu += __shfl_xor(nu, off, pw);
+  for (int off = L >> 1; off >= 1; off >>= 1) {
+    ny += __shfl_xor(ny, off, L);
+    nu += __shfl_xor(nu, off, L);
   }
   smax[0][threadIdx.x] = (in && r < n) ? sqrt(ny) : 0.0;
   smax[1][threadIdx.x] = (in && r < n) ? sqrt(nu) : 0.0;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m0 = 0.0, m1 = 0.0;
-    for (int i = 0; i < 256; i += pw) {
+    for (int i = 0; i < 256; i += L) {
       m0 = fmax(m0, smax[0][i]);
       m1 = fmax(m1, smax[1][i]);
     }
@@ -216,12 +223,17 @@ __global__ __launch_bounds__(256) void k_classsum(KArgs a) {
 // ---------------------------------------------------------------------------
 // residual / product pass
 // ---------------------------------------------------------------------------
+// The FP64 HVP at width 128 is split into two 64-column slices (blockIdx.y):
+// it needs no S tile, so the slices share nothing but the class data reads.
 template <typename T, int MODE, int PW>
 struct ResidLds {
   static constexpr bool NEED_Y = (MODE != M_XMV);
   static constexpr bool SEPARATE_U = (MODE == M_HVP || MODE == M_XMV);
   static constexpr bool HAS_B = (MODE == M_HVP);
-  static constexpr int LPW = PW + 1;
+  static constexpr bool SLICED = (MODE == M_HVP && sizeof(T) == 8 && PW > 64);
+  static constexpr int SW = SLICED ? 64 : PW;  // columns per block
+  static constexpr int NSL = PW / SW;
+  static constexpr int LPW = SW + 1;
   static constexpr size_t slab = 64 * LPW;  // one 64-row slice
   static constexpr size_t nslab = (NEED_Y ? 2 : 0) + (SEPARATE_U ? 2 : 0);
   static constexpr size_t tbuf = 16 * LP;    // one 16 x 16 transpose buffer
@@ -236,7 +248,8 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
   constexpr bool HAS_B = L::HAS_B;
   constexpr bool SEPARATE_U = L::SEPARATE_U;
   constexpr bool NEED_Y = L::NEED_Y;
-  constexpr int NC = PW / 16, LPW = L::LPW;
+  constexpr int SW = L::SW, NC = SW / 16, LPW = L::LPW;
+  const int col0 = L::SLICED ? (int)blockIdx.y * SW : 0;
   const int sidx = seg_of_block(blockIdx.x, a.seg_per_xcd, a.nseg);
   if (sidx < 0) return;
   const Seg sg = a.segs[sidx];
@@ -269,11 +282,11 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
   const T* rY = sYr;
   const T* cU = SEPARATE_U ? sUc : sYc;
   const T* rU = SEPARATE_U ? sUr : sYr;
-  if (NEED_Y) load_rows<PW>(sYc, Yp, sg.J * 64, tid);
-  if (SEPARATE_U) load_rows<PW>(sUc, Up, sg.J * 64, tid);
+  if (NEED_Y) load_rows<SW, PW>(sYc, Yp, sg.J * 64, col0, tid);
+  if (SEPARATE_U) load_rows<SW, PW>(sUc, Up, sg.J * 64, col0, tid);
 
   const double sigma = a.sigma;
-  const int nk = min(PW / 4, a.nk);
+  const int nk = min(SW / 4, a.nk);
   v4 accC[4][NC];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -285,8 +298,8 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
 
   for (int I = sg.I0; I <= sg.I1; ++I) {
     __syncthreads();
-    if (NEED_Y) load_rows<PW>(sYr, Yp, I * 64, tid);
-    if (SEPARATE_U) load_rows<PW>(sUr, Up, I * 64, tid);
+    if (NEED_Y) load_rows<SW, PW>(sYr, Yp, I * 64, col0, tid);
+    if (SEPARATE_U) load_rows<SW, PW>(sUr, Up, I * 64, col0, tid);
     __syncthreads();
     const long long t = (long long)sg.J * (sg.J + 1) / 2 + I;
     const bool diag = (I == sg.J);
@@ -406,7 +419,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     // row-side partial of this tile: rows w*16 + drow(lk, v), columns c*16 + li
-    T* rp = (T*)a.rowpart + ((size_t)t * 64 + w * 16) * PW + li;
+    T* rp = (T*)a.rowpart + ((size_t)t * 64 + w * 16) * PW + col0 + li;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -433,7 +446,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
           sum += cred[0 * 256 + pc * 16 + li];
           sum += cred[1 * 256 + pc * 16 + li];
           sum += cred[2 * 256 + pc * 16 + li];
-          cp[(sc * 16 + li) * PW + c * 16 + pc] = sum;
+          cp[(sc * 16 + li) * PW + col0 + c * 16 + pc] = sum;
         }
       }
     }
@@ -491,21 +504,38 @@ __device__ __forceinline__ double sum16(double v) {
   return v;
 }
 
-// threads: one per (row, column) of the pw-padded factor
+// Threads: L = min(pw, 64) lanes per row; lane c0 owns columns c0, c0 + L
+// (pw = 128); row dots are butterfly sums over the L lanes.
+constexpr int RMAXC = 2;  // columns per lane at most
+
+__device__ __forceinline__ int row_lanes(int pw) { return pw < 64 ? pw : 64; }
+
 __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __restrict__ Y,
                                                   double* __restrict__ egrad, double* __restrict__ rgrad,
                                                   double* __restrict__ zvec) {
+  const int L = row_lanes(ra.pw);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx / ra.pw, k = idx % ra.pw;
+  const int r = idx / L, c0 = idx % L;
   const bool in = r < ra.n;
-  const bool kin = in && k < ra.p;
-  double gy = kin ? row_sum<double>(ra, r, k) : 0.0;
-  const double y = kin ? Y[(size_t)r * ra.p + k] : 0.0;
-  const double z = sum_row(gy * y, ra.pw);
-  if (in && k == 0) zvec[r] = z;
-  if (kin) {
-    if (egrad) egrad[(size_t)r * ra.p + k] = 2.0 * gy;
-    if (rgrad) rgrad[(size_t)r * ra.p + k] = 2.0 * (gy - z * y);
+  double gy[RMAXC], y[RMAXC];
+  double zp = 0.0;
+#pragma unroll
+  for (int j = 0; j < RMAXC; ++j) {
+    const int k = c0 + j * L;
+    const bool kin = in && k < ra.p && k < ra.pw;
+    gy[j] = kin ? row_sum<double>(ra, r, k) : 0.0;
+    y[j] = kin ? Y[(size_t)r * ra.p + k] : 0.0;
+    zp += gy[j] * y[j];
+  }
+  const double z = sum_row(zp, L);
+  if (in && c0 == 0) zvec[r] = z;
+#pragma unroll
+  for (int j = 0; j < RMAXC; ++j) {
+    const int k = c0 + j * L;
+    if (in && k < ra.p && k < ra.pw) {
+      if (egrad) egrad[(size_t)r * ra.p + k] = 2.0 * gy[j];
+      if (rgrad) rgrad[(size_t)r * ra.p + k] = 2.0 * (gy[j] - z * y[j]);
+    }
   }
 }
 
@@ -514,52 +544,70 @@ __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __res
                                                  const double* __restrict__ U, const double* __restrict__ gram,
                                                  const double* __restrict__ zvec, double sigma, int fp32, int riem,
                                                  double* __restrict__ HU) {
+  const int pw = ra.pw, L = row_lanes(pw);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int pw = ra.pw;
-  const int r = idx / pw, k = idx % pw;
+  const int r = idx / L, c0 = idx % L;
   const bool in = r < ra.n;
-  const bool kin = in && k < ra.p;
-  double h = kin ? row_sum<T>(ra, r, k) : 0.0;
   // low-rank terms: sigma [Y (Y^T U + U^T Y) + U (Y^T Y)] (FP64 tiles) or
   // sigma [Y (U^T Y) + U (Y^T Y)] (FP32 tiles carry S U entry-wise)
   const double* YtY = gram;
-  const double* YtU = gram + 4096;
-  double lr = 0.0;
-  if (kin) {
-    for (int i = 0; i < ra.p; ++i) {
-      const double yi = Y[(size_t)r * ra.p + i];
-      const double ui = U[(size_t)r * ra.p + i];
-      double w1 = YtU[k * pw + i];
-      if (!fp32) w1 += YtU[i * pw + k];
-      lr += yi * w1 + ui * YtY[i * pw + k];
+  const double* YtU = gram + GRAM_U;
+  double Ht[RMAXC], y[RMAXC], u[RMAXC];
+  double dp = 0.0;
+#pragma unroll
+  for (int j = 0; j < RMAXC; ++j) {
+    const int k = c0 + j * L;
+    const bool kin = in && k < ra.p && k < pw;
+    double h = kin ? row_sum<T>(ra, r, k) : 0.0;
+    double lr = 0.0;
+    if (kin) {
+      for (int i = 0; i < ra.p; ++i) {
+        const double yi = Y[(size_t)r * ra.p + i];
+        const double ui = U[(size_t)r * ra.p + i];
+        double w1 = YtU[k * pw + i];
+        if (!fp32) w1 += YtU[i * pw + k];
+        lr += yi * w1 + ui * YtY[i * pw + k];
+      }
+    }
+    Ht[j] = kin ? 2.0 * (h + sigma * lr) : 0.0;
+    y[j] = kin ? Y[(size_t)r * ra.p + k] : 0.0;
+    u[j] = kin ? U[(size_t)r * ra.p + k] : 0.0;
+    dp += Ht[j] * y[j];
+  }
+  const double d = riem ? sum_row(dp, L) : 0.0;
+  const double zr = (riem && in) ? zvec[r] : 0.0;
+#pragma unroll
+  for (int j = 0; j < RMAXC; ++j) {
+    const int k = c0 + j * L;
+    if (in && k < ra.p && k < pw) {
+      const double v = riem ? Ht[j] - d * y[j] - 2.0 * zr * u[j] : Ht[j];
+      HU[(size_t)r * ra.p + k] = v;
     }
   }
-  double Ht = kin ? 2.0 * (h + sigma * lr) : 0.0;
-  const double y = kin ? Y[(size_t)r * ra.p + k] : 0.0;
-  const double u = kin ? U[(size_t)r * ra.p + k] : 0.0;
-  if (riem) {
-    const double d = sum_row(Ht * y, pw);
-    Ht = Ht - d * y - 2.0 * (in ? zvec[r] : 0.0) * u;
-  }
-  if (kin) HU[(size_t)r * ra.p + k] = Ht;
 }
 
 __global__ __launch_bounds__(256) void k_row_mult(RowArgs ra, const double* __restrict__ Y,
                                                   double* __restrict__ zmult, double* __restrict__ zout,
                                                   double* __restrict__ zpart) {
   __shared__ double red[256];
+  const int L = row_lanes(ra.pw);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx / ra.pw, k = idx % ra.pw;
+  const int r = idx / L, c0 = idx % L;
   const bool in = r < ra.n;
-  const bool kin = in && k < ra.p;
-  const double o = kin ? row_sum<double>(ra, r, k) : 0.0;
-  const double y = kin ? Y[(size_t)r * ra.p + k] : 0.0;
-  const double z = sum_row(o * y, ra.pw);
-  if (in && k == 0) {
+  double zp = 0.0;
+#pragma unroll
+  for (int j = 0; j < RMAXC; ++j) {
+    const int k = c0 + j * L;
+    const bool kin = in && k < ra.p && k < ra.pw;
+    const double o = kin ? row_sum<double>(ra, r, k) : 0.0;
+    zp += o * (kin ? Y[(size_t)r * ra.p + k] : 0.0);
+  }
+  const double z = sum_row(zp, L);
+  if (in && c0 == 0) {
     zmult[r] = z;
     if (zout) zout[r] = z;
   }
-  red[threadIdx.x] = (in && k == 0) ? z : 0.0;
+  red[threadIdx.x] = (in && c0 == 0) ? z : 0.0;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
@@ -570,11 +618,14 @@ __global__ __launch_bounds__(256) void k_row_mult(RowArgs ra, const double* __re
 
 __global__ __launch_bounds__(256) void k_row_xmv(RowArgs ra, const double* __restrict__ V,
                                                  const double* __restrict__ zmult, double* __restrict__ XV) {
+  const int L = row_lanes(ra.pw);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx / ra.pw, k = idx % ra.pw;
-  if (r >= ra.n || k >= ra.p) return;
-  const double o = row_sum<double>(ra, r, k);
-  XV[(size_t)r * ra.p + k] = o - zmult[r] * V[(size_t)r * ra.p + k];
+  const int r = idx / L, c0 = idx % L;
+  if (r >= ra.n) return;
+  for (int k = c0; k < ra.p && k < ra.pw; k += L) {
+    const double o = row_sum<double>(ra, r, k);
+    XV[(size_t)r * ra.p + k] = o - zmult[r] * V[(size_t)r * ra.p + k];
+  }
 }
 
 // scalar reduction (single block, fixed order)
@@ -638,15 +689,16 @@ __global__ __launch_bounds__(256) void k_scalars(int mode, const double* __restr
 
 // Gram matrices Y^T Y and Y^T U (pw x pw, FP64, row pitch pw) with MFMA over
 // 4-row chunks.  The NC x NC grid of 16 x 16 block pairs is spread over the
-// four waves (NC = 4: wave w owns block row i = w; NC = 2: one pair per wave);
-// for NC = 1 the waves split the rows instead.  Every (block, row group)
+// four waves and over NGRP groups (blockIdx.y) of at most 16 pairs, four per
+// wave; for NC = 1 the waves split the rows instead.  Every (block, row group)
 // writes its own partial; a fixed-order final sum follows.
 template <int PW>
 struct GramSplit {
   static constexpr int NC = PW / 16;
   static constexpr int NPAIR = NC * NC;
   static constexpr int RS = NPAIR >= 4 ? 1 : 4 / NPAIR;   // row groups
-  static constexpr int PPW = NPAIR >= 4 ? NPAIR / 4 : 1;  // pairs per wave
+  static constexpr int PPW = NPAIR >= 16 ? 4 : (NPAIR >= 4 ? NPAIR / 4 : 1);  // pairs per wave
+  static constexpr int NGRP = NPAIR >= 16 ? NPAIR / 16 : 1;                    // pair groups
 };
 
 template <int PW>
@@ -657,7 +709,7 @@ __global__ __launch_bounds__(256) void k_gram_part(int n, int p, const double* _
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const int per = (n + gridDim.x - 1) / gridDim.x;
   const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
-  const int rg = w % RS, pbase = (w / RS) * PPW;
+  const int rg = w % RS, pbase = blockIdx.y * 4 * PPW + (w / RS) * PPW;
   v4d ayy[PPW], ayu[PPW];
 #pragma unroll
   for (int q = 0; q < PPW; ++q) {
@@ -694,14 +746,14 @@ __global__ __launch_bounds__(256) void k_gram_part(int n, int p, const double* _
 
 __global__ __launch_bounds__(256) void k_gram_final(int nblk, int len, const double* __restrict__ part,
                                                     double* __restrict__ gram, int pw) {
-  // part: nblk x (2 pw^2); gram: Y^T Y at [0, pw^2), Y^T U at [4096, 4096 + pw^2)
+  // part: nblk x (2 pw^2); gram: Y^T Y at [0, pw^2), Y^T U at [GRAM_U, GRAM_U + pw^2)
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= len) return;
   double s = 0.0;
 #pragma unroll 8
   for (int b = 0; b < nblk; ++b) s += part[(size_t)b * len + e];
   const int pw2 = pw * pw;
-  gram[e < pw2 ? e : 4096 + (e - pw2)] = s;
+  gram[e < pw2 ? e : GRAM_U + (e - pw2)] = s;
 }
 
 // retraction and tangent projection: one thread per row, any p
@@ -872,7 +924,7 @@ __global__ __launch_bounds__(256) void k_tcg_update1(int n, int p, const double*
   double rr = 0.0;
   if (i < n) {
     const size_t o = (size_t)i * p;
-    double rn[64];
+    double rn[PMAX];
     double dr = 0.0;
     for (int k = 0; k < p; ++k) {
       eta[o + k] += alpha * d[o + k];
@@ -903,7 +955,7 @@ __global__ __launch_bounds__(256) void k_tcg_update2(int n, int p, const double*
   if (i >= n) return;
   const double beta = *beta_dev;
   const size_t o = (size_t)i * p;
-  double dn[64];
+  double dn[PMAX];
   double dd = 0.0;
   for (int k = 0; k < p; ++k) {
     dn[k] = -r[o + k] + beta * d[o + k];
@@ -918,7 +970,7 @@ __global__ __launch_bounds__(256) void k_rightmul(int n, int p, int q, const dou
                                                   double* __restrict__ Yout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double out[64];
+  double out[PMAX];
   double nrm = 0.0;
   for (int c = 0; c < q; ++c) {
     double s = 0.0;
@@ -1344,7 +1396,7 @@ static KArgs make_args(mdsdp_problem P) {
 static unsigned seg_grid(mdsdp_problem P) { return (unsigned)(8 * ((P->nseg + 7) / 8)); }
 
 // factor width of the staged tiles: 16, 32 or 64 columns
-int pw_of(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : 64); }
+int pw_of(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : (p <= 64 ? 64 : 128)); }
 
 #define PW_DISPATCH(pw, ...)      \
   do {                            \
@@ -1354,8 +1406,11 @@ int pw_of(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : 64); }
     } else if ((pw) == 32) {      \
       constexpr int PWV = 32;     \
       __VA_ARGS__;                \
-    } else {                      \
+    } else if ((pw) == 64) {      \
       constexpr int PWV = 64;     \
+      __VA_ARGS__;                \
+    } else {                      \
+      constexpr int PWV = 128;    \
       __VA_ARGS__;                \
     }                             \
   } while (0)
@@ -1384,7 +1439,7 @@ mdsdp_status launch_stage(mdsdp_problem P, int p, const double* Y, const double*
   timer_begin(P, s, "stage");
   unsigned long long* bnd = P->bqp_q > 0 ? nullptr : P->bound;
   if (bnd) MDSDP_HIP(hipMemsetAsync(P->bound, 0, 2 * sizeof(unsigned long long), s));
-  const long long cnt = (long long)P->npad * P->pw;
+  const long long cnt = (long long)P->npad * std::min(P->pw, 64);
   if (fp32)
     k_stage<float><<<blocks_for(cnt, 256), 256, 0, s>>>(P->n, p, P->npad, P->pw, Y, U, (float*)P->Yp,
                                                          (float*)P->Up, bnd);
@@ -1494,7 +1549,7 @@ static mdsdp_status resid_go(mdsdp_problem P, const KArgs& a, unsigned g, hipStr
                                   (int)L::bytes));
     attr_set[dev] = true;
   }
-  k_resid<T, MODE, PW><<<g, 256, L::bytes, s>>>(a);
+  k_resid<T, MODE, PW><<<dim3(g, L::NSL), 256, L::bytes, s>>>(a);
   return MDSDP_OK;
 }
 
@@ -1552,7 +1607,7 @@ mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* 
   const int len = 2 * gpw * gpw;
   int nparts = nblk;
   PW_DISPATCH(gpw, {
-    k_gram_part<PWV><<<nblk, 256, 0, s>>>(P->n, p, Y, U, P->gpart + GP_GRAM);
+    k_gram_part<PWV><<<dim3(nblk, GramSplit<PWV>::NGRP), 256, 0, s>>>(P->n, p, Y, U, P->gpart + GP_GRAM);
     nparts = nblk * GramSplit<PWV>::RS;
   });
   k_gram_final<<<(len + 255) / 256, 256, 0, s>>>(nparts, len, P->gpart + GP_GRAM, P->gram, gpw);
@@ -1565,7 +1620,7 @@ mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, doubl
                                   double* f, hipStream_t s) {
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_grad");
-  k_row_grad<<<blocks_for((long long)P->n * P->pw, 256), 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
+  k_row_grad<<<blocks_for((long long)P->n * std::min(P->pw, 64), 256), 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
   k_scalars<<<1, 256, 0, s>>>(M_GRAD, P->wgpart, P->nseg, nullptr, 0, P->gpart + GP_BTY, 64, P->sigma, P->scal, f,
                               nullptr);
   timer_end(P, s);
@@ -1578,10 +1633,10 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_hvp");
   if (fp32)
-    k_row_hvp<float><<<blocks_for((long long)P->n * P->pw, 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec, P->sigma,
+    k_row_hvp<float><<<blocks_for((long long)P->n * std::min(P->pw, 64), 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec, P->sigma,
                                                                             1, riem, HU);
   else
-    k_row_hvp<double><<<blocks_for((long long)P->n * P->pw, 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec,
+    k_row_hvp<double><<<blocks_for((long long)P->n * std::min(P->pw, 64), 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec,
                                                                              P->sigma, 0, riem, HU);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
@@ -1591,7 +1646,7 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
 mdsdp_status launch_rowfinal_mult(mdsdp_problem P, int p, const double* Y, double* z, double* kkt,
                                   hipStream_t s) {
   RowArgs ra = row_args(P, p);
-  const unsigned nblk = blocks_for((long long)P->n * P->pw, 256);
+  const unsigned nblk = blocks_for((long long)P->n * std::min(P->pw, 64), 256);
   k_row_mult<<<nblk, 256, 0, s>>>(ra, Y, P->zmult, z, P->zpart);
   k_scalars<<<1, 256, 0, s>>>(M_MULT, P->wgpart, P->nseg, P->zpart, (int)nblk, P->gpart + GP_BTY, 64, P->sigma,
                               P->scal, nullptr, kkt);
@@ -1601,7 +1656,7 @@ mdsdp_status launch_rowfinal_mult(mdsdp_problem P, int p, const double* Y, doubl
 
 mdsdp_status launch_rowfinal_xmv(mdsdp_problem P, int k, const double* V, double* XV, hipStream_t s) {
   RowArgs ra = row_args(P, k);
-  k_row_xmv<<<blocks_for((long long)P->n * P->pw, 256), 256, 0, s>>>(ra, V, P->zmult, XV);
+  k_row_xmv<<<blocks_for((long long)P->n * std::min(P->pw, 64), 256), 256, 0, s>>>(ra, V, P->zmult, XV);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }

@@ -29,16 +29,18 @@ namespace mdsdp {
 
 constexpr int TS = 64;          // tile side
 constexpr int SB = 16;          // MFMA sub-block side
-constexpr int PMAX = 64;        // largest factor width (p <= 64)
+constexpr int PMAX = 128;       // largest factor width (p <= 128)
+constexpr int GRAM_U = PMAX * PMAX;  // offset of Y^T U in the Gram buffer
+constexpr int HBUF_LEN = 64 + PMAX * PMAX;  // pinned read-back buffer (doubles)
 constexpr int TSLOTS = TS * TS;  // slots per tile
 constexpr int LP = 17;          // LDS row pitch (elements) for 16-wide rows
 constexpr uint32_t CLS_MASK = 0x3FFFFFFFu;
 constexpr uint32_t OWNER_BIT = 0x40000000u;
 
 // carve of the `gpart` scratch (doubles): Gram partials (<= 32 blocks of
-// 2 x 64 x 64), b^T y partials, degree-0 BQP partials, host-built p x p matrix
+// 2 x 128 x 128), b^T y partials, degree-0 BQP partials, host-built p x p matrix
 constexpr size_t GP_GRAM = 0;
-constexpr size_t GP_BTY = 262144;
+constexpr size_t GP_BTY = 32 * 2 * PMAX * PMAX;
 constexpr size_t GP_BQP0 = GP_BTY + 64;
 constexpr size_t GP_M = GP_BQP0 + 4096;
 constexpr size_t GP_SIZE = GP_M + PMAX * PMAX;

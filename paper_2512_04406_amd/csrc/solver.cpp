@@ -39,7 +39,7 @@ double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration
 
 // ---- small host linear algebra ------------------------------------------------
 
-// cyclic Jacobi for a symmetric k x k matrix (k <= 64): A is overwritten,
+// cyclic Jacobi for a symmetric k x k matrix (k <= 128): A is overwritten,
 // eigenvalues in w, eigenvectors in the columns of V (row-major)
 void jacobi_eig(int k, double* A, double* w, double* V) {
   for (int i = 0; i < k; ++i)
@@ -185,9 +185,9 @@ mdsdp_status dots(mdsdp_problem P, int npairs, const double* const* a, const dou
   return MDSDP_OK;
 }
 
-// pinned read-back buffer: [0, 64) scalars, [64, 8192) small arrays
+// pinned read-back buffer: [0, 64) scalars, [64, HBUF_LEN) small arrays
 mdsdp_status read_dev(mdsdp_problem P, const double* dev, int cnt, double* host, hipStream_t s) {
-  if (cnt > 8192 - 64) {
+  if (cnt > HBUF_LEN - 64) {
     set_error("read_dev: too many values");
     return MDSDP_EINVAL;
   }
@@ -481,7 +481,7 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->gamma = 2.0;
   o->kappa1 = 0.1;
   o->kappa2 = 10.0;
-  o->p_max = 64;
+  o->p_max = 128;
   o->n_neg = 4;
   o->tau_rank = 1e-4;
   o->gtol0 = 1e-2;
@@ -529,7 +529,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     return MDSDP_EINVAL;
   }
   if (opt->p_max < 1 || opt->p_max > PMAX || p0 < 1 || p0 > opt->p_max) {
-    set_error("need 1 <= p0 <= p_max <= 64");
+    set_error("need 1 <= p0 <= p_max <= 128");
     return MDSDP_EINVAL;
   }
   if (!(opt->gtol_decay > 0.0 && opt->gtol_decay <= 1.0)) {
@@ -537,7 +537,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     return MDSDP_EINVAL;
   }
   if (opt->n_neg < 0 || opt->n_neg > PMAX) {
-    set_error("need 0 <= n_neg <= 64");
+    set_error("need 0 <= n_neg <= 128");
     return MDSDP_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;

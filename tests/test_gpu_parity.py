@@ -1,7 +1,7 @@
 """GPU parity of the HIP hot path against the FP64 oracle (element by element).
 
 Cases span one ragged tile (n = 7, 22), several 64-tiles with ragged tails
-(n = 79, 211, 466, 821) and p = 1..64 (staged widths 16, 32 and 64).  Inputs: random (Q, c), Y with unit
+(n = 79, 211, 466, 821) and p = 1..128 (staged widths 16, 32, 64 and 128).  Inputs: random (Q, c), Y with unit
 rows, tangent U, a multiplier Xt with A(Xt) = 0, sigma > 0.  FP64 outputs must
 agree to 1e-10 relative (Frobenius, scaled by the reference's norm); class
 averages to 1e-12 absolute on values of size <= 1; the FP32-tile HVP is
@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 CASES = [(2, 3), (5, 2), (6, 7), (10, 2), (12, 5), (20, 4), (30, 16), (40, 7),
-         (6, 40), (12, 17), (20, 32), (30, 45), (40, 64)]
+         (6, 40), (12, 17), (20, 32), (30, 45), (40, 64), (12, 100), (20, 128), (40, 77)]
 
 
 def _rel(a, b):
@@ -100,7 +100,7 @@ def test_class_average_parity(q, p, structured):
     assert np.max(np.abs(y - y_ref)) <= 1e-12
 
 
-@pytest.mark.parametrize("q,p", [(6, 3), (12, 5), (30, 16), (40, 4), (20, 33), (30, 64)])
+@pytest.mark.parametrize("q,p", [(6, 3), (12, 5), (30, 16), (40, 4), (20, 33), (30, 64), (20, 100)])
 @pytest.mark.parametrize("structured", [True, False])
 def test_update_multiplier_and_certificate_parity(q, p, structured):
     rel, sub, prob, Xt, Y, U, sigma = _case(q, p, structured=structured)
@@ -192,7 +192,7 @@ def test_nonzero_C_parity():
     assert _rel(H.cpu().numpy(), sub.rhess(Y, U)) <= 1e-10
 
 
-@pytest.mark.parametrize("q,p", [(4, 3), (9, 16), (25, 5), (9, 29), (25, 64)])
+@pytest.mark.parametrize("q,p", [(4, 3), (9, 16), (25, 5), (9, 29), (25, 64), (9, 128)])
 def test_structured_matches_generic_class_sums(q, p):
     """The class-map-free BQP kernels and the generic fixed-point class map
     path give the same class averages (both are within rounding of the
@@ -215,3 +215,26 @@ def test_structured_matches_generic_class_sums(q, p):
     ha, hb = a.hvp(Yt, Ut, FP64), b.hvp(Yt, Ut, FP64)
     torch.cuda.synchronize()
     assert float((ha - hb).norm() / hb.norm()) <= 1e-12
+
+
+def test_width_switching_on_one_problem():
+    """Calls with different factor widths (and a certificate eigensolve in
+    between, which stages width 1) on one problem must each match the
+    oracle: no staged width may leak from one call into the next."""
+    from paper_2512_04406_amd.problem import FP32, FP64
+
+    rel, sub, prob, Xt, Y0, U0, sigma = _case(20, 3, structured=True)
+    for p in (100, 5, 40, 17, 128, 2):
+        Y = gaussian(rel.n, p, 7000 + p)
+        Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+        U = proj_tangent(Y, gaussian(rel.n, p, 8000 + p))
+        Yt, Ut = _t(Y), _t(U)
+        print(f"[width] p={p}", flush=True)
+        f, eg, rg = prob.cost_grad(Yt)
+        h64 = prob.hvp(Yt, Ut, FP64)
+        prob.min_eigpair(tol=1e-8, maxit=50)
+        h32 = prob.hvp(Yt, Ut, FP32)
+        torch.cuda.synchronize()
+        assert _rel(rg.cpu().numpy(), sub.rgrad(Y)) <= 1e-10
+        assert _rel(h64.cpu().numpy(), sub.rhess(Y, U)) <= 1e-10
+        assert _rel(h32.cpu().numpy(), sub.rhess(Y, U)) <= 1e-4
