@@ -186,6 +186,9 @@ typedef struct {
   double gtol_decay;   /* in (0, 1]; 1 = tolerance follows eta alone */
   double gtol_ratio;   /* > 0: also cap the tolerance at gtol_ratio ||R|| / (1 + ||b||), the primal
                           measure of the sigma rule (eq. sec5:eq1); <= 0: no such cap */
+  double gtol_stall;   /* > 0: when an RTR call starts below its tolerance (takes no step), cap all
+                          later tolerances at gtol_stall * ||grad||; default 0.1; <= 0: off */
+  int32_t sigma_hold;  /* 1: do not decrease sigma after an RTR call that stopped at rtr_maxiter */
   int32_t rtr_maxiter, tcg_maxinner;
   int32_t hvp_prec;    /* mdsdp_prec for tCG HVPs */
   int32_t polish_fp64; /* switch HVPs to FP64 once eta_max < polish_eta */

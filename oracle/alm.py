@@ -27,9 +27,15 @@ Readings of points the paper leaves open (each also listed in the design doc):
 * inner tolerance: RTR stops at ||grad|| <= max(gtol_min, min(gtol0, 0.1 eta_max^k,
   gtol_decay * previous tolerance, gtol_ratio ||R^k|| / (1 + ||b||))); the decay keeps
   the tolerances of an inexact ALM going to zero when the residuals stall, the
-  ratio term ties the tolerance to the primal measure of the sigma rule.
+  ratio term ties the tolerance to the primal measure of the sigma rule, and
+  whenever RTR starts below its tolerance (takes no step) every later tolerance
+  is capped at gtol_stall * ||grad|| (otherwise the multiplier update alone
+  repeats without moving Y).
 * sigma constants: sigma_0 = 1, sigma_min = 1e-3, sigma_max = 1e6, gamma = 2,
-  kappa_1 = 0.1, kappa_2 = 10 (the paper states none).
+  kappa_1 = 0.1, kappa_2 = 10 (the paper states none); with sigma_hold the
+  decrease branch of eq. sec5:eq1 is skipped after an RTR call that stopped at
+  its iteration cap (its gradient norm then measures the unfinished
+  subproblem rather than a dual residual).
 * eigenvector sign: the largest-magnitude component is made positive.
 
 Parity: not pinned on iterates; the result is pinned by brute force (q <= 16,
@@ -68,6 +74,8 @@ class ALMOptions:
     gtol_min: float = 1e-10
     gtol_decay: float = 1.0
     gtol_ratio: float = 0.0
+    gtol_stall: float = 0.1
+    sigma_hold: bool = True
     rtr_maxiter: int = 50
     neg_tol: float = 1e-12
 
@@ -130,6 +138,7 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
     eta_max = 1.0
     gtol = opts.gtol0 / opts.gtol_decay
     prim_ratio = None
+    stall_cap = math.inf
     hist = []
     normb = float(np.linalg.norm(b))
     y = z = X = None
@@ -141,8 +150,10 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
         g = min(opts.gtol0, 0.1 * eta_max, opts.gtol_decay * gtol)
         if opts.gtol_ratio > 0.0 and prim_ratio is not None:
             g = min(g, opts.gtol_ratio * prim_ratio)
-        gtol = max(opts.gtol_min, g)
+        gtol = max(opts.gtol_min, min(g, stall_cap))
         res = rtr(sub, Y, gtol, maxiter=opts.rtr_maxiter)
+        if opts.gtol_stall > 0.0 and res.iters == 0 and res.gradnorm > 0.0:
+            stall_cap = min(stall_cap, opts.gtol_stall * res.gradnorm)
         Y = res.Y
         S = Y @ Y.T
         Z = S if C is None else S + C
@@ -182,7 +193,8 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
         # sigma rule, eq. sec5:eq1
         ratio = float(np.linalg.norm(Rq)) / (1.0 + normb)
         prim_ratio = ratio
-        if ratio < opts.kappa1 * res.gradnorm:
+        unsolved = res.gradnorm > gtol  # RTR stopped at its iteration cap
+        if ratio < opts.kappa1 * res.gradnorm and not (opts.sigma_hold and unsolved):
             sigma = max(sigma / opts.gamma, opts.sigma_min)
         elif ratio > opts.kappa2 * res.gradnorm:
             sigma = min(opts.gamma * sigma, opts.sigma_max)

@@ -31,6 +31,7 @@ class Options(C.Structure):
                 ("sigma_max", _f64), ("gamma", _f64), ("kappa1", _f64), ("kappa2", _f64),
                 ("p_max", _i32), ("n_neg", _i32), ("tau_rank", _f64), ("gtol0", _f64), ("gtol_min", _f64),
                 ("gtol_decay", _f64), ("gtol_ratio", _f64),
+                ("gtol_stall", _f64), ("sigma_hold", _i32),
                 ("rtr_maxiter", _i32), ("tcg_maxinner", _i32), ("hvp_prec", _i32),
                 ("polish_fp64", _i32), ("polish_eta", _f64), ("eig_tol", _f64), ("eig_maxit", _i32),
                 ("time_limit_s", _f64), ("verbose", _i32), ("seed", _u64),

@@ -7,7 +7,16 @@
 // Readings of points the paper leaves open (same as the oracle's):
 //  * RTR constants rho' = 0.1, kappa = 0.1, theta = 1, Delta_bar = pi sqrt(n),
 //    Delta_0 = Delta_bar / 8 (Absil-Baker-Gallivan trust region);
-//  * inner tolerance max(gtol_min, min(gtol0, 0.1 eta_max, gtol_decay * previous tolerance));
+//  * inner tolerance max(gtol_min, min(gtol0, 0.1 eta_max, gtol_decay * previous tolerance,
+//    gtol_ratio ||R|| / (1 + ||b||), stall cap)); the stall cap becomes
+//    gtol_stall ||grad|| whenever an RTR call starts below its tolerance;
+//  * the certificate Lanczos starts from the previous Ritz vector plus a
+//    random component and stops when the error estimate of theta_min
+//    (residual, or residual^2 / Ritz gap) is below eig_tol (1 + |theta_max|);
+//    when it stops unconverged, eta_d uses theta_min minus that estimate;
+//  * with sigma_hold, sigma is not decreased after an RTR call that stopped
+//    at its iteration cap (its gradient norm then measures the unfinished
+//    subproblem, not the dual residual of eq. sec5:eq1);
 //  * carried direction: backtracking t = sqrt(n), sqrt(n)/2, ... along
 //    R_[Y,0](t [0, v]) until Psi_k decreases, then RTR;
 //  * rank rule: drop singular directions of Y below tau_rank * s_1, then add
@@ -381,7 +390,8 @@ mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, i
 // -neg_rel (1 + |theta_max|).  *nfound counts the vectors written.
 static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t seed, double* lmin, double* lmax,
                             double* evec, int* iters, bool* converged, hipStream_t s, int nvec = 1,
-                            double neg_rel = 0.0, int* nfound = nullptr) {
+                            double neg_rel = 0.0, int* nfound = nullptr, const double* warm = nullptr,
+                            double* resid_out = nullptr, bool use_gap = false) {
   const int n = P->n;
   maxit = std::max(2, std::min(maxit, n));
   if (P->lz_cap < maxit + 1) {
@@ -402,6 +412,24 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
   for (double x : v0) nrm += x * x;
   nrm = sqrt(nrm);
   for (double& x : v0) x /= nrm;
+  if (warm) {
+    // previous Ritz vector plus a 0.1-weighted random unit vector
+    std::vector<double> wv(n);
+    MDSDP_HIP(hipMemcpyAsync(wv.data(), warm, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    MDSDP_HIP(hipStreamSynchronize(s));
+    double wn = 0.0;
+    for (double x : wv) wn += x * x;
+    wn = sqrt(wn);
+    if (wn > 0.0 && std::isfinite(wn)) {
+      double t = 0.0;
+      for (int i = 0; i < n; ++i) {
+        v0[i] = wv[i] / wn + 0.1 * v0[i];
+        t += v0[i] * v0[i];
+      }
+      t = sqrt(t);
+      for (double& x : v0) x /= t;
+    }
+  }
   MDSDP_HIP(hipMemcpyAsync(V, v0.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
   MDSDP_HIP(hipStreamSynchronize(s));
   std::vector<double> al, be;
@@ -432,8 +460,16 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
     th_min = tridiag_eig(k, al.data(), be.data(), 0);
     th_max = tridiag_eig(k, al.data(), be.data(), k - 1);
     tridiag_evec(k, al.data(), be.data(), th_min, sv);
+    // error estimate of theta_min: the residual, or residual^2 / gap with the
+    // Ritz gap to the next Ritz value when that is smaller
     const double resid = bj * fabs(sv[k - 1]);
-    if (k >= 3 && resid <= tol * (1.0 + fabs(th_max))) {
+    double err = resid;
+    if (use_gap && k >= 2) {
+      const double gap = tridiag_eig(k, al.data(), be.data(), 1) - th_min;
+      if (gap > 0.0) err = std::min(resid, resid * resid / gap);
+    }
+    if (resid_out) *resid_out = err;
+    if (k >= 3 && err <= tol * (1.0 + fabs(th_max))) {
       *converged = true;
       break;
     }
@@ -488,6 +524,8 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->gtol_min = 1e-10;
   o->gtol_decay = 1.0;
   o->gtol_ratio = 0.0;
+  o->gtol_stall = 0.1;
+  o->sigma_hold = 1;
   o->rtr_maxiter = 50;
   o->tcg_maxinner = 200;
   o->hvp_prec = MDSDP_FP64;
@@ -568,6 +606,8 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   double* evec = W.tmp;
   double gtol = opt->gtol0 / opt->gtol_decay;
   double prim_ratio = INFINITY;  // ||R|| / (1 + ||b||) of the last outer step
+  double stall_cap = INFINITY;   // tolerance cap after an RTR call that took no step
+  bool have_evec = false;
   for (k = 0; k < opt->max_outer; ++k) {
     CHK(mdsdp_set_sigma(P, sigma));
     const int prec = (opt->polish_fp64 && eta_max < opt->polish_eta) ? MDSDP_FP64 : opt->hvp_prec;
@@ -590,10 +630,12 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     {
       double g = std::min(std::min(opt->gtol0, 0.1 * eta_max), opt->gtol_decay * gtol);
       if (opt->gtol_ratio > 0.0 && std::isfinite(prim_ratio)) g = std::min(g, opt->gtol_ratio * prim_ratio);
+      g = std::min(g, stall_cap);
       gtol = std::max(opt->gtol_min, g);
     }
     RTRState rs;
     CHK(rtr(P, p, Y, gtol, opt->rtr_maxiter, opt->tcg_maxinner, prec, W, C, rs, s, opt->verbose));
+    if (opt->gtol_stall > 0.0 && rs.iters == 0 && rs.gn > 0.0) stall_cap = std::min(stall_cap, opt->gtol_stall * rs.gn);
     // multiplier update (Algorithm alg1 steps 5-8)
     auto tu = clk::now();
     CHK(mdsdp_update_multiplier(P, p, Y, nullptr, nullptr, P->scal + SC_KKT, s));
@@ -606,13 +648,17 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     int eit = 0;
     bool conv = false;
     int nfound = 0;
+    double lres = 0.0;
     CHK(lanczos(P, opt->eig_tol, opt->eig_maxit, opt->seed + (uint64_t)k, &lmin, &lmax, evec, &eit, &conv, s,
-                std::max(1, opt->n_neg), 1e-12, &nfound));
+                std::max(1, opt->n_neg), 1e-12, &nfound, have_evec ? evec : nullptr, &lres, true));
+    have_evec = true;
     C.eig_iters += eit;
     C.t_eig += secs(te, clk::now());
     const double normR = kk[0], bty = kk[1], sumz = kk[2], cx = kk[3];
     eta[0] = normR / (1.0 + P->normC);
-    eta[1] = std::max(0.0, -lmin) / (1.0 + fabs(lmax));
+    // an unconverged Lanczos only certifies an eigenvalue within its residual
+    // of theta_min: use theta_min - residual then
+    eta[1] = std::max(0.0, -(conv ? lmin : lmin - lres)) / (1.0 + fabs(lmax));
     const double prim = cx + sumz;
     eta[2] = fabs(prim - bty) / (1.0 + fabs(prim) + fabs(bty));
     eta_max = std::max(eta[0], std::max(eta[1], eta[2]));
@@ -681,7 +727,8 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     // sigma rule, eq. sec5:eq1
     const double ratio = normR / (1.0 + P->normb);
     prim_ratio = ratio;
-    if (ratio < opt->kappa1 * rs.gn)
+    const bool unsolved = rs.gn > gtol;  // RTR stopped at its iteration cap
+    if (ratio < opt->kappa1 * rs.gn && !(opt->sigma_hold && unsolved))
       sigma = std::max(sigma / opt->gamma, opt->sigma_min);
     else if (ratio > opt->kappa2 * rs.gn)
       sigma = std::min(opt->gamma * sigma, opt->sigma_max);

@@ -31,7 +31,7 @@ def test_q10_matches_brute_force(seed):
     assert max(res.eta) <= 1e-8
     assert res.value <= fmin + 1e-8 * (1 + abs(fmin))
     sv = np.linalg.svd(res.Y, compute_uv=False)
-    assert sv[1] <= 1e-3 * sv[0]  # numerically rank one
+    assert sv.size == 1 or sv[1] <= 1e-3 * sv[0]  # numerically rank one
     assert abs(res.value - fmin) <= 1e-8 * (1 + abs(fmin))
     x, fx = alm.rank_one_rounding(res.Y, Q, c, None)
     assert abs(fx - fmin) <= 1e-9 * (1 + abs(fmin))
