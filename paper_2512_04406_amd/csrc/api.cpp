@@ -137,8 +137,8 @@ namespace mdsdp {
 static void free_problem(mdsdp_problem P) {
   if (!P) return;
   void* ptrs[] = {P->cls,      P->Xt,     P->Xt32,    P->Ct,      P->segs,   P->seg_start, P->cy,
-                  P->Cavg,     P->yp,     P->invc,    P->bvec,    P->sacc,   P->Yp,        P->Up,
-                  P->bqp4a_items, P->bqp_cd,
+                  P->Cavg,     P->yp,     P->ab32,    P->invc,    P->bvec,    P->sacc,   P->Yp,        P->Up,
+                  P->bqp4_items, P->bqpT,     P->bqpStar,
                   P->zvec,     P->zmult,  P->rowpart, P->colpart, P->wgpart, P->zpart,     P->gram,
                   P->gpart,    P->scal,   P->bound,   P->dotpart, (void*)P->dotptr, P->lz_V, P->lz_w,
                   P->lz_h,     P->lz_hpart, P->work};
@@ -303,6 +303,7 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   TRY(dalloc(&P->seg_start, P->nb + 1));
   TRY(dalloc(&P->cy, m));
   TRY(dalloc(&P->yp, m));
+  TRY(dalloc(&P->ab32, m));
   TRY(dalloc(&P->invc, m));
   TRY(dalloc(&P->bvec, m));
   TRY(dalloc(&P->sacc, m));
@@ -398,33 +399,24 @@ mdsdp_status mdsdp_create_bqp(int32_t q, int32_t order, const double* Q, const d
   if ((st = mdsdp_bqp_b(q, Q, c, b.data())) != MDSDP_OK) return st;
   mdsdp_problem P = nullptr;
   if ((st = create_from_packed(n, m, cls.data(), b.data(), nullptr, &P)) != MDSDP_OK) return st;
-  // the structured kernels stage at most 111 pair rows per set in LDS
-  if (order == MDSDP_ORDER_COLEX && q >= 1 && q <= 112) {
-    // structured class-sum kernels: work lists
+  if (order == MDSDP_ORDER_COLEX && q >= 1) {
+    // structured class-sum kernels: degree-4 work items (c, d0, a0, b0) with
+    // 16-blocks of d > c, of b < c and of a <= b
     P->bqp_q = q;
     bqp_offsets(q, P->bqp_off);
     std::vector<int4> items;
-    for (int cc = 2; cc <= q - 2; ++cc) {
-      const long long npi = binom(cc, 2);
-      for (int d0 = cc + 1; d0 < q; d0 += 16)
-        for (long long p0 = 0; p0 < npi; p0 += 64) items.push_back(make_int4(cc, d0, (int)p0, 0));
-    }
-    std::vector<int2> cd;
     for (int cc = 2; cc <= q - 2; ++cc)
-      for (int dd = cc + 1; dd < q; ++dd) cd.push_back(make_int2(cc, dd));
-    // largest work first for the degree-4 symmetric pass
-    std::stable_sort(cd.begin(), cd.end(), [](const int2& x, const int2& y) { return x.x > y.x; });
-    P->bqp4a_n = (int)items.size();
-    P->bqp_ncd = (int)cd.size();
+      for (int d0 = cc + 1; d0 < q; d0 += 16)
+        for (int b0 = 0; b0 < cc; b0 += 16)
+          for (int a0 = 0; a0 <= b0; a0 += 16) items.push_back(make_int4(cc, d0, a0, b0));
+    P->bqp4_n = (int)items.size();
     hipError_t e = hipSuccess;
     if (!items.empty()) {
-      e = hipMalloc((void**)&P->bqp4a_items, items.size() * sizeof(int4));
-      if (e == hipSuccess) e = hipMemcpy(P->bqp4a_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
+      e = hipMalloc((void**)&P->bqp4_items, items.size() * sizeof(int4));
+      if (e == hipSuccess) e = hipMemcpy(P->bqp4_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
     }
-    if (e == hipSuccess && !cd.empty()) {
-      e = hipMalloc((void**)&P->bqp_cd, cd.size() * sizeof(int2));
-      if (e == hipSuccess) e = hipMemcpy(P->bqp_cd, cd.data(), cd.size() * sizeof(int2), hipMemcpyHostToDevice);
-    }
+    if (e == hipSuccess) e = hipMalloc((void**)&P->bqpT, (size_t)n * (q + 1) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&P->bqpStar, (size_t)STAR_LG * q * q * sizeof(double));
     if (e != hipSuccess) {
       st = hip_fail(e, "bqp tables");
       free_problem(P);
@@ -486,6 +478,7 @@ mdsdp_status mdsdp_problem_info(mdsdp_problem P, int32_t* n, int64_t* m, int64_t
 mdsdp_status mdsdp_set_multiplier(mdsdp_problem P, const double* Xt_dev, double sigma, void* stream) {
   if (!P) return einval("problem is NULL");
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return einval("sigma must be positive and finite");
+  if (sigma != P->sigma) P->a32_valid = false;
   P->sigma = sigma;
   return launch_set_dense(P, Xt_dev, (hipStream_t)stream);
 }
@@ -498,6 +491,7 @@ mdsdp_status mdsdp_get_multiplier(mdsdp_problem P, double* Xt_dev, void* stream)
 mdsdp_status mdsdp_set_sigma(mdsdp_problem P, double sigma) {
   if (!P) return einval("problem is NULL");
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return einval("sigma must be positive and finite");
+  if (sigma != P->sigma) P->a32_valid = false;
   P->sigma = sigma;
   return MDSDP_OK;
 }
@@ -526,7 +520,7 @@ mdsdp_status mdsdp_hvp(mdsdp_problem P, int32_t p, int32_t prec, const double* Y
   if ((st = launch_stage(P, p, Y, U, fp32, s)) != MDSDP_OK) return st;
   if ((st = launch_gram(P, p, Y, U, s)) != MDSDP_OK) return st;
   if ((st = launch_classsum_Z(P, fp32, s)) != MDSDP_OK) return st;
-  if ((st = launch_resid(P, M_HVP, fp32, s)) != MDSDP_OK) return st;
+  if ((st = fp32 ? launch_hvp32(P, s) : launch_resid(P, M_HVP, false, s)) != MDSDP_OK) return st;
   return launch_rowfinal_hvp(P, p, fp32, Y, U, HU, riemannian ? 1 : 0, s);
 }
 

@@ -467,6 +467,213 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// FP32-tile HVP product pass (mixed precision).  Per packed entry e of class g
+// the Euclidean HVP 2 G U + 2 sigma Q(Y U^T + U Y^T) Y needs the entry-wise
+//     A_e = Xt_e + (D_g - sigma y_g) + sigma C_e   (coefficient of U)
+//     B_e = -sigma y'_g                            (coefficient of Y)
+// while sigma S U = sigma Y (Y^T U) and the rank-2p part sigma (Y U^T + U Y^T) Y
+// are added in FP64 by the row finaliser from the Gram matrices, so no S tile
+// is formed here.  Class data are one 8-byte gather of the FP32 pair
+// {D_g - sigma y_g, -sigma y'_g}, entry data the class word and the FP32
+// shadow of Xt: 8 bytes per packed entry and 8 per class.  The factor columns are cut into slices of SW <= 64 columns; the
+// slices of one segment go to consecutive workgroups of one XCD so that they
+// share the entry and class reads through that XCD's L2.
+// ---------------------------------------------------------------------------
+struct H32Args {
+  const uint32_t* cls;
+  const float* Xt32;
+  const double* Ct;
+  const Seg* segs;
+  int nseg, seg_per_xcd, nsl, pw;
+  const float* Yp;
+  const float* Up;
+  const float2* ab32;   // per class {D - sigma y, -sigma y'}
+  float sigma;
+  float* rowpart;
+  float* colpart;
+};
+
+template <int SW>
+struct H32Lds {
+  static constexpr int LPW = SW + 1;
+  static constexpr size_t slab = 64 * LPW;
+  static constexpr size_t tbuf = 16 * LP;
+  static constexpr size_t bytes = (4 * slab + 8 * tbuf) * sizeof(float);
+};
+
+template <int SW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SW == 16 ? 4 : 2))) void k_hvp32(H32Args a) {
+  typedef H32Lds<SW> L;
+  constexpr int NC = SW / 16, LPW = L::LPW;
+  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
+  const int sl = loc % a.nsl, sloc = loc / a.nsl;
+  if (sloc >= a.seg_per_xcd) return;
+  const int sidx = xcd * a.seg_per_xcd + sloc;
+  if (sidx >= a.nseg) return;
+  const int col0 = sl * SW, pw = a.pw;
+  const Seg sg = a.segs[sidx];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* sYc = (float*)smem_raw;
+  float* sUc = sYc + L::slab;
+  float* sYr = sUc + L::slab;
+  float* sUr = sYr + L::slab;
+  float* tA = sUr + L::slab;
+  float* tB = tA + 4 * L::tbuf;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int i = tid; i < 64 * SW; i += 256) {
+    const int r = i / SW, c = i % SW;
+    const size_t o = (size_t)(sg.J * 64 + r) * pw + col0 + c;
+    sYc[r * LPW + c] = a.Yp[o];
+    sUc[r * LPW + c] = a.Up[o];
+  }
+  const float sigma = a.sigma;
+  v4f accC[4][NC];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) accC[i][c] = v4f{0, 0, 0, 0};
+  float* tAw = tA + w * L::tbuf;
+  float* tBw = tB + w * L::tbuf;
+
+  // per tile: the entry words and the factor rows are loaded at the top of the
+  // tile (loading those of the next tile during the products measured slower)
+  constexpr bool PREF_ROWS = (SW == 16);
+  constexpr int RPT = PREF_ROWS ? 64 * SW / 256 : 1;  // factor-row values per thread
+  uint32_t cwv[4][4];
+  float xv[4][4];
+  float yrv[RPT], urv[RPT];
+  auto load_tile = [&](int I) {
+    const long long t = (long long)sg.J * (sg.J + 1) / 2 + I;
+    const size_t tb = (size_t)t * TSLOTS + (size_t)(w * 4) * 256 + li;
+#pragma unroll
+    for (int sc = 0; sc < 4; ++sc)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const size_t off = tb + sc * 256 + (4 * lk + v) * 16;
+        cwv[sc][v] = a.cls[off];
+        xv[sc][v] = a.Xt32[off];
+      }
+    if (PREF_ROWS) {
+#pragma unroll
+      for (int e = 0; e < RPT; ++e) {
+        const int i = tid + 256 * e, r = i / SW, c = i % SW;
+        const size_t o = (size_t)(I * 64 + r) * pw + col0 + c;
+        yrv[e] = a.Yp[o];
+        urv[e] = a.Up[o];
+      }
+    }
+  };
+  for (int I = sg.I0; I <= sg.I1; ++I) {
+    load_tile(I);
+    __syncthreads();
+    if (PREF_ROWS) {
+#pragma unroll
+      for (int e = 0; e < RPT; ++e) {
+        const int i = tid + 256 * e, r = i / SW, c = i % SW;
+        sYr[r * LPW + c] = yrv[e];
+        sUr[r * LPW + c] = urv[e];
+      }
+    } else {
+      for (int i = tid; i < 64 * SW; i += 256) {
+        const int r = i / SW, c = i % SW;
+        const size_t o = (size_t)(I * 64 + r) * pw + col0 + c;
+        sYr[r * LPW + c] = a.Yp[o];
+        sUr[r * LPW + c] = a.Up[o];
+      }
+    }
+    __syncthreads();
+    const long long t = (long long)sg.J * (sg.J + 1) / 2 + I;
+    const bool diag = (I == sg.J);
+    v4f accR[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) accR[c] = v4f{0, 0, 0, 0};
+    // entry data of this wave's 16 x 64 slab: lane (li, lk) holds column li,
+    // rows 4 lk + v of each 16 x 16 sub-block (the FP32 MFMA result layout)
+    const size_t tb = (size_t)t * TSLOTS + (size_t)(w * 4) * 256 + li;
+    float av[4][4], bv[4][4];
+#pragma unroll
+    for (int sc = 0; sc < 4; ++sc)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t cw = cwv[sc][v];
+        const bool valid = !(cw & 0x80000000u);
+        const uint32_t id = valid ? (cw & CLS_MASK) : 0u;
+        const float2 ab = a.ab32[id];
+        float A = xv[sc][v] + ab.x;
+        if (a.Ct) A += sigma * (float)a.Ct[tb + sc * 256 + (4 * lk + v) * 16];
+        av[sc][v] = valid ? A : 0.0f;
+        bv[sc][v] = valid ? ab.y : 0.0f;
+      }
+#pragma unroll
+    for (int sc = 0; sc < 4; ++sc) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        tAw[(4 * lk + v) * LP + li] = av[sc][v];
+        tBw[(4 * lk + v) * LP + li] = bv[sc][v];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // row side:    out_R[row][pcol] += sum_c A[row][c] U_C[c][pcol] + B[row][c] Y_C[c][pcol]
+      // column side: out_C^T[pcol][c] += sum_r U_R[r][pcol] A[r][c] + Y_R[r][pcol] B[r][c]
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float a1 = tAw[li * LP + 4 * j + lk];
+        const float a2 = tAw[(4 * j + lk) * LP + li];
+        const float b1 = tBw[li * LP + 4 * j + lk];
+        const float b2 = tBw[(4 * j + lk) * LP + li];
+        const int rc = (sc * 16 + 4 * j + lk) * LPW + li;
+        const int rr = (w * 16 + 4 * j + lk) * LPW + li;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          accR[c] = mfma(a1, sUc[rc + 16 * c], accR[c]);
+          accR[c] = mfma(b1, sYc[rc + 16 * c], accR[c]);
+          if (!diag) {
+            accC[sc][c] = mfma(sUr[rr + 16 * c], a2, accC[sc][c]);
+            accC[sc][c] = mfma(sYr[rr + 16 * c], b2, accC[sc][c]);
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // row-side partial of this tile: rows w*16 + 4 lk + v, columns col0 + c*16 + li
+    float* rp = a.rowpart + ((size_t)t * 64 + w * 16) * pw + col0 + li;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) rp[(4 * lk + v) * pw + 16 * c] = accR[c][v];
+  }
+  // column-side partial of the segment: sum of the four waves (row sub-blocks)
+  float* cred = tA;  // 3 x 256 floats (the transpose buffers are free now)
+  float* cp = a.colpart + (size_t)sidx * 64 * pw;
+  for (int sc = 0; sc < 4; ++sc) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      __syncthreads();
+      if (w > 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cred[(w - 1) * 256 + (4 * lk + v) * 16 + li] = accC[sc][c][v];
+      }
+      __syncthreads();
+      if (w == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int pc = 4 * lk + v;
+          float sum = accC[sc][c][v];
+          sum += cred[0 * 256 + pc * 16 + li];
+          sum += cred[1 * 256 + pc * 16 + li];
+          sum += cred[2 * 256 + pc * 16 + li];
+          cp[(sc * 16 + li) * pw + col0 + c * 16 + pc] = sum;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // row finalisers: thread per (row, pcol); 16 lanes per row
 // ---------------------------------------------------------------------------
 struct RowArgs {
@@ -476,20 +683,39 @@ struct RowArgs {
   const void* colpart;
 };
 
+// sum of the partials of output (r, k): the row-side partials of tiles (I, J),
+// J >= I, and the column-side partials of the segments of column block I;
+// with spl > 1 this lane takes every spl-th of them, starting at `part`
 template <typename T>
-__device__ __forceinline__ double row_sum(const RowArgs& ra, int r, int k) {
+__device__ __forceinline__ double row_sum(const RowArgs& ra, int r, int k, int part = 0, int spl = 1) {
   const int I = r >> 6, rr = r & 63;
   const T* rp = (const T*)ra.rowpart;
   const T* cp = (const T*)ra.colpart;
   const int pw = ra.pw;
   double s = 0.0;
 #pragma unroll 8
-  for (int J = I; J < ra.nb; ++J) {
+  for (int J = I + part; J < ra.nb; J += spl) {
     const long long t = ((long long)J * (J + 1) >> 1) + I;
     s += (double)rp[((size_t)t * 64 + rr) * pw + k];
   }
-  for (int q = ra.seg_start[I]; q < ra.seg_start[I + 1]; ++q) s += (double)cp[((size_t)q * 64 + rr) * pw + k];
+  for (int q = ra.seg_start[I] + part; q < ra.seg_start[I + 1]; q += spl)
+    s += (double)cp[((size_t)q * 64 + rr) * pw + k];
   return s;
+}
+
+// Thread layout of the split row finalisers: L = min(pw, 64) columns per row,
+// each (row, column) shared by SPL = 64 / L lanes (pw <= 32) that split its
+// partial sums; lane index = (row * L + column) * SPL + part.  Sums over the
+// SPL lanes and over the L columns of a row are xor butterflies, which give
+// every lane the same bits (each step adds a commuted pair).
+__device__ __forceinline__ int row_split(int pw) { return pw >= 64 ? 1 : 64 / pw; }
+__device__ __forceinline__ double sum_parts(double v, int spl) {
+  for (int off = 1; off < spl; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double sum_row_split(double v, int L, int spl) {
+  for (int off = L >> 1; off >= 1; off >>= 1) v += __shfl_xor(v, off * spl, 64);
+  return v;
 }
 
 // sum over the pw lanes of one row (pw = 16, 32 or 64), fixed butterfly order
@@ -513,9 +739,10 @@ __device__ __forceinline__ int row_lanes(int pw) { return pw < 64 ? pw : 64; }
 __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __restrict__ Y,
                                                   double* __restrict__ egrad, double* __restrict__ rgrad,
                                                   double* __restrict__ zvec) {
-  const int L = row_lanes(ra.pw);
+  const int L = row_lanes(ra.pw), spl = row_split(ra.pw);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx / L, c0 = idx % L;
+  const int part = idx % spl, rc = idx / spl;
+  const int r = rc / L, c0 = rc % L;
   const bool in = r < ra.n;
   double gy[RMAXC], y[RMAXC];
   double zp = 0.0;
@@ -523,16 +750,16 @@ __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __re
   for (int j = 0; j < RMAXC; ++j) {
     const int k = c0 + j * L;
     const bool kin = in && k < ra.p && k < ra.pw;
-    gy[j] = kin ? row_sum<double>(ra, r, k) : 0.0;
+    gy[j] = sum_parts(kin ? row_sum<double>(ra, r, k, part, spl) : 0.0, spl);
     y[j] = kin ? Y[(size_t)r * ra.p + k] : 0.0;
     zp += gy[j] * y[j];
   }
-  const double z = sum_row(zp, L);
-  if (in && c0 == 0) zvec[r] = z;
+  const double z = sum_row_split(zp, L, spl);
+  if (in && c0 == 0 && part == 0) zvec[r] = z;
 #pragma unroll
   for (int j = 0; j < RMAXC; ++j) {
     const int k = c0 + j * L;
-    if (in && k < ra.p && k < ra.pw) {
+    if (in && part == 0 && k < ra.p && k < ra.pw) {
       if (egrad) egrad[(size_t)r * ra.p + k] = 2.0 * gy[j];
       if (rgrad) rgrad[(size_t)r * ra.p + k] = 2.0 * (gy[j] - z * y[j]);
     }
@@ -542,14 +769,15 @@ __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __re
 template <typename T>
 __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __restrict__ Y,
                                                  const double* __restrict__ U, const double* __restrict__ gram,
-                                                 const double* __restrict__ zvec, double sigma, int fp32, int riem,
+                                                 const double* __restrict__ zvec, double sigma, int riem,
                                                  double* __restrict__ HU) {
-  const int pw = ra.pw, L = row_lanes(pw);
+  const int pw = ra.pw, L = row_lanes(pw), spl = row_split(pw);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = idx / L, c0 = idx % L;
+  const int part = idx % spl, rc = idx / spl;
+  const int r = rc / L, c0 = rc % L;
   const bool in = r < ra.n;
-  // low-rank terms: sigma [Y (Y^T U + U^T Y) + U (Y^T Y)] (FP64 tiles) or
-  // sigma [Y (U^T Y) + U (Y^T Y)] (FP32 tiles carry S U entry-wise)
+  // low-rank terms sigma [Y (Y^T U + U^T Y) + U (Y^T Y)]: sigma S U and the
+  // rank-2p part of sigma (Y U^T + U Y^T) Y (the tiles carry neither)
   const double* YtY = gram;
   const double* YtU = gram + GRAM_U;
   double Ht[RMAXC], y[RMAXC], u[RMAXC];
@@ -558,28 +786,26 @@ __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __res
   for (int j = 0; j < RMAXC; ++j) {
     const int k = c0 + j * L;
     const bool kin = in && k < ra.p && k < pw;
-    double h = kin ? row_sum<T>(ra, r, k) : 0.0;
+    double h = kin ? row_sum<T>(ra, r, k, part, spl) : 0.0;
     double lr = 0.0;
     if (kin) {
-      for (int i = 0; i < ra.p; ++i) {
+      for (int i = part; i < ra.p; i += spl) {
         const double yi = Y[(size_t)r * ra.p + i];
         const double ui = U[(size_t)r * ra.p + i];
-        double w1 = YtU[k * pw + i];
-        if (!fp32) w1 += YtU[i * pw + k];
-        lr += yi * w1 + ui * YtY[i * pw + k];
+        lr += yi * (YtU[k * pw + i] + YtU[i * pw + k]) + ui * YtY[i * pw + k];
       }
     }
-    Ht[j] = kin ? 2.0 * (h + sigma * lr) : 0.0;
+    Ht[j] = 2.0 * sum_parts(h + sigma * lr, spl);
     y[j] = kin ? Y[(size_t)r * ra.p + k] : 0.0;
     u[j] = kin ? U[(size_t)r * ra.p + k] : 0.0;
     dp += Ht[j] * y[j];
   }
-  const double d = riem ? sum_row(dp, L) : 0.0;
+  const double d = riem ? sum_row_split(dp, L, spl) : 0.0;
   const double zr = (riem && in) ? zvec[r] : 0.0;
 #pragma unroll
   for (int j = 0; j < RMAXC; ++j) {
     const int k = c0 + j * L;
-    if (in && k < ra.p && k < pw) {
+    if (in && part == 0 && k < ra.p && k < pw) {
       const double v = riem ? Ht[j] - d * y[j] - 2.0 * zr * u[j] : Ht[j];
       HU[(size_t)r * ra.p + k] = v;
     }
@@ -746,14 +972,16 @@ __global__ __launch_bounds__(256) void k_gram_part(int n, int p, const double* _
 
 __global__ __launch_bounds__(256) void k_gram_final(int nblk, int len, const double* __restrict__ part,
                                                     double* __restrict__ gram, int pw) {
-  // part: nblk x (2 pw^2); gram: Y^T Y at [0, pw^2), Y^T U at [GRAM_U, GRAM_U + pw^2)
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  // part: nblk x (2 pw^2); gram: Y^T Y at [0, pw^2), Y^T U at [GRAM_U, GRAM_U + pw^2).
+  // One wave per element: lanes take every 64th partial, then a butterfly.
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (e >= len) return;
   double s = 0.0;
-#pragma unroll 8
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * len + e];
+  for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * len + e];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
   const int pw2 = pw * pw;
-  gram[e < pw2 ? e : GRAM_U + (e - pw2)] = s;
+  if (lane == 0) gram[e < pw2 ? e : GRAM_U + (e - pw2)] = s;
 }
 
 // retraction and tangent projection: one thread per row, any p
@@ -1036,6 +1264,25 @@ __global__ __launch_bounds__(256) void k_final_Z(long long m, long long* __restr
   sacc[g] = 0;
 }
 
+// FP32-tile HVP: class coefficient -sigma y' of Y
+__global__ __launch_bounds__(256) void k_final_Z32(long long m, long long* __restrict__ sacc,
+                                                   const double* __restrict__ invc, const double* __restrict__ scal,
+                                                   double sigma, float2* __restrict__ ab32) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m) return;
+  ab32[g].y = (float)(-sigma * ((double)sacc[g] / scal[SC_SCALE_Z] * invc[g]));
+  sacc[g] = 0;
+}
+
+// FP32-tile HVP: class coefficient D - sigma y of U (y of the last S-pass)
+__global__ __launch_bounds__(256) void k_make_a32(long long m, const double2* __restrict__ cy, double sigma,
+                                                  float2* __restrict__ ab32) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m) return;
+  const double2 dy = cy[g];
+  ab32[g].x = (float)(dy.x - sigma * dy.y);
+}
+
 // b^T y over the classes that may carry b != 0 (deterministic two-stage)
 __global__ __launch_bounds__(256) void k_bty_part(long long range, const double* __restrict__ b,
                                                   const double2* __restrict__ cy, double* __restrict__ part) {
@@ -1064,13 +1311,19 @@ __global__ __launch_bounds__(256) void k_bty_part(long long range, const double*
 //   {a<b<c}  : (a|bc) + (b|ac) + (c|ab)           |gamma| = 6
 //   {i<j}    : ({}|ij) + (i|j) + sum_l (il|jl)     |gamma| = 2q
 //   {i}      : ({}|i) + sum_j (j|ij)              |gamma| = 2q
-//   {}       : sum_alpha B(alpha, alpha) / 2 ...  |gamma| = n
-// For fixed (c, d) the classes {a<b<c<d} occupy the contiguous id range
-// base4(c, d) + pi(a, b), pi(a, b) = a + C(b, 2) being the colex index of the
-// pair {a, b}.  k_bqp4a writes the (ab|cd) term (a tall GEMM of the pair rows
-// below c against the pairs {c, d}); k_bqp4b adds (ac|bd) + (ad|bc), which for
-// fixed (c, d) is the symmetric part of a c x c product of the pair rows
-// {x, c} and {x, d}, and scales by 1/3.  No class map is read, no atomics.
+//   {}       : sum_alpha B(alpha, alpha)          |gamma| = n
+// Degree 4 (96% of the classes): k_bqp4 takes one (c, 16 d's, 16 a's, 16 b's)
+// block; (ab|cd) is an MFMA tile in (a, d) for each b, (ac|bd) + (ad|bc) an
+// MFMA tile in (a, b) for each d, and the first is transposed through LDS
+// onto the second.  Ids base4(c, d) + a + C(b, 2) are written once each.
+// Degrees 0-3 read the table T[r][x] = B(row r, row x) of every basis row r
+// against the rows {} and {i} (one small GEMM, k_bqpT), and the contraction
+// star[i][j] = sum_l (il|jl) (k_bqpStar, partials over residues of l), and
+// are finished by k_bqpFin.  No class map is read, no atomics are used, every
+// sum has a fixed order.  MFMA operands come straight from the staged rows:
+// lane (i, k) loads the 4-vector of columns 4k..4k+3 of row i, and the four
+// MFMAs of a 16-column chunk use its four components (a permutation of the
+// contraction index shared by both operands).
 // ---------------------------------------------------------------------------
 // binomials without 64-bit integer division (emulated on the GPU): x <= 362
 __device__ __forceinline__ long long c2(long long x) { return (x * (x - 1)) >> 1; }
@@ -1082,15 +1335,16 @@ __device__ __forceinline__ long long c4(long long x) {
   const long long t = c3(x);  // C(x,4) = C(x,3) (x - 3) / 4, exact
   return x < 4 ? 0 : (t * (x - 3)) >> 2;
 }
-// largest c with C(c, 3) <= t, and largest b with C(b, 2) <= t
+// largest c with C(c, 3) <= t, and largest b with C(b, 2) <= t (t < 2^24:
+// a single-precision first guess, corrected exactly in integers)
 __device__ __forceinline__ int inv_c3(long long t) {
-  int c = (int)cbrt(6.0 * (double)t) + 1;
+  int c = (int)cbrtf(6.0f * (float)t) + 1;
   while (c3(c) > t) --c;
   while (c3(c + 1) <= t) ++c;
   return c;
 }
 __device__ __forceinline__ int inv_c2(long long t) {
-  int b = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+  int b = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
   while (c2(b) > t) --b;
   while (c2(b + 1) <= t) ++b;
   return b;
@@ -1098,267 +1352,321 @@ __device__ __forceinline__ int inv_c2(long long t) {
 
 struct BqpArgs {
   int q;
-  int nk;              // 4-wide K chunks covering p
+  int pw;              // row pitch of the staged factors
+  int nkc;             // 16-column chunks covering p
   long long off2, off3, off4;
   const void* Yp;
   const void* Up;
-  const int4* items;   // k_bqp4a work items
-  const int2* cd;      // (c, d) pairs
-  int ncd;
+  const int4* items;   // k_bqp4 work items (c, d0, a0, b0)
+  double* T;           // n x (q + 1) table B(row r, row x), x in {}, {0}, ..., {q-1}
+  double* star;        // STAR_LG x q x q partials of sum_l (il|jl)
   double* dst;         // output element g at dst[g * stride]
   int stride;          // 2 for the .y field of cy, 1 for yp
-  double* part;        // partials (degree 0)
+  double* part;        // degree-0 partials
+  float2* dst32;       // FP32-tile HVP: class coefficient -sigma y'_g written to dst32[g].y instead
+  double scale32;      // -sigma
 };
+
+// final class average `val` of class g: FP64 slot, or the FP32-tile HVP
+// coefficient -sigma val
+template <typename T, bool ZMODE>
+__device__ __forceinline__ void bqp_store(const BqpArgs& a, long long g, double val) {
+  if (ZMODE && sizeof(T) == 4)
+    a.dst32[g].y = (float)(a.scale32 * val);
+  else
+    a.dst[g * a.stride] = val;
+}
 
 // row of the colex basis: {} -> 0, {i} -> 1 + i, {i<j} -> 1 + q + C(j,2) + i
 __device__ __forceinline__ int prow(int q, int i, int j) { return 1 + q + (int)c2(j) + i; }
+// row of the pair {x, y}; row 0 (a valid row whose products are discarded)
+// when x == y or an index is out of range
+__device__ __forceinline__ int pair_row(int q, int x, int y) {
+  if (x == y || x < 0 || y < 0 || x >= q || y >= q) return 0;
+  return x < y ? prow(q, x, y) : prow(q, y, x);
+}
 
-template <typename T, bool ZMODE, int PW>
-__global__ __launch_bounds__(256) void k_bqp4a(BqpArgs a) {
-  typedef typename V4<T>::type v4;
-  const int4 it = a.items[blockIdx.x];
-  const int c = it.x, d0 = it.y, pi0 = it.z;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  const int q = a.q;
-  const T* Y = (const T*)a.Yp;
-  const T* U = (const T*)a.Up;
-  const long long npi = c2(c);
-  const int pib = pi0 + 16 * w;  // this wave's 16 pairs
-  if (pib >= npi) return;
-  // A operand: rows d (pairs {c, d}); B operand: columns pi (pairs below c)
-  const int dA = d0 + li;
-  const bool dok = dA < q;
-  const size_t rowA = (size_t)(dok ? prow(q, c, dA) : 0) * PW;
-  const long long piB = pib + li;
-  const size_t rowB = (size_t)((piB < npi) ? (1 + q + (int)piB) : 0) * PW;
-  const int nk = min(PW / 4, a.nk);
-  v4 acc = {0, 0, 0, 0};
-  for (int j = 0; j < nk; ++j) {
-    const int k = 4 * j + lk;
-    const T ya = dok ? Y[rowA + k] : (T)0;
-    const T yb = Y[rowB + k];
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type ld4(const T* p) {
+  return *(const typename V4<T>::type*)p;
+}
+
+// acc += B(row ra, row rb) over the 16-column chunks (A rows per lane li,
+// B rows per lane li; lane (li, lk) reads columns 16 kc + 4 lk .. + 3)
+template <typename T, bool ZMODE>
+__device__ __forceinline__ void bform_mfma(const T* Y, const T* U, size_t ra, size_t rb, int nkc, int lk,
+                                           typename V4<T>::type& acc) {
+  for (int kc = 0; kc < nkc; ++kc) {
+    const int k0 = 16 * kc + 4 * lk;
+    const auto ya = ld4(Y + ra + k0), yb = ld4(Y + rb + k0);
     if (ZMODE) {
-      const T ua = dok ? U[rowA + k] : (T)0;
-      const T ub = U[rowB + k];
-      acc = mfma(ua, yb, acc);
-      acc = mfma(ya, ub, acc);
-    } else {
-      acc = mfma(ya, yb, acc);
-    }
-  }
-  // element v: row d = d0 + drow(lk, v), column pi = pib + li
+      const auto ua = ld4(U + ra + k0), ub = ld4(U + rb + k0);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int d = d0 + drow<T>(lk, v);
-    const long long pi = pib + li;
-    if (d < q && pi < npi) {
-      const long long g = a.off4 + c3(c) + c4(d) + pi;
-      a.dst[g * a.stride] = (double)acc[v];
+      for (int e = 0; e < 4; ++e) {
+        acc = mfma(ya[e], ub[e], acc);
+        acc = mfma(ua[e], yb[e], acc);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc = mfma(ya[e], yb[e], acc);
     }
   }
 }
 
-// one workgroup per (c, d): the pair rows {x, c} and {x, d} (x < c) of Y and
-// U are staged in LDS, then the waves sweep the tiles (b-block J, a-block I),
-// I <= J, of the symmetric c x c term
-template <typename T, bool ZMODE, int PW>
-__global__ __launch_bounds__(256) void k_bqp4b(BqpArgs a) {
+template <typename T, bool ZMODE>
+__device__ __forceinline__ void bqp4_block(const BqpArgs& a, int item) {
   typedef typename V4<T>::type v4;
-  constexpr int NS = ZMODE ? 4 : 2;   // staged row sets
-  constexpr int MAXT = 7;            // tiles per wave (c <= 111 -> at most 28 tiles)
-  const int2 cdp = a.cd[blockIdx.x];
-  const int c = cdp.x, d = cdp.y;
-  const int q = a.q;
+  constexpr int DB = 2;            // d values whose operands are loaded together
+  __shared__ T t1s[16 * 16 * 17];  // (ab|cd) as [b][a][d]
+  const int4 it = a.items[item];
+  const int c = it.x, d0 = it.y, a0 = it.z, b0 = it.w;
+  const int q = a.q, pw = a.pw, nkc = a.nkc;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
   const T* Y = (const T*)a.Yp;
   const T* U = (const T*)a.Up;
-  __shared__ T sm[NS][112 * LP];     // one 16-column chunk of c <= 111 rows per set
-  const int tid = threadIdx.x;
-  const int rc0 = 1 + q + (int)c2(c), rd0 = 1 + q + (int)c2(d);
-  const int nrow = ((c + 15) >> 4) << 4;
-  const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
-  const int nbk = (c + 15) >> 4;
-  const int ntile = nbk * (nbk + 1) / 2;
-  v4 acc[MAXT];
+  // (ab|cd): for b = b0 + 4 w + bb an MFMA tile with rows a = a0 + i, columns d = d0 + j
+  {
+    const size_t rcd = (size_t)pair_row(q, c, d0 + li) * pw;
+    size_t rab[4];
 #pragma unroll
-  for (int i = 0; i < MAXT; ++i) acc[i] = v4{0, 0, 0, 0};
-  const int nchunk = (min(PW / 4, a.nk) + 3) / 4;
-  for (int kc = 0; kc < nchunk; ++kc) {
-    __syncthreads();
-    for (int i = tid; i < nrow * 16; i += 256) {
-      const int x = i >> 4, k = i & 15, kk = 16 * kc + k;
-      const bool ok = x < c;
-      sm[0][x * LP + k] = ok ? Y[(size_t)(rc0 + x) * PW + kk] : (T)0;
-      sm[1][x * LP + k] = ok ? Y[(size_t)(rd0 + x) * PW + kk] : (T)0;
-      if (ZMODE) {
-        sm[2 % NS][x * LP + k] = ok ? U[(size_t)(rc0 + x) * PW + kk] : (T)0;
-        sm[3 % NS][x * LP + k] = ok ? U[(size_t)(rd0 + x) * PW + kk] : (T)0;
+    for (int bb = 0; bb < 4; ++bb) rab[bb] = (size_t)pair_row(q, a0 + li, b0 + 4 * w + bb) * pw;
+    v4 acc[4];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) acc[bb] = v4{0, 0, 0, 0};
+    for (int kc = 0; kc < nkc; ++kc) {
+      const int k0 = 16 * kc + 4 * lk;
+      const v4 yb = ld4(Y + rcd + k0);
+      const v4 ub = ZMODE ? ld4(U + rcd + k0) : yb;
+      v4 ya[4], ua[4];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        ya[bb] = ld4(Y + rab[bb] + k0);
+        ua[bb] = ZMODE ? ld4(U + rab[bb] + k0) : ya[bb];
       }
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (ZMODE) {
+            acc[bb] = mfma(ya[bb][e], ub[e], acc[bb]);
+            acc[bb] = mfma(ua[bb][e], yb[e], acc[bb]);
+          } else {
+            acc[bb] = mfma(ya[bb][e], yb[e], acc[bb]);
+          }
+        }
     }
-    __syncthreads();
-    const T* Yc = sm[0];
-    const T* Yd = sm[1];
-    const T* Uc = sm[2 % NS];
-    const T* Ud = sm[3 % NS];
 #pragma unroll
-    for (int ti = 0; ti < MAXT; ++ti) {
-      const int t = w + 4 * ti;
-      if (t >= ntile) break;
-      int J = 0;
-      while ((J + 1) * (J + 2) / 2 <= t) ++J;
-      const int I = t - J * (J + 1) / 2;
-      const int rb = J * 16 + li, ra = I * 16 + li;  // A rows b, B columns a
+    for (int bb = 0; bb < 4; ++bb)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = 4 * j + lk;
-        if (ZMODE) {
-          // (ad|bc) = Y_bc.U_ad + U_bc.Y_ad ; (ac|bd) = Y_bd.U_ac + U_bd.Y_ac
-          acc[ti] = mfma(Yc[rb * LP + k], Ud[ra * LP + k], acc[ti]);
-          acc[ti] = mfma(Uc[rb * LP + k], Yd[ra * LP + k], acc[ti]);
-          acc[ti] = mfma(Yd[rb * LP + k], Uc[ra * LP + k], acc[ti]);
-          acc[ti] = mfma(Ud[rb * LP + k], Yc[ra * LP + k], acc[ti]);
-        } else {
-          acc[ti] = mfma(Yc[rb * LP + k], Yd[ra * LP + k], acc[ti]);
-          acc[ti] = mfma(Yd[rb * LP + k], Yc[ra * LP + k], acc[ti]);
+      for (int v = 0; v < 4; ++v) t1s[((4 * w + bb) * 16 + drow<T>(lk, v)) * 17 + li] = acc[bb][v];
+  }
+  __syncthreads();
+  // (ac|bd) + (ad|bc): for d = d0 + 4 w + dd an MFMA tile with rows a = a0 + i, columns b = b0 + j
+  const size_t rac = (size_t)pair_row(q, a0 + li, c) * pw;
+  const size_t rbc = (size_t)pair_row(q, b0 + li, c) * pw;
+  const long long base_c = a.off4 + c3(c);
+  const int bn = b0 + li;
+  v4 accd[4];
+  for (int dh = 0; dh < 4; dh += DB) {
+    size_t rad[DB], rbd[DB];
+#pragma unroll
+    for (int u = 0; u < DB; ++u) {
+      const int d = d0 + 4 * w + dh + u;
+      rad[u] = (size_t)pair_row(q, a0 + li, d) * pw;
+      rbd[u] = (size_t)pair_row(q, bn, d) * pw;
+    }
+    v4 acc[DB];
+#pragma unroll
+    for (int u = 0; u < DB; ++u) acc[u] = v4{0, 0, 0, 0};
+    for (int kc = 0; kc < nkc; ++kc) {
+      const int k0 = 16 * kc + 4 * lk;
+      const v4 yac = ld4(Y + rac + k0), ybc = ld4(Y + rbc + k0);
+      const v4 uac = ZMODE ? ld4(U + rac + k0) : yac, ubc = ZMODE ? ld4(U + rbc + k0) : ybc;
+      v4 yad[DB], ybd[DB], uad[DB], ubd[DB];
+#pragma unroll
+      for (int u = 0; u < DB; ++u) {
+        yad[u] = ld4(Y + rad[u] + k0);
+        ybd[u] = ld4(Y + rbd[u] + k0);
+        uad[u] = ZMODE ? ld4(U + rad[u] + k0) : yad[u];
+        ubd[u] = ZMODE ? ld4(U + rbd[u] + k0) : ybd[u];
+      }
+#pragma unroll
+      for (int u = 0; u < DB; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (ZMODE) {
+            acc[u] = mfma(yac[e], ubd[u][e], acc[u]);
+            acc[u] = mfma(uac[e], ybd[u][e], acc[u]);
+            acc[u] = mfma(yad[u][e], ubc[e], acc[u]);
+            acc[u] = mfma(uad[u][e], ybc[e], acc[u]);
+          } else {
+            acc[u] = mfma(yac[e], ybd[u][e], acc[u]);
+            acc[u] = mfma(yad[u][e], ybc[e], acc[u]);
+          }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < DB; ++u) accd[dh + u] = acc[u];
+  }
+  // stores last (vector memory counters retire in order: a store ahead of a
+  // load would make the load's wait include it)
+#pragma unroll
+  for (int dd = 0; dd < 4; ++dd) {
+    const int d = d0 + 4 * w + dd;
+    if (d < q) {
+      const long long base = base_c + c4(d);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int al = drow<T>(lk, v), an = a0 + al;
+        if (an < bn && bn < c) {
+          const double t1 = (double)t1s[(li * 16 + al) * 17 + 4 * w + dd];
+          bqp_store<T, ZMODE>(a, base + c2(bn) + an, (t1 + (double)accd[dd][v]) * (1.0 / 3.0));
         }
       }
     }
   }
-  const long long base = a.off4 + c3(c) + c4(d);
+}
+
+// T[r][x] = B(row r, row x) for every basis row r and x in 0..q (row x is {}
+// for x = 0 and {x-1} otherwise); blocks with blockIdx.y = 0 also write the
+// partial sum of B(row r, row r) over their 16 rows (class {})
+template <typename T, bool ZMODE>
+__device__ __forceinline__ void bqpT_tile(const BqpArgs& a, int n, int bx, int by, int lane) {
+  typedef typename V4<T>::type v4;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = bx * 16, x0 = by * 16;
+  const int q = a.q, pw = a.pw;
+  const T* Y = (const T*)a.Yp;
+  const T* U = (const T*)a.Up;
+  const int r = r0 + li, x = x0 + li;
+  const size_t ra = (size_t)(r < n ? r : 0) * pw, rx = (size_t)(x <= q ? x : 0) * pw;
+  v4 acc = {0, 0, 0, 0};
+  bform_mfma<T, ZMODE>(Y, U, ra, rx, a.nkc, lk, acc);
 #pragma unroll
-  for (int ti = 0; ti < MAXT; ++ti) {
-    const int t = w + 4 * ti;
-    if (t >= ntile) break;
-    int J = 0;
-    while ((J + 1) * (J + 2) / 2 <= t) ++J;
-    const int I = t - J * (J + 1) / 2;
+  for (int v = 0; v < 4; ++v) {
+    const int rr = r0 + drow<T>(lk, v);
+    if (rr < n && x <= q) a.T[(size_t)rr * (q + 1) + x] = (double)acc[v];
+  }
+  if (by == 0) {
+    double d = 0.0;
+    if (lk == 0 && r < n) {
+      for (int k = 0; k < 16 * a.nkc; ++k) {
+        const double yk = (double)Y[ra + k];
+        d += ZMODE ? 2.0 * yk * (double)U[ra + k] : yk * yk;
+      }
+    }
+    d = sum16(d);
+    if (lane == 0) a.part[bx] = d;
+  }
+}
+
+// star partials: sum over l = lg, lg + STAR_LG, ... of (il|jl) for the 16 x 16
+// tile (I, J), I <= J, of (i, j); the term l = i or l = j is left out
+template <typename T, bool ZMODE>
+__device__ __forceinline__ void bqpStar_tile(const BqpArgs& a, int tile, int lg, int lane) {
+  typedef typename V4<T>::type v4;
+  const int li = lane & 15, lk = lane >> 4;
+  int J = 0;
+  while ((J + 1) * (J + 2) / 2 <= tile) ++J;
+  const int I = tile - J * (J + 1) / 2;
+  const int q = a.q, pw = a.pw;
+  const T* Y = (const T*)a.Yp;
+  const T* U = (const T*)a.Up;
+  const int i = 16 * I + li, j = 16 * J + li;
+  v4 acc = {0, 0, 0, 0};
+  for (int l = lg; l < q; l += STAR_LG) {
+    const bool iok = i < q && i != l, jok = j < q && j != l;
+    const size_t ri = (size_t)pair_row(q, i, l) * pw, rj = (size_t)pair_row(q, j, l) * pw;
+    for (int kc = 0; kc < a.nkc; ++kc) {
+      const int k0 = 16 * kc + 4 * lk;
+      const v4 z = {0, 0, 0, 0};
+      const v4 yi = iok ? ld4(Y + ri + k0) : z, yj = jok ? ld4(Y + rj + k0) : z;
+      if (ZMODE) {
+        const v4 ui = iok ? ld4(U + ri + k0) : z, uj = jok ? ld4(U + rj + k0) : z;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int bb = J * 16 + drow<T>(lk, v);
-      const int aa = I * 16 + li;
-      if (aa < bb && bb < c) {
-        const long long g = base + aa + c2(bb);
-        const double t1 = a.dst[g * a.stride];
-        a.dst[g * a.stride] = (t1 + (double)acc[ti][v]) * (1.0 / 3.0);
+        for (int e = 0; e < 4; ++e) {
+          acc = mfma(yi[e], uj[e], acc);
+          acc = mfma(ui[e], yj[e], acc);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = mfma(yi[e], yj[e], acc);
       }
     }
   }
-}
-
-// B(r1, r2) by 16 lanes (lane k owns elements k, k + 16, ...), summed by the
-// caller in a fixed order
-template <typename T, bool ZMODE, int PW>
-__device__ __forceinline__ double bform16(const T* Y, const T* U, int r1, int r2, int k) {
-  double v = 0.0;
 #pragma unroll
-  for (int c = 0; c < PW / 16; ++c) {
-    const size_t o1 = (size_t)r1 * PW + 16 * c + k, o2 = (size_t)r2 * PW + 16 * c + k;
-    if (ZMODE)
-      v += (double)Y[o1] * (double)U[o2] + (double)U[o1] * (double)Y[o2];
-    else
-      v += (double)Y[o1] * (double)Y[o2];
+  for (int v = 0; v < 4; ++v) {
+    const int ii = 16 * I + drow<T>(lk, v);
+    if (ii < q && j < q) a.star[((size_t)lg * q + ii) * q + j] = (double)acc[v];
   }
-  return v;
 }
 
-// degree 3: 16 lanes per class {a<b<c}, id = off3 + a + C(b,2) + C(c,3)
-template <typename T, bool ZMODE, int PW>
-__global__ __launch_bounds__(256) void k_bqp3(BqpArgs a) {
-  const long long t = ((long long)blockIdx.x * 256 + threadIdx.x) >> 4;
-  const int k = threadIdx.x & 15;
-  const int q = a.q;
-  const bool ok = t < c3(q);
-  int c = 2, b = 1, aa = 0;
-  if (ok) {
-    c = inv_c3(t);
-    const long long t2 = t - c3(c);
-    b = inv_c2(t2);
-    aa = (int)(t2 - c2(b));
+// One launch for the whole structured class-sum pass before its finisher:
+// blocks [0, n4) take degree-4 items, the blocks after them give one T or star
+// tile to each of their four waves (those start as the degree-4 blocks drain).
+template <typename T, bool ZMODE>
+__global__ __launch_bounds__(256) void k_bqp_sums(BqpArgs a, int n, int n4, int nTx, int nTy, int nS) {
+  if ((int)blockIdx.x < n4) {
+    bqp4_block<T, ZMODE>(a, blockIdx.x);
+    return;
   }
-  const T* Y = (const T*)a.Yp;
-  const T* U = (const T*)a.Up;
-  double v = 0.0;
-  if (ok)
-    v = bform16<T, ZMODE, PW>(Y, U, 1 + aa, prow(q, b, c), k) + bform16<T, ZMODE, PW>(Y, U, 1 + b, prow(q, aa, c), k) +
-        bform16<T, ZMODE, PW>(Y, U, 1 + c, prow(q, aa, b), k);
-  v = sum16(v);
-  if (ok && k == 0) a.dst[(a.off3 + t) * a.stride] = v * (1.0 / 3.0);
+  const int task = ((int)blockIdx.x - n4) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int nT = nTx * nTy;
+  if (task < nT)
+    bqpT_tile<T, ZMODE>(a, n, task % nTx, task / nTx, lane);
+  else if (task < nT + nS * STAR_LG)
+    bqpStar_tile<T, ZMODE>(a, (task - nT) % nS, (task - nT) / nS, lane);
 }
 
-// degrees 2 and 1: one wave per class; 4 groups of 16 lanes split the sum
-// over the third index, combined in a fixed order
-template <typename T, bool ZMODE, int PW>
-__global__ __launch_bounds__(256) void k_bqp21(BqpArgs a) {
-  const int q = a.q;
-  const long long t = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63, k = lane & 15, g = lane >> 4;
-  const long long n2 = c2(q);
-  const T* Y = (const T*)a.Yp;
-  const T* U = (const T*)a.Up;
-  double v = 0.0;
-  long long out = -1;
-  if (t < n2) {
-    const int j = inv_c2(t);
-    const int i = (int)(t - c2(j));
-    if (g == 0) v = bform16<T, ZMODE, PW>(Y, U, 0, prow(q, i, j), k) + bform16<T, ZMODE, PW>(Y, U, 1 + i, 1 + j, k);
-    for (int l = g; l < q; l += 4) {
-      if (l == i || l == j) continue;
-      const int ri = l < i ? prow(q, l, i) : prow(q, i, l);
-      const int rj = l < j ? prow(q, l, j) : prow(q, j, l);
-      v += bform16<T, ZMODE, PW>(Y, U, ri, rj, k);
-    }
-    out = a.off2 + t;
-  } else if (t < n2 + q) {
-    const int i = (int)(t - n2);
-    if (g == 0) v = bform16<T, ZMODE, PW>(Y, U, 0, 1 + i, k);
-    for (int j = g; j < q; j += 4) {
-      if (j == i) continue;
-      v += bform16<T, ZMODE, PW>(Y, U, 1 + j, j < i ? prow(q, j, i) : prow(q, i, j), k);
-    }
-    out = 1 + i;
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  if (out >= 0 && lane == 0) a.dst[out * a.stride] = v / (double)q;
-}
-
-// degree 0: partial sums of B(alpha, alpha) / 2 ... per block (16 lanes per row)
-template <typename T, bool ZMODE, int PW>
-__global__ __launch_bounds__(256) void k_bqp0(BqpArgs a, int n) {
-  __shared__ double red[16];
-  const int r = (blockIdx.x * 256 + threadIdx.x) >> 4;
-  const int k = threadIdx.x & 15;
-  const T* Y = (const T*)a.Yp;
-  const T* U = (const T*)a.Up;
-  double v = (r < n) ? bform16<T, ZMODE, PW>(Y, U, r, r, k) : 0.0;
-  v = sum16(v);
-  if (k == 0) red[threadIdx.x >> 4] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
+// Finisher of the structured class sums, one launch: the first nb01 blocks
+// take the classes of degree 0 and 1 (one wave each, lanes split the sum,
+// fixed butterfly order): {} = sum of the degree-0 partials / n,
+// {i} = (({}|i) + sum_j (j|ij)) / q; the other blocks take the classes of
+// degree 2 and 3 (one thread each).
+template <typename T, bool ZMODE>
+__global__ __launch_bounds__(256) void k_bqpFin(BqpArgs a, int n, int nblkT, int nb01) {
+  const int q = a.q, ldT = q + 1;
+  const double* Tt = a.T;
+  if ((int)blockIdx.x < nb01) {
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (g > q) return;
     double s = 0.0;
-    for (int i = 0; i < 16; ++i) s += red[i];
-    a.part[blockIdx.x] = s;
+    if (g == 0) {
+      for (int i = lane; i < nblkT; i += 64) s += a.part[i];
+    } else {
+      const int i = g - 1;
+      if (lane == 0) s = Tt[(size_t)(1 + i) * ldT];
+      for (int j = lane; j < q; j += 64)
+        if (j != i) s += Tt[(size_t)pair_row(q, i, j) * ldT + 1 + j];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) bqp_store<T, ZMODE>(a, g, s / (double)(g == 0 ? n : q));
+    return;
   }
-}
-
-// fixed-order reduction of `cnt` partials by one 256-thread block
-__device__ __forceinline__ double block_sum(const double* __restrict__ x, int cnt, double* red) {
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < cnt; i += 256) acc += x[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
+  const long long g = a.off2 + (long long)(blockIdx.x - nb01) * 256 + threadIdx.x;
+  if (g >= a.off4) return;
+  double val;
+  if (g < a.off3) {
+    const long long t = g - a.off2;
+    const int j = inv_c2(t), i = (int)(t - c2(j));
+    double sp[STAR_LG];
+#pragma unroll
+    for (int lg = 0; lg < STAR_LG; ++lg) sp[lg] = a.star[((size_t)lg * q + i) * q + j];
+    double s = Tt[(size_t)prow(q, i, j) * ldT] + Tt[(size_t)(1 + i) * ldT + 1 + j];
+#pragma unroll
+    for (int lg = 0; lg < STAR_LG; ++lg) s += sp[lg];
+    val = s / (double)q;
+  } else {
+    const long long t = g - a.off3;
+    const int c = inv_c3(t);
+    const long long t2 = t - c3(c);
+    const int b = inv_c2(t2), aa = (int)(t2 - c2(b));
+    val = (Tt[(size_t)prow(q, b, c) * ldT + 1 + aa] + Tt[(size_t)prow(q, aa, c) * ldT + 1 + b] +
+           Tt[(size_t)prow(q, aa, b) * ldT + 1 + c]) *
+          (1.0 / 3.0);
   }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
-
-__global__ __launch_bounds__(256) void k_bqp0_final(BqpArgs a, int nblk, int n) {
-  __shared__ double red[256];
-  const double s = block_sum(a.part, nblk, red);
-  if (threadIdx.x == 0) a.dst[0] = s / (double)n;
+  bqp_store<T, ZMODE>(a, g, val);
 }
 
 // ---------------------------------------------------------------------------
@@ -1454,52 +1762,51 @@ mdsdp_status launch_stage(mdsdp_problem P, int p, const double* Y, const double*
 static mdsdp_status launch_bqp(mdsdp_problem P, bool zmode, bool fp32, hipStream_t s) {
   BqpArgs b{};
   b.q = P->bqp_q;
+  b.pw = P->pw;
+  b.nkc = (P->last_p + 15) / 16;
   b.off2 = P->bqp_off[2];
   b.off3 = P->bqp_off[3];
   b.off4 = P->bqp_off[4];
   b.Yp = P->Yp;
   b.Up = P->Up;
-  b.items = P->bqp4a_items;
-  b.cd = P->bqp_cd;
-  b.ncd = P->bqp_ncd;
+  b.items = P->bqp4_items;
+  b.T = P->bqpT;
+  b.star = P->bqpStar;
   b.dst = zmode ? P->yp : (double*)P->cy + 1;
   b.stride = zmode ? 1 : 2;
   b.part = P->gpart + GP_BQP0;
-  b.nk = (P->last_p + 3) / 4;
-  const int q = P->bqp_q;
-  const long long n3 = (long long)q * (q - 1) * (q - 2) / 6, n2 = (long long)q * (q - 1) / 2;
-  const int nrowblk = (P->n * 16 + 255) / 256;
-#define BQP_LAUNCH(TT, ZZ, PWX)                                                                 \
-  do {                                                                                          \
-    timer_begin(P, s, "bqp4a");                                                                 \
-    if (P->bqp4a_n > 0) k_bqp4a<TT, ZZ, PWX><<<P->bqp4a_n, 256, 0, s>>>(b);                     \
-    timer_end(P, s);                                                                            \
-    timer_begin(P, s, "bqp4b");                                                                 \
-    if (P->bqp_ncd > 0) k_bqp4b<TT, ZZ, PWX><<<P->bqp_ncd, 256, 0, s>>>(b);                    \
-    timer_end(P, s);                                                                            \
-    timer_begin(P, s, "bqp3");                                                                  \
-    if (n3 > 0) k_bqp3<TT, ZZ, PWX><<<blocks_for(n3 * 16, 256), 256, 0, s>>>(b);                 \
-    timer_end(P, s);                                                                            \
-    timer_begin(P, s, "bqp21");                                                                 \
-    k_bqp21<TT, ZZ, PWX><<<blocks_for((n2 + q) * 64, 256), 256, 0, s>>>(b);                      \
-    timer_end(P, s);                                                                            \
-    timer_begin(P, s, "bqp0");                                                                  \
-    k_bqp0<TT, ZZ, PWX><<<nrowblk, 256, 0, s>>>(b, P->n);                                       \
-    k_bqp0_final<<<1, 256, 0, s>>>(b, nrowblk, P->n);                                          \
-    timer_end(P, s);                                                                            \
+  b.dst32 = P->ab32;
+  b.scale32 = -P->sigma;
+  const int q = P->bqp_q, n = P->n;
+  const unsigned nblkT = (unsigned)((n + 15) / 16), ncolT = (unsigned)((q + 1 + 15) / 16);
+  const unsigned nqt = (unsigned)((q + 15) / 16), ntile = nqt * (nqt + 1) / 2;
+  const int nS = (int)ntile;
+  const long long ntask = (long long)nblkT * ncolT + (long long)nS * STAR_LG;
+  const unsigned nsum = (unsigned)P->bqp4_n + (unsigned)((ntask + 3) / 4);
+  const int nb01 = (q + 1 + 3) / 4;
+  const unsigned nfin = (unsigned)nb01 + blocks_for(b.off4 - b.off2, 256);
+#define BQP_LAUNCH(TT, ZZ)                                                                                  \
+  do {                                                                                                      \
+    timer_begin(P, s, "bqp_sums");                                                                          \
+    k_bqp_sums<TT, ZZ><<<nsum, 256, 0, s>>>(b, n, P->bqp4_n, (int)nblkT, (int)ncolT, nS);                   \
+    timer_end(P, s);                                                                                        \
+    timer_begin(P, s, "bqp_fin");                                                                           \
+    k_bqpFin<TT, ZZ><<<nfin, 256, 0, s>>>(b, n, (int)nblkT, nb01);                                          \
+    timer_end(P, s);                                                                                        \
   } while (0)
   if (!zmode)
-    PW_DISPATCH(P->pw, BQP_LAUNCH(double, false, PWV));
+    BQP_LAUNCH(double, false);
   else if (fp32)
-    PW_DISPATCH(P->pw, BQP_LAUNCH(float, true, PWV));
+    BQP_LAUNCH(float, true);
   else
-    PW_DISPATCH(P->pw, BQP_LAUNCH(double, true, PWV));
+    BQP_LAUNCH(double, true);
 #undef BQP_LAUNCH
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
 
 mdsdp_status launch_classsum_S(mdsdp_problem P, hipStream_t s) {
+  P->a32_valid = false;
   timer_begin(P, s, "classsum_S");
   if (P->bqp_q > 0) {
     mdsdp_status st = launch_bqp(P, false, false, s);
@@ -1525,7 +1832,10 @@ mdsdp_status launch_classsum_Z(mdsdp_problem P, bool fp32, hipStream_t s) {
       PW_DISPATCH(P->pw, (k_classsum<float, true, PWV><<<seg_grid(P), 256, 0, s>>>(a)));
     else
       PW_DISPATCH(P->pw, (k_classsum<double, true, PWV><<<seg_grid(P), 256, 0, s>>>(a)));
-    k_final_Z<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->scal, P->yp);
+    if (fp32)
+      k_final_Z32<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->scal, P->sigma, P->ab32);
+    else
+      k_final_Z<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->scal, P->yp);
   }
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
@@ -1585,6 +1895,56 @@ mdsdp_status launch_resid(mdsdp_problem P, int mode, bool fp32, hipStream_t s) {
   return MDSDP_OK;
 }
 
+template <int SW>
+static mdsdp_status hvp32_go(mdsdp_problem P, const H32Args& a, unsigned g, hipStream_t s) {
+  typedef H32Lds<SW> L;
+  static bool attr_set[64] = {};
+  const int dev = P->device & 63;
+  if (L::bytes > 65536 && !attr_set[dev]) {
+    MDSDP_HIP(hipFuncSetAttribute((const void*)k_hvp32<SW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)L::bytes));
+    attr_set[dev] = true;
+  }
+  k_hvp32<SW><<<g, 256, L::bytes, s>>>(a);
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_hvp32(mdsdp_problem P, hipStream_t s) {
+  if (!P->a32_valid) {
+    k_make_a32<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->cy, P->sigma, P->ab32);
+    P->a32_valid = true;
+  }
+  H32Args a{};
+  a.cls = P->cls;
+  a.Xt32 = P->Xt32;
+  a.Ct = P->Ct;
+  a.segs = P->segs;
+  a.nseg = P->nseg;
+  a.seg_per_xcd = (P->nseg + 7) / 8;
+  a.pw = P->pw;
+  const int sw = std::min(P->pw, 64);
+  a.nsl = P->pw / sw;
+  a.Yp = (const float*)P->Yp;
+  a.Up = (const float*)P->Up;
+  a.ab32 = P->ab32;
+  a.sigma = (float)P->sigma;
+  a.rowpart = (float*)P->rowpart;
+  a.colpart = (float*)P->colpart;
+  const unsigned g = (unsigned)(8 * a.seg_per_xcd * a.nsl);
+  mdsdp_status st = MDSDP_OK;
+  timer_begin(P, s, "resid_hvp32");
+  if (sw == 16)
+    st = hvp32_go<16>(P, a, g, s);
+  else if (sw == 32)
+    st = hvp32_go<32>(P, a, g, s);
+  else
+    st = hvp32_go<64>(P, a, g, s);
+  timer_end(P, s);
+  if (st != MDSDP_OK) return st;
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
 static RowArgs row_args(mdsdp_problem P, int p) {
   RowArgs ra;
   ra.n = P->n;
@@ -1610,7 +1970,7 @@ mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* 
     k_gram_part<PWV><<<dim3(nblk, GramSplit<PWV>::NGRP), 256, 0, s>>>(P->n, p, Y, U, P->gpart + GP_GRAM);
     nparts = nblk * GramSplit<PWV>::RS;
   });
-  k_gram_final<<<(len + 255) / 256, 256, 0, s>>>(nparts, len, P->gpart + GP_GRAM, P->gram, gpw);
+  k_gram_final<<<(len + 3) / 4, 256, 0, s>>>(nparts, len, P->gpart + GP_GRAM, P->gram, gpw);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -1620,7 +1980,7 @@ mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, doubl
                                   double* f, hipStream_t s) {
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_grad");
-  k_row_grad<<<blocks_for((long long)P->n * std::min(P->pw, 64), 256), 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
+  k_row_grad<<<blocks_for((long long)P->n * 64, 256), 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
   k_scalars<<<1, 256, 0, s>>>(M_GRAD, P->wgpart, P->nseg, nullptr, 0, P->gpart + GP_BTY, 64, P->sigma, P->scal, f,
                               nullptr);
   timer_end(P, s);
@@ -1632,12 +1992,11 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
                                  double* HU, int riem, hipStream_t s) {
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_hvp");
+  const unsigned nblk = blocks_for((long long)P->n * 64, 256);  // L * SPL = 64 lanes per row
   if (fp32)
-    k_row_hvp<float><<<blocks_for((long long)P->n * std::min(P->pw, 64), 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec, P->sigma,
-                                                                            1, riem, HU);
+    k_row_hvp<float><<<nblk, 256, 0, s>>>(ra, Y, U, P->gram, P->zvec, P->sigma, riem, HU);
   else
-    k_row_hvp<double><<<blocks_for((long long)P->n * std::min(P->pw, 64), 256), 256, 0, s>>>(ra, Y, U, P->gram, P->zvec,
-                                                                             P->sigma, 0, riem, HU);
+    k_row_hvp<double><<<nblk, 256, 0, s>>>(ra, Y, U, P->gram, P->zvec, P->sigma, riem, HU);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;

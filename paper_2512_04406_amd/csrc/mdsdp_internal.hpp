@@ -34,6 +34,7 @@ constexpr int GRAM_U = PMAX * PMAX;  // offset of Y^T U in the Gram buffer
 constexpr int HBUF_LEN = 64 + PMAX * PMAX;  // pinned read-back buffer (doubles)
 constexpr int TSLOTS = TS * TS;  // slots per tile
 constexpr int LP = 17;          // LDS row pitch (elements) for 16-wide rows
+constexpr int STAR_LG = 32;     // residue classes of l in the degree-2 BQP contraction
 constexpr uint32_t CLS_MASK = 0x3FFFFFFFu;
 constexpr uint32_t OWNER_BIT = 0x40000000u;
 
@@ -86,6 +87,8 @@ struct mdsdp_problem_s {
   int* seg_start = nullptr;     // nb + 1: segments of column block J are seg_start[J]..seg_start[J+1]-1
   double2* cy = nullptr;        // m: {D_gamma, y_gamma} (y = class average of Z at the last S-pass)
   double* yp = nullptr;         // m: class average of Y U^T + U Y^T at the last HVP
+  float2* ab32 = nullptr;       // m: FP32-tile HVP class coefficients {D - sigma y (of U), -sigma y' (of Y)}
+  bool a32_valid = false;       // ab32[].x matches the current y and sigma
   double* invc = nullptr;       // m: 1 / |gamma|
   double* bvec = nullptr;       // m: b
   double* Cavg = nullptr;       // m or null: A(C)_gamma / |gamma|
@@ -94,10 +97,10 @@ struct mdsdp_problem_s {
   // structured BQP path (colex basis and class order), q = 0 when generic
   int bqp_q = 0;
   long long bqp_off[6] = {0, 0, 0, 0, 0, 0};
-  int4* bqp4a_items = nullptr;  // (c, d0, pi0, 0) work items of the (ab|cd) pass
-  int bqp4a_n = 0;
-  int2* bqp_cd = nullptr;       // (c, d) pairs, 2 <= c < d < q
-  int bqp_ncd = 0;
+  int4* bqp4_items = nullptr;   // (c, d0, a0, b0) work items of the degree-4 pass
+  int bqp4_n = 0;
+  double* bqpT = nullptr;       // n x (q + 1) table of the degree 0..3 pass
+  double* bqpStar = nullptr;    // STAR_LG x q x q partials of the degree-2 contraction
   // staging / workspace
   void* Yp = nullptr;           // npad x 16 (double or float)
   void* Up = nullptr;
@@ -165,6 +168,7 @@ mdsdp_status launch_classsum_S(mdsdp_problem P, hipStream_t s);
 mdsdp_status launch_classsum_Z(mdsdp_problem P, bool fp32, hipStream_t s);
 mdsdp_status launch_bty(mdsdp_problem P, hipStream_t s);
 mdsdp_status launch_resid(mdsdp_problem P, int mode, bool fp32, hipStream_t s);
+mdsdp_status launch_hvp32(mdsdp_problem P, hipStream_t s);
 mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* U,
                          hipStream_t s);
 mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, double* egrad,

@@ -95,6 +95,7 @@ class Problem:
         call("mdsdp_problem_info", self._h, C.byref(n), C.byref(m), C.byref(ns), C.byref(nt))
         self.n, self.m, self.n_slots, self.n_tiles = n.value, m.value, ns.value, nt.value
         self.sigma = 1.0
+        self._ad_key = None  # point of the last cost/gradient pass made for autograd
 
     # ---- construction -------------------------------------------------------
     @classmethod
@@ -151,6 +152,7 @@ class Problem:
 
     # ---- multiplier -----------------------------------------------------------
     def set_multiplier(self, Xt: torch.Tensor | None, sigma: float) -> None:
+        self._ad_key = None
         if Xt is not None:
             _dev_f64(Xt, "Xt")
             if Xt.shape != (self.n, self.n):
@@ -159,6 +161,7 @@ class Problem:
         self.sigma = float(sigma)
 
     def set_sigma(self, sigma: float) -> None:
+        self._ad_key = None
         call("mdsdp_set_sigma", self._h, float(sigma))
         self.sigma = float(sigma)
 
@@ -169,6 +172,7 @@ class Problem:
 
     # ---- evaluations ------------------------------------------------------------
     def cost_grad(self, Y: torch.Tensor, want_egrad: bool = True, want_rgrad: bool = True):
+        self._ad_key = None
         _dev_f64(Y, "Y")
         n, p = Y.shape
         f = torch.empty(1, dtype=torch.float64, device=Y.device)
@@ -188,12 +192,14 @@ class Problem:
         return out
 
     def class_average(self, Y: torch.Tensor) -> torch.Tensor:
+        self._ad_key = None
         _dev_f64(Y, "Y")
         y = torch.empty(self.m, dtype=torch.float64, device=Y.device)
         call("mdsdp_class_average", self._h, Y.shape[1], _ptr(Y), _ptr(y), _stream())
         return y
 
     def update_multiplier(self, Y: torch.Tensor):
+        self._ad_key = None
         _dev_f64(Y, "Y")
         y = torch.empty(self.m, dtype=torch.float64, device=Y.device)
         z = torch.empty(self.n, dtype=torch.float64, device=Y.device)
@@ -252,6 +258,7 @@ class Problem:
         return o
 
     def solve(self, Y0: torch.Tensor, opts: Options | None = None, history_cap: int = 1000) -> SolveResult:
+        self._ad_key = None
         _dev_f64(Y0, "Y0")
         opts = opts or self.default_options()
         n, p0 = Y0.shape

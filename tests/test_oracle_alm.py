@@ -78,3 +78,33 @@ def test_q8_value_bounds(seed):
     fmin, _ = brute.brute_force_min(Q, c)
     assert max(res.eta) <= 1e-8
     assert res.value <= fmin + 1e-8 * (1 + abs(fmin))
+
+
+def test_adjoint_of_value_in_C_by_central_differences():
+    """dv/dC = X + Diag z = Xt + D (Lagrangian duality: C enters the Lagrangian
+    of DSDP as <X + Diag z, C>), checked by central differences of oracle
+    re-solves at a generic strictly feasible C0 (zero diagonal, ||C0||_2 = 1/2)
+    along a zero-diagonal E.  A dropped D or a sign error in the multiplier
+    update fails it.  (At C = 0 the tight relaxation is degenerate and v has a
+    kink along such E, so the point C0 is generic on purpose.)"""
+    from oracle.operators import D_matrix
+
+    q, seed, eps = 6, 3, 1e-4
+    Q, c = bqp_instance(q, seed)
+    rel = bqp.build_relaxation(Q, c, "colex")
+    n = rel.n
+    G = gaussian(n, n, 901)
+    G = G + G.T
+    np.fill_diagonal(G, 0.0)
+    G *= 0.5 / np.max(np.abs(np.linalg.eigvalsh(G)))
+    E = gaussian(n, n, 900)
+    E = E + E.T
+    np.fill_diagonal(E, 0.0)
+    opts = alm.ALMOptions(tol=1e-11)
+    Y0 = gaussian(n, 2, 100 + seed)
+    r0 = alm.solve(rel.cls, rel.counts, rel.b, Y0, opts, C=G)
+    pred = float(np.sum((r0.Xt + D_matrix(rel.b, rel.cls, rel.counts)) * E))
+    vp = alm.solve(rel.cls, rel.counts, rel.b, Y0, opts, C=G + eps * E).value
+    vm = alm.solve(rel.cls, rel.counts, rel.b, Y0, opts, C=G - eps * E).value
+    fd = (vp - vm) / (2 * eps)
+    assert abs(fd - pred) <= 1e-3 * (1 + abs(pred))
