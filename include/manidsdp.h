@@ -35,8 +35,10 @@
  *    become valid when the stream reaches them.
  *  - Argument errors are detected synchronously (MDSDP_EINVAL) before any work
  *    is enqueued.  A problem handle must not be used from two streams at once.
- *  - p may be 1..128 for every call that takes a factor width (staged in
- *    widths 16, 32, 64 or 128: MFMA tiles are 16 wide).
+ *  - p may be 1..512 for every call that takes a factor width (staged in
+ *    widths 16, 32, 64 or a multiple of 64; the product kernels work on
+ *    slices of at most 64 columns, MFMA tiles are 16 wide).  p > 512 returns
+ *    MDSDP_EUNSUPPORTED.
  */
 #ifndef MANIDSDP_H
 #define MANIDSDP_H
@@ -135,7 +137,8 @@ mdsdp_status mdsdp_set_sigma(mdsdp_problem prob, double sigma);
  * Proposition prop. */
 mdsdp_status mdsdp_cost_grad(mdsdp_problem prob, int32_t p, const double* Y_dev, double* f_dev,
                              double* egrad_dev, double* rgrad_dev, void* stream);
-/* HVP at the Y of the last mdsdp_cost_grad call (same Y_dev contents).
+/* HVP at the Y of the last mdsdp_cost_grad call (same Y_dev contents; the
+ * class averages, diag(G S) and Y^T Y of that point are reused).
  * riemannian = 0: ehess[U]; 1: rhess[U] (U should be tangent).  prec selects
  * the tile precision.  Proposition prop, eq. sec4:eq7. */
 mdsdp_status mdsdp_hvp(mdsdp_problem prob, int32_t p, int32_t prec, const double* Y_dev,
@@ -158,7 +161,7 @@ mdsdp_status mdsdp_project_tangent(int32_t n, int32_t p, const double* Y_dev,
 mdsdp_status mdsdp_update_multiplier(mdsdp_problem prob, int32_t p, const double* Y_dev,
                                      double* y_dev, double* z_dev, double* kkt_dev, void* stream);
 /* X v = (Xt + D) v - z o v for k vectors (columns of V, n x k row-major,
- * k <= 128), with z from the last update_multiplier.  FP64. */
+ * k <= 512), with z from the last update_multiplier.  FP64. */
 mdsdp_status mdsdp_certificate_matvec(mdsdp_problem prob, int32_t k, const double* V_dev,
                                       double* XV_dev, void* stream);
 /* Smallest eigenpair and largest eigenvalue of X = Xt + D - Diag(z) by
@@ -179,7 +182,7 @@ typedef struct {
   double tol;          /* stop when eta_max <= tol (eq. res); default 1e-8 */
   int32_t max_outer;   /* default 200 */
   double sigma0, sigma_min, sigma_max, gamma, kappa1, kappa2; /* eq. sec5:eq1 */
-  int32_t p_max;       /* largest factor width, 1..128 */
+  int32_t p_max;       /* largest factor width, 1..512 (default 512) */
   int32_t n_neg;       /* negative-curvature directions added per outer step (Theorem sec5:thm1) */
   double tau_rank;     /* drop singular directions below tau_rank * s_1 */
   double gtol0, gtol_min;  /* inner tolerance max(gtol_min, min(gtol0, 0.1 eta, gtol_decay * previous)) */

@@ -141,7 +141,7 @@ static void free_problem(mdsdp_problem P) {
                   P->bqp4_items, P->bqpT,     P->bqpStar,
                   P->zvec,     P->zmult,  P->rowpart, P->colpart, P->wgpart, P->zpart,     P->gram,
                   P->gpart,    P->scal,   P->bound,   P->dotpart, (void*)P->dotptr, P->lz_V, P->lz_w,
-                  P->lz_h,     P->lz_hpart, P->work};
+                  P->lz_h,     P->lz_hpart, P->work,   P->Xt2,     P->lrbuf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (P->hbuf) (void)hipHostFree(P->hbuf);
@@ -316,6 +316,7 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   TRY(dalloc(&P->colpart, (size_t)P->nseg * 64 * PMAX));
   TRY(dalloc(&P->wgpart, (size_t)P->nseg * 4));
   TRY(dalloc(&P->zpart, (size_t)(n * PMAX + 255) / 256 + 1));
+  TRY(dalloc(&P->lrbuf, (size_t)n * PMAX));
   TRY(dalloc(&P->gram, 2 * GRAM_U));
   TRY(dalloc(&P->gpart, GP_SIZE));
   TRY(dalloc(&P->scal, SC_COUNT));
@@ -369,7 +370,7 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
 static mdsdp_status check_p(mdsdp_problem P, int p) {
   if (!P) return einval("problem is NULL");
   if (p < 1 || p > PMAX) {
-    set_error("p must be in [1, 128]");
+    set_error("p must be in [1, " + std::to_string(PMAX) + "]");
     return p < 1 ? MDSDP_EINVAL : MDSDP_EUNSUPPORTED;
   }
   return MDSDP_OK;
@@ -518,7 +519,10 @@ mdsdp_status mdsdp_hvp(mdsdp_problem P, int32_t p, int32_t prec, const double* Y
   const bool fp32 = prec == MDSDP_FP32;
   hipStream_t s = (hipStream_t)stream;
   if ((st = launch_stage(P, p, Y, U, fp32, s)) != MDSDP_OK) return st;
-  if ((st = launch_gram(P, p, Y, U, s)) != MDSDP_OK) return st;
+  const bool need_yy = !(P->gram_yy_valid && P->gram_yy_p == p);
+  if ((st = launch_gram(P, p, Y, U, s, need_yy)) != MDSDP_OK) return st;
+  P->gram_yy_valid = true;
+  P->gram_yy_p = p;
   if ((st = launch_classsum_Z(P, fp32, s)) != MDSDP_OK) return st;
   if ((st = fp32 ? launch_hvp32(P, s) : launch_resid(P, M_HVP, false, s)) != MDSDP_OK) return st;
   return launch_rowfinal_hvp(P, p, fp32, Y, U, HU, riemannian ? 1 : 0, s);

@@ -75,11 +75,14 @@ __device__ __forceinline__ int drow(int lk, int v) {
 struct KArgs {
   const uint32_t* cls;
   double* Xt;
+  double* Xt_out;       // multiplier update target (Xt itself, or a second buffer when sliced)
   float* Xt32;
   const double* Ct;
   const Seg* segs;
   int nseg, seg_per_xcd, nb;
   int nk;  // number of 4-wide K chunks covering p
+  int pw;  // row pitch of the staged factors (16, 32, 64 or a multiple of 64)
+  int nsl; // column slices of width min(pw, 64)
   const void* Yp;
   const void* Up;
   const double2* cy;    // {D, y}
@@ -172,29 +175,29 @@ __global__ __launch_bounds__(256) void k_stage(int n, int p, int npad, int pw, c
 // ---------------------------------------------------------------------------
 // class sums
 // ---------------------------------------------------------------------------
-template <typename T, bool ZMODE, int PW>
+template <typename T, bool ZMODE>
 __global__ __launch_bounds__(256) void k_classsum(KArgs a) {
   typedef typename V4<T>::type v4;
-  constexpr int NK = PW / 4;
   const int sidx = seg_of_block(blockIdx.x, a.seg_per_xcd, a.nseg);
   if (sidx < 0) return;
   const Seg sg = a.segs[sidx];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const T* Yp = (const T*)a.Yp;
   const T* Up = (const T*)a.Up;
+  const int pw = a.pw;
   const double ymax = bound_val(a.bound, 0);
   const double scale = ZMODE ? fx_scale(a.kmax, 2.0 * ymax * bound_val(a.bound, 1))
                              : fx_scale(a.kmax, ymax * ymax);
   if (sidx == 0 && tid == 0) a.scal[ZMODE ? SC_SCALE_Z : SC_SCALE_S] = scale;
   long long* acc_t = a.sacc;
   const int li = lane & 15, lk = lane >> 4;
-  const int nk = min(NK, a.nk);
+  const int nk = a.nk;
   for (int I = sg.I0; I <= sg.I1; ++I) {
     const long long t = (long long)sg.J * (sg.J + 1) / 2 + I;
     const double wgt = (I == sg.J) ? 1.0 : 2.0;
-    const size_t ra = (size_t)(I * 64 + w * 16 + li) * PW;
+    const size_t ra = (size_t)(I * 64 + w * 16 + li) * pw;
     for (int sc = 0; sc < 4; ++sc) {
-      const size_t rb = (size_t)(sg.J * 64 + sc * 16 + li) * PW;
+      const size_t rb = (size_t)(sg.J * 64 + sc * 16 + li) * pw;
       v4 acc = {0, 0, 0, 0};
       for (int j = 0; j < nk; ++j) {
         const int k = 4 * j + lk;
@@ -223,16 +226,19 @@ __global__ __launch_bounds__(256) void k_classsum(KArgs a) {
 // ---------------------------------------------------------------------------
 // residual / product pass
 // ---------------------------------------------------------------------------
-// The FP64 HVP at width 128 is split into two 64-column slices (blockIdx.y):
-// it needs no S tile, so the slices share nothing but the class data reads.
-template <typename T, int MODE, int PW>
+// Factor columns are cut into slices of SW = min(pw, 64) columns
+// (blockIdx.y); a workgroup forms the products of one slice.  The S tile needs
+// the whole contraction over p: with one slice it comes from the staged slabs
+// themselves, with several the rows are staged chunk by chunk (64 columns) and
+// the S tile is accumulated before the slice is staged for the products.  With
+// several slices the multiplier update writes a second buffer (Xt_out, slice 0
+// only) while every slice reads the old Xt, and only slice 0 adds the cost
+// and KKT partial sums.
+template <typename T, int MODE, int SW>
 struct ResidLds {
   static constexpr bool NEED_Y = (MODE != M_XMV);
   static constexpr bool SEPARATE_U = (MODE == M_HVP || MODE == M_XMV);
   static constexpr bool HAS_B = (MODE == M_HVP);
-  static constexpr bool SLICED = (MODE == M_HVP && sizeof(T) == 8 && PW > 64);
-  static constexpr int SW = SLICED ? 64 : PW;  // columns per block
-  static constexpr int NSL = PW / SW;
   static constexpr int LPW = SW + 1;
   static constexpr size_t slab = 64 * LPW;  // one 64-row slice
   static constexpr size_t nslab = (NEED_Y ? 2 : 0) + (SEPARATE_U ? 2 : 0);
@@ -240,16 +246,28 @@ struct ResidLds {
   static constexpr size_t bytes = (nslab * slab + (HAS_B ? 8 : 4) * tbuf) * sizeof(T) + 256 * sizeof(double);
 };
 
-template <typename T, int MODE, int PW>
+// 64 rows x SW columns (from column col0, row pitch pw) into LDS (row pitch SW + 1)
+template <int SW, typename T>
+__device__ __forceinline__ void load_slab(T* sdst, const T* src, int row0, int col0, int pw, int tid) {
+  for (int i = tid; i < 64 * SW; i += 256) {
+    const int r = i / SW, c = i % SW;
+    sdst[r * (SW + 1) + c] = src[(size_t)(row0 + r) * pw + col0 + c];
+  }
+}
+
+template <typename T, int MODE, int SW>
 __global__ __launch_bounds__(256) void k_resid(KArgs a) {
   typedef typename V4<T>::type v4;
-  typedef ResidLds<T, MODE, PW> L;
-  constexpr bool HAS_S = (MODE == M_GRAD || MODE == M_MULT || (MODE == M_HVP && sizeof(T) == 4));
+  typedef ResidLds<T, MODE, SW> L;
+  constexpr bool HAS_S = (MODE == M_GRAD || MODE == M_MULT);
   constexpr bool HAS_B = L::HAS_B;
   constexpr bool SEPARATE_U = L::SEPARATE_U;
   constexpr bool NEED_Y = L::NEED_Y;
-  constexpr int SW = L::SW, NC = SW / 16, LPW = L::LPW;
-  const int col0 = L::SLICED ? (int)blockIdx.y * SW : 0;
+  constexpr int NC = SW / 16, LPW = L::LPW;
+  const int pw = a.pw, nsl = a.nsl;
+  const int col0 = (int)blockIdx.y * SW;
+  const bool lead = blockIdx.y == 0;  // the slice that owns writes of entry data and scalar partials
+  const bool chunked = HAS_S && nsl > 1;
   const int sidx = seg_of_block(blockIdx.x, a.seg_per_xcd, a.nseg);
   if (sidx < 0) return;
   const Seg sg = a.segs[sidx];
@@ -282,11 +300,12 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
   const T* rY = sYr;
   const T* cU = SEPARATE_U ? sUc : sYc;
   const T* rU = SEPARATE_U ? sUr : sYr;
-  if (NEED_Y) load_rows<SW, PW>(sYc, Yp, sg.J * 64, col0, tid);
-  if (SEPARATE_U) load_rows<SW, PW>(sUc, Up, sg.J * 64, col0, tid);
+  if (!chunked) {
+    if (NEED_Y) load_slab<SW>(sYc, Yp, sg.J * 64, col0, pw, tid);
+    if (SEPARATE_U) load_slab<SW>(sUc, Up, sg.J * 64, col0, pw, tid);
+  }
 
   const double sigma = a.sigma;
-  const int nk = min(SW / 4, a.nk);
   v4 accC[4][NC];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -297,16 +316,9 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
   T* tBw = tB + w * L::tbuf;
 
   for (int I = sg.I0; I <= sg.I1; ++I) {
-    __syncthreads();
-    if (NEED_Y) load_rows<SW, PW>(sYr, Yp, I * 64, col0, tid);
-    if (SEPARATE_U) load_rows<SW, PW>(sUr, Up, I * 64, col0, tid);
-    __syncthreads();
     const long long t = (long long)sg.J * (sg.J + 1) / 2 + I;
     const bool diag = (I == sg.J);
     const double wgt = diag ? 1.0 : 2.0;
-    v4 accR[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) accR[c] = v4{0, 0, 0, 0};
     // ---- batched memory phase for this wave's 16 x 64 slab of the tile ----
     typedef typename std::conditional<sizeof(T) == 8 || MODE != M_HVP, double, float>::type XT;
     const size_t tb = (size_t)t * TSLOTS + (size_t)(w * 4) * 256 + li;
@@ -338,15 +350,42 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
     // S blocks of the four sub-blocks (MFMA from LDS, K = p)
     v4 Sbv[4];
 #pragma unroll
-    for (int sc = 0; sc < 4; ++sc) {
-      Sbv[sc] = v4{0, 0, 0, 0};
+    for (int sc = 0; sc < 4; ++sc) Sbv[sc] = v4{0, 0, 0, 0};
+    if (HAS_S && chunked) {
+      for (int kc = 0; kc < nsl; ++kc) {
+        __syncthreads();
+        load_slab<SW>(sYc, Yp, sg.J * 64, kc * SW, pw, tid);
+        load_slab<SW>(sYr, Yp, I * 64, kc * SW, pw, tid);
+        __syncthreads();
+#pragma unroll
+        for (int sc = 0; sc < 4; ++sc)
+          for (int j = 0; j < SW / 4; ++j) {
+            const int k = 4 * j + lk;
+            Sbv[sc] = mfma(rY[(w * 16 + li) * LPW + k], cY[(sc * 16 + li) * LPW + k], Sbv[sc]);
+          }
+      }
+      __syncthreads();
+      load_slab<SW>(sYc, Yp, sg.J * 64, col0, pw, tid);
+      load_slab<SW>(sYr, Yp, I * 64, col0, pw, tid);
+      __syncthreads();
+    } else {
+      __syncthreads();
+      if (NEED_Y) load_slab<SW>(sYr, Yp, I * 64, col0, pw, tid);
+      if (SEPARATE_U) load_slab<SW>(sUr, Up, I * 64, col0, pw, tid);
+      __syncthreads();
       if (HAS_S) {
-        for (int j = 0; j < nk; ++j) {
-          const int k = 4 * j + lk;
-          Sbv[sc] = mfma(rY[(w * 16 + li) * LPW + k], cY[(sc * 16 + li) * LPW + k], Sbv[sc]);
-        }
+        const int nk = min(SW / 4, a.nk);
+#pragma unroll
+        for (int sc = 0; sc < 4; ++sc)
+          for (int j = 0; j < nk; ++j) {
+            const int k = 4 * j + lk;
+            Sbv[sc] = mfma(rY[(w * 16 + li) * LPW + k], cY[(sc * 16 + li) * LPW + k], Sbv[sc]);
+          }
       }
     }
+    v4 accR[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) accR[c] = v4{0, 0, 0, 0};
 #pragma unroll
     for (int sc = 0; sc < 4; ++sc) {
 #pragma unroll
@@ -369,21 +408,18 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
               av = (T)(x + dy.x + sigma * r);
             } else {
               const double xn = x + sigma * r;
-              a.Xt[off] = xn;
-              a.Xt32[off] = (float)xn;
+              if (lead) {
+                a.Xt_out[off] = xn;
+                a.Xt32[off] = (float)xn;
+              }
               p_cx += wgt * Ce * (xn + dy.x);
               av = (T)(xn + dy.x);
             }
           } else if (MODE == M_XMV) {
             av = (T)((double)xv[sc][v] + dy.x);
-          } else {  // HVP
+          } else {  // HVP (FP64 tiles; the FP32-tile HVP is k_hvp32)
             bv = (T)(-sigma * yzv[sc][v]);
-            if (sizeof(T) == 8) {
-              av = (T)((double)xv[sc][v] + (dy.x - sigma * dy.y) + sigma * Ce);
-            } else {
-              const float rS = (float)Sbv[sc][v] + (float)(Ce - dy.y);
-              av = (T)((float)xv[sc][v] + (float)dy.x + (float)sigma * rS);
-            }
+            av = (T)((double)xv[sc][v] + (dy.x - sigma * dy.y) + sigma * Ce);
           }
         }
         tAw[rv * LP + li] = av;
@@ -419,15 +455,15 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     // row-side partial of this tile: rows w*16 + drow(lk, v), columns c*16 + li
-    T* rp = (T*)a.rowpart + ((size_t)t * 64 + w * 16) * PW + col0 + li;
+    T* rp = (T*)a.rowpart + ((size_t)t * 64 + w * 16) * pw + col0 + li;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) rp[drow<T>(lk, v) * PW + 16 * c] = accR[c][v];
+      for (int v = 0; v < 4; ++v) rp[drow<T>(lk, v) * pw + 16 * c] = accR[c][v];
   }
   // column-side partial of the segment: sum the four waves (row sub-blocks)
   T* cred = tA;  // 3 x 256 values (the transpose buffers are free now)
-  T* cp = (T*)a.colpart + (size_t)sidx * 64 * PW;
+  T* cp = (T*)a.colpart + (size_t)sidx * 64 * pw;
   for (int sc = 0; sc < 4; ++sc) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -446,12 +482,12 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
           sum += cred[0 * 256 + pc * 16 + li];
           sum += cred[1 * 256 + pc * 16 + li];
           sum += cred[2 * 256 + pc * 16 + li];
-          cp[(sc * 16 + li) * PW + col0 + c * 16 + pc] = sum;
+          cp[(sc * 16 + li) * pw + col0 + c * 16 + pc] = sum;
         }
       }
     }
   }
-  if (MODE == M_GRAD || MODE == M_MULT) {
+  if ((MODE == M_GRAD || MODE == M_MULT) && lead) {
     double vals[NWP] = {p_r2, p_xz, 0.0, p_cx};
     for (int qq = 0; qq < NWP; ++qq) {
       __syncthreads();
@@ -730,12 +766,12 @@ __device__ __forceinline__ double sum16(double v) {
   return v;
 }
 
-// Threads: L = min(pw, 64) lanes per row; lane c0 owns columns c0, c0 + L
-// (pw = 128); row dots are butterfly sums over the L lanes.
-constexpr int RMAXC = 2;  // columns per lane at most
-
+// Threads: L = min(pw, 64) lanes per row; lane c0 owns columns c0, c0 + L,
+// ... (RM of them, RM = pw / 64 rounded up to a power of two for pw > 64);
+// row dots are butterfly sums over the L lanes.
 __device__ __forceinline__ int row_lanes(int pw) { return pw < 64 ? pw : 64; }
 
+template <int RM>
 __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __restrict__ Y,
                                                   double* __restrict__ egrad, double* __restrict__ rgrad,
                                                   double* __restrict__ zvec) {
@@ -744,10 +780,10 @@ __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __re
   const int part = idx % spl, rc = idx / spl;
   const int r = rc / L, c0 = rc % L;
   const bool in = r < ra.n;
-  double gy[RMAXC], y[RMAXC];
+  double gy[RM], y[RM];
   double zp = 0.0;
 #pragma unroll
-  for (int j = 0; j < RMAXC; ++j) {
+  for (int j = 0; j < RM; ++j) {
     const int k = c0 + j * L;
     const bool kin = in && k < ra.p && k < ra.pw;
     gy[j] = sum_parts(kin ? row_sum<double>(ra, r, k, part, spl) : 0.0, spl);
@@ -757,7 +793,7 @@ __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __re
   const double z = sum_row_split(zp, L, spl);
   if (in && c0 == 0 && part == 0) zvec[r] = z;
 #pragma unroll
-  for (int j = 0; j < RMAXC; ++j) {
+  for (int j = 0; j < RM; ++j) {
     const int k = c0 + j * L;
     if (in && part == 0 && k < ra.p && k < ra.pw) {
       if (egrad) egrad[(size_t)r * ra.p + k] = 2.0 * gy[j];
@@ -766,11 +802,13 @@ __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __re
   }
 }
 
-template <typename T>
+// lr (nullable, n x p): precomputed low-rank term (wide factors); otherwise
+// it is formed here from the Gram matrices
+template <typename T, int RM>
 __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __restrict__ Y,
                                                  const double* __restrict__ U, const double* __restrict__ gram,
-                                                 const double* __restrict__ zvec, double sigma, int riem,
-                                                 double* __restrict__ HU) {
+                                                 const double* __restrict__ lr_pre, const double* __restrict__ zvec,
+                                                 double sigma, int riem, double* __restrict__ HU) {
   const int pw = ra.pw, L = row_lanes(pw), spl = row_split(pw);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int part = idx % spl, rc = idx / spl;
@@ -780,19 +818,23 @@ __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __res
   // rank-2p part of sigma (Y U^T + U Y^T) Y (the tiles carry neither)
   const double* YtY = gram;
   const double* YtU = gram + GRAM_U;
-  double Ht[RMAXC], y[RMAXC], u[RMAXC];
+  double Ht[RM], y[RM], u[RM];
   double dp = 0.0;
 #pragma unroll
-  for (int j = 0; j < RMAXC; ++j) {
+  for (int j = 0; j < RM; ++j) {
     const int k = c0 + j * L;
     const bool kin = in && k < ra.p && k < pw;
     double h = kin ? row_sum<T>(ra, r, k, part, spl) : 0.0;
     double lr = 0.0;
     if (kin) {
-      for (int i = part; i < ra.p; i += spl) {
-        const double yi = Y[(size_t)r * ra.p + i];
-        const double ui = U[(size_t)r * ra.p + i];
-        lr += yi * (YtU[k * pw + i] + YtU[i * pw + k]) + ui * YtY[i * pw + k];
+      if (lr_pre) {
+        if (part == 0) lr = lr_pre[(size_t)r * ra.p + k];
+      } else {
+        for (int i = part; i < ra.p; i += spl) {
+          const double yi = Y[(size_t)r * ra.p + i];
+          const double ui = U[(size_t)r * ra.p + i];
+          lr += yi * (YtU[k * pw + i] + YtU[i * pw + k]) + ui * YtY[i * pw + k];
+        }
       }
     }
     Ht[j] = 2.0 * sum_parts(h + sigma * lr, spl);
@@ -803,12 +845,45 @@ __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __res
   const double d = riem ? sum_row_split(dp, L, spl) : 0.0;
   const double zr = (riem && in) ? zvec[r] : 0.0;
 #pragma unroll
-  for (int j = 0; j < RMAXC; ++j) {
+  for (int j = 0; j < RM; ++j) {
     const int k = c0 + j * L;
     if (in && part == 0 && k < ra.p && k < pw) {
       const double v = riem ? Ht[j] - d * y[j] - 2.0 * zr * u[j] : Ht[j];
       HU[(size_t)r * ra.p + k] = v;
     }
+  }
+}
+
+// Low-rank part of the HVP for wide factors, as an FP64 MFMA product:
+// LR (n x p) = Y W1 + U W2, W1 = Y^T U + U^T Y, W2 = Y^T Y (row pitch pw in
+// `gram`).  One wave per 16 x 16 output tile, contraction over p in steps of 4.
+__global__ __launch_bounds__(256) void k_lowrank(int n, int p, int pw, const double* __restrict__ Y,
+                                                 const double* __restrict__ U, const double* __restrict__ gram,
+                                                 double* __restrict__ LR) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int ntc = (p + 15) / 16;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int rt = tile / ntc, ct = tile % ntc;
+  if (rt * 16 >= n) return;
+  const double* YtY = gram;
+  const double* YtU = gram + GRAM_U;
+  const int r = rt * 16 + li, c = ct * 16 + li;
+  const bool rok = r < n, cok = c < p;
+  v4d acc = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < p; k0 += 4) {
+    const int k = k0 + lk;
+    const bool kok = k < p;
+    const double ya = (rok && kok) ? Y[(size_t)r * p + k] : 0.0;
+    const double ua = (rok && kok) ? U[(size_t)r * p + k] : 0.0;
+    const double w1 = (cok && kok) ? YtU[k * pw + c] + YtU[c * pw + k] : 0.0;
+    const double w2 = (cok && kok) ? YtY[k * pw + c] : 0.0;
+    acc = mfma(ya, w1, acc);
+    acc = mfma(ua, w2, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rr = rt * 16 + drow<double>(lk, v);
+    if (rr < n && cok) LR[(size_t)rr * p + c] = acc[v];
   }
 }
 
@@ -821,10 +896,8 @@ __global__ __launch_bounds__(256) void k_row_mult(RowArgs ra, const double* __re
   const int r = idx / L, c0 = idx % L;
   const bool in = r < ra.n;
   double zp = 0.0;
-#pragma unroll
-  for (int j = 0; j < RMAXC; ++j) {
-    const int k = c0 + j * L;
-    const bool kin = in && k < ra.p && k < ra.pw;
+  for (int k = c0; k < ra.pw; k += L) {
+    const bool kin = in && k < ra.p;
     const double o = kin ? row_sum<double>(ra, r, k) : 0.0;
     zp += o * (kin ? Y[(size_t)r * ra.p + k] : 0.0);
   }
@@ -914,31 +987,33 @@ __global__ __launch_bounds__(256) void k_scalars(int mode, const double* __restr
 }
 
 // Gram matrices Y^T Y and Y^T U (pw x pw, FP64, row pitch pw) with MFMA over
-// 4-row chunks.  The NC x NC grid of 16 x 16 block pairs is spread over the
-// four waves and over NGRP groups (blockIdx.y) of at most 16 pairs, four per
-// wave; for NC = 1 the waves split the rows instead.  Every (block, row group)
-// writes its own partial; a fixed-order final sum follows.
-template <int PW>
+// 4-row chunks.  The NC x NC grid of 16 x 16 block pairs (NC = pw / 16) is
+// spread over the four waves and over groups (blockIdx.y) of at most 16
+// pairs, four per wave; for NC = 1 the waves split the rows instead.  Every
+// (block, row group) writes its own partial; a fixed-order final sum follows.
+// with_yy = 0 skips Y^T Y (kept from an earlier call at the same Y).
 struct GramSplit {
-  static constexpr int NC = PW / 16;
-  static constexpr int NPAIR = NC * NC;
-  static constexpr int RS = NPAIR >= 4 ? 1 : 4 / NPAIR;   // row groups
-  static constexpr int PPW = NPAIR >= 16 ? 4 : (NPAIR >= 4 ? NPAIR / 4 : 1);  // pairs per wave
-  static constexpr int NGRP = NPAIR >= 16 ? NPAIR / 16 : 1;                    // pair groups
+  int NC, NPAIR, RS, PPW, NGRP;
+  __host__ __device__ explicit GramSplit(int pw) {
+    NC = pw / 16;
+    NPAIR = NC * NC;
+    RS = NPAIR >= 4 ? 1 : 4 / NPAIR;                            // row groups
+    PPW = NPAIR >= 16 ? 4 : (NPAIR >= 4 ? NPAIR / 4 : 1);       // pairs per wave
+    NGRP = NPAIR >= 16 ? NPAIR / 16 : 1;                         // pair groups
+  }
 };
 
-template <int PW>
-__global__ __launch_bounds__(256) void k_gram_part(int n, int p, const double* __restrict__ Y,
+__global__ __launch_bounds__(256) void k_gram_part(int n, int p, int pw, int with_yy, const double* __restrict__ Y,
                                                    const double* __restrict__ U, double* __restrict__ part) {
-  typedef GramSplit<PW> GS;
-  constexpr int NC = GS::NC, RS = GS::RS, PPW = GS::PPW;
+  const GramSplit GS(pw);
+  const int NC = GS.NC, RS = GS.RS, PPW = GS.PPW;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const int per = (n + gridDim.x - 1) / gridDim.x;
   const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
   const int rg = w % RS, pbase = blockIdx.y * 4 * PPW + (w / RS) * PPW;
-  v4d ayy[PPW], ayu[PPW];
+  v4d ayy[4], ayu[4];
 #pragma unroll
-  for (int q = 0; q < PPW; ++q) {
+  for (int q = 0; q < 4; ++q) {
     ayy[q] = v4d{0, 0, 0, 0};
     ayu[q] = v4d{0, 0, 0, 0};
   }
@@ -947,34 +1022,39 @@ __global__ __launch_bounds__(256) void k_gram_part(int n, int p, const double* _
     const bool rok = r < r1;
     // A[i][k] = Y[r_k][i] (lane i + 16 k), B[k][j] = Y[r_k][j] / U[r_k][j]
 #pragma unroll
-    for (int q = 0; q < PPW; ++q) {
+    for (int q = 0; q < 4; ++q) {
+      if (q >= PPW) break;
       const int pr = pbase + q, bi = pr / NC, bj = pr % NC;
       const int ci = 16 * bi + li, cj = 16 * bj + li;
       const double yi = (rok && ci < p) ? Y[(size_t)r * p + ci] : 0.0;
-      const double yj = (rok && cj < p) ? Y[(size_t)r * p + cj] : 0.0;
       const double uj = (rok && cj < p) ? U[(size_t)r * p + cj] : 0.0;
-      ayy[q] = mfma(yi, yj, ayy[q]);
+      if (with_yy) {
+        const double yj = (rok && cj < p) ? Y[(size_t)r * p + cj] : 0.0;
+        ayy[q] = mfma(yi, yj, ayy[q]);
+      }
       ayu[q] = mfma(yi, uj, ayu[q]);
     }
   }
-  double* out = part + ((size_t)blockIdx.x * RS + rg) * 2 * PW * PW;
+  double* out = part + ((size_t)blockIdx.x * RS + rg) * 2 * pw * pw;
 #pragma unroll
-  for (int q = 0; q < PPW; ++q) {
+  for (int q = 0; q < 4; ++q) {
+    if (q >= PPW) break;
     const int pr = pbase + q, bi = pr / NC, bj = pr % NC;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int rr = drow<double>(lk, v);
-      out[(16 * bi + rr) * PW + 16 * bj + li] = ayy[q][v];
-      out[PW * PW + (16 * bi + rr) * PW + 16 * bj + li] = ayu[q][v];
+      if (with_yy) out[(16 * bi + rr) * pw + 16 * bj + li] = ayy[q][v];
+      out[pw * pw + (16 * bi + rr) * pw + 16 * bj + li] = ayu[q][v];
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_gram_final(int nblk, int len, const double* __restrict__ part,
+__global__ __launch_bounds__(256) void k_gram_final(int nblk, int len, int e0, const double* __restrict__ part,
                                                     double* __restrict__ gram, int pw) {
   // part: nblk x (2 pw^2); gram: Y^T Y at [0, pw^2), Y^T U at [GRAM_U, GRAM_U + pw^2).
-  // One wave per element: lanes take every 64th partial, then a butterfly.
-  const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  // Elements e0 .. len - 1; one wave per element: lanes take every 64th
+  // partial, then a butterfly.
+  const int e = e0 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (e >= len) return;
   double s = 0.0;
   for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * len + e];
@@ -1141,29 +1221,43 @@ __global__ __launch_bounds__(256) void k_fill(long long len, double v, double* o
   if (i < len) out[i] = v;
 }
 
-// truncated-CG update (Steihaug-Toint step), one thread per row.
+// truncated-CG update (Steihaug-Toint step): L lanes per row (L = the
+// smallest power of two >= p, at most 64), lane c0 owns columns c0, c0 + L, ...
 // part 1: eta += alpha d; Heta += alpha Hd; r = P_Y(r + alpha Hd); partial ||r||^2
-__global__ __launch_bounds__(256) void k_tcg_update1(int n, int p, const double* __restrict__ Y, double alpha,
-                                                     double* __restrict__ eta, double* __restrict__ Heta,
-                                                     double* __restrict__ r, const double* __restrict__ d,
-                                                     const double* __restrict__ Hd, double* __restrict__ part) {
+template <int RM>
+__global__ __launch_bounds__(256) void k_tcg_update1(int n, int p, int L, const double* __restrict__ Y,
+                                                     double alpha, double* __restrict__ eta,
+                                                     double* __restrict__ Heta, double* __restrict__ r,
+                                                     const double* __restrict__ d, const double* __restrict__ Hd,
+                                                     double* __restrict__ part) {
   __shared__ double red[256];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double rr = 0.0;
-  if (i < n) {
-    const size_t o = (size_t)i * p;
-    double rn[PMAX];
-    double dr = 0.0;
-    for (int k = 0; k < p; ++k) {
-      eta[o + k] += alpha * d[o + k];
-      Heta[o + k] += alpha * Hd[o + k];
-      rn[k] = r[o + k] + alpha * Hd[o + k];
-      dr += rn[k] * Y[o + k];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = idx / L, c0 = idx % L;
+  const bool in = i < n;
+  double rn[RM];
+  double dr = 0.0;
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    const int k = c0 + j * L;
+    rn[j] = 0.0;
+    if (in && k < p) {
+      const size_t o = (size_t)i * p + k;
+      eta[o] += alpha * d[o];
+      Heta[o] += alpha * Hd[o];
+      rn[j] = r[o] + alpha * Hd[o];
+      dr += rn[j] * Y[o];
     }
-    for (int k = 0; k < p; ++k) {
-      rn[k] -= dr * Y[o + k];
-      r[o + k] = rn[k];
-      rr += rn[k] * rn[k];
+  }
+  for (int off = L >> 1; off >= 1; off >>= 1) dr += __shfl_xor(dr, off, L);
+  double rr = 0.0;
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    const int k = c0 + j * L;
+    if (in && k < p) {
+      const size_t o = (size_t)i * p + k;
+      rn[j] -= dr * Y[o];
+      r[o] = rn[j];
+      rr += rn[j] * rn[j];
     }
   }
   red[threadIdx.x] = rr;
@@ -1176,38 +1270,58 @@ __global__ __launch_bounds__(256) void k_tcg_update1(int n, int p, const double*
 }
 
 // part 2: d = P_Y(-r + beta d) with beta read from device memory
-__global__ __launch_bounds__(256) void k_tcg_update2(int n, int p, const double* __restrict__ Y,
-                                                     const double* __restrict__ beta_dev, const double* __restrict__ r,
-                                                     double* __restrict__ d) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+template <int RM>
+__global__ __launch_bounds__(256) void k_tcg_update2(int n, int p, int L, const double* __restrict__ Y,
+                                                     const double* __restrict__ beta_dev,
+                                                     const double* __restrict__ r, double* __restrict__ d) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = idx / L, c0 = idx % L;
+  const bool in = i < n;
   const double beta = *beta_dev;
-  const size_t o = (size_t)i * p;
-  double dn[PMAX];
+  double dn[RM];
   double dd = 0.0;
-  for (int k = 0; k < p; ++k) {
-    dn[k] = -r[o + k] + beta * d[o + k];
-    dd += dn[k] * Y[o + k];
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    const int k = c0 + j * L;
+    dn[j] = 0.0;
+    if (in && k < p) {
+      const size_t o = (size_t)i * p + k;
+      dn[j] = -r[o] + beta * d[o];
+      dd += dn[j] * Y[o];
+    }
   }
-  for (int k = 0; k < p; ++k) d[o + k] = dn[k] - dd * Y[o + k];
+  for (int off = L >> 1; off >= 1; off >>= 1) dd += __shfl_xor(dd, off, L);
+#pragma unroll
+  for (int j = 0; j < RM; ++j) {
+    const int k = c0 + j * L;
+    if (in && k < p) {
+      const size_t o = (size_t)i * p + k;
+      d[o] = dn[j] - dd * Y[o];
+    }
+  }
 }
 
 // Yout (n x q) = Yin (n x p) M (p x q, row-major); optional row normalisation
+// (one thread per row; the row norm is taken in a first pass)
 __global__ __launch_bounds__(256) void k_rightmul(int n, int p, int q, const double* __restrict__ Yin,
                                                   const double* __restrict__ M, int normalize,
                                                   double* __restrict__ Yout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double out[PMAX];
   double nrm = 0.0;
+  if (normalize) {
+    for (int c = 0; c < q; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < p; ++k) s += Yin[(size_t)i * p + k] * M[k * q + c];
+      nrm += s * s;
+    }
+  }
+  const double inv = (normalize && nrm > 0.0) ? 1.0 / sqrt(nrm) : 1.0;
   for (int c = 0; c < q; ++c) {
     double s = 0.0;
     for (int k = 0; k < p; ++k) s += Yin[(size_t)i * p + k] * M[k * q + c];
-    out[c] = s;
-    nrm += s * s;
+    Yout[(size_t)i * q + c] = s * inv;
   }
-  const double inv = (normalize && nrm > 0.0) ? 1.0 / sqrt(nrm) : 1.0;
-  for (int c = 0; c < q; ++c) Yout[(size_t)i * q + c] = out[c] * inv;
 }
 
 // column `col` of U (n x p) = v; with zero_rest the other columns are cleared
@@ -1685,6 +1799,9 @@ static KArgs make_args(mdsdp_problem P) {
   a.seg_per_xcd = (P->nseg + 7) / 8;
   a.nb = P->nb;
   a.nk = (P->last_p + 3) / 4;
+  a.pw = P->pw;
+  a.nsl = P->pw > 64 ? P->pw / 64 : 1;
+  a.Xt_out = P->Xt;
   a.Yp = P->Yp;
   a.Up = P->Up;
   a.cy = P->cy;
@@ -1703,22 +1820,21 @@ static KArgs make_args(mdsdp_problem P) {
 
 static unsigned seg_grid(mdsdp_problem P) { return (unsigned)(8 * ((P->nseg + 7) / 8)); }
 
-// factor width of the staged tiles: 16, 32 or 64 columns
-int pw_of(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : (p <= 64 ? 64 : 128)); }
+// factor width of the staged tiles: 16, 32, 64, or a multiple of 64 (cut
+// into 64-column slices by the product kernels)
+int pw_of(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : (p <= 64 ? 64 : 64 * ((p + 63) / 64))); }
 
-#define PW_DISPATCH(pw, ...)      \
+// slice width of the product kernels for staged width pw
+#define SW_DISPATCH(pw, ...)      \
   do {                            \
     if ((pw) == 16) {             \
-      constexpr int PWV = 16;     \
+      constexpr int SWV = 16;     \
       __VA_ARGS__;                \
     } else if ((pw) == 32) {      \
-      constexpr int PWV = 32;     \
-      __VA_ARGS__;                \
-    } else if ((pw) == 64) {      \
-      constexpr int PWV = 64;     \
+      constexpr int SWV = 32;     \
       __VA_ARGS__;                \
     } else {                      \
-      constexpr int PWV = 128;    \
+      constexpr int SWV = 64;     \
       __VA_ARGS__;                \
     }                             \
   } while (0)
@@ -1742,6 +1858,7 @@ void timer_end(mdsdp_problem P, hipStream_t s) {
 
 mdsdp_status launch_stage(mdsdp_problem P, int p, const double* Y, const double* U, bool fp32,
                           hipStream_t s) {
+  if (!U) P->gram_yy_valid = false;  // an S-pass: Y may have changed
   P->last_p = p;
   P->pw = pw_of(p);
   timer_begin(P, s, "stage");
@@ -1813,7 +1930,7 @@ mdsdp_status launch_classsum_S(mdsdp_problem P, hipStream_t s) {
     if (st != MDSDP_OK) return st;
   } else {
     KArgs a = make_args(P);
-    PW_DISPATCH(P->pw, (k_classsum<double, false, PWV><<<seg_grid(P), 256, 0, s>>>(a)));
+    k_classsum<double, false><<<seg_grid(P), 256, 0, s>>>(a);
     k_final_S<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->Cavg, P->scal, P->cy);
   }
   timer_end(P, s);
@@ -1829,9 +1946,9 @@ mdsdp_status launch_classsum_Z(mdsdp_problem P, bool fp32, hipStream_t s) {
   } else {
     KArgs a = make_args(P);
     if (fp32)
-      PW_DISPATCH(P->pw, (k_classsum<float, true, PWV><<<seg_grid(P), 256, 0, s>>>(a)));
+      k_classsum<float, true><<<seg_grid(P), 256, 0, s>>>(a);
     else
-      PW_DISPATCH(P->pw, (k_classsum<double, true, PWV><<<seg_grid(P), 256, 0, s>>>(a)));
+      k_classsum<double, true><<<seg_grid(P), 256, 0, s>>>(a);
     if (fp32)
       k_final_Z32<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->scal, P->sigma, P->ab32);
     else
@@ -1849,45 +1966,47 @@ mdsdp_status launch_bty(mdsdp_problem P, hipStream_t s) {
   return MDSDP_OK;
 }
 
-template <typename T, int MODE, int PW>
+template <typename T, int MODE, int SW>
 static mdsdp_status resid_go(mdsdp_problem P, const KArgs& a, unsigned g, hipStream_t s) {
-  typedef ResidLds<T, MODE, PW> L;
+  typedef ResidLds<T, MODE, SW> L;
   static bool attr_set[64] = {};
   const int dev = P->device & 63;
   if (L::bytes > 65536 && !attr_set[dev]) {
-    MDSDP_HIP(hipFuncSetAttribute((const void*)k_resid<T, MODE, PW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    MDSDP_HIP(hipFuncSetAttribute((const void*)k_resid<T, MODE, SW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)L::bytes));
     attr_set[dev] = true;
   }
-  k_resid<T, MODE, PW><<<dim3(g, L::NSL), 256, L::bytes, s>>>(a);
+  k_resid<T, MODE, SW><<<dim3(g, a.nsl), 256, L::bytes, s>>>(a);
   return MDSDP_OK;
 }
 
 mdsdp_status launch_resid(mdsdp_problem P, int mode, bool fp32, hipStream_t s) {
+  (void)fp32;  // the FP32-tile HVP has its own kernel (launch_hvp32)
   KArgs a = make_args(P);
   const unsigned g = seg_grid(P);
   mdsdp_status st = MDSDP_OK;
   switch (mode) {
     case M_GRAD:
       timer_begin(P, s, "resid_grad");
-      PW_DISPATCH(P->pw, st = (resid_go<double, M_GRAD, PWV>(P, a, g, s)));
+      SW_DISPATCH(P->pw, st = (resid_go<double, M_GRAD, SWV>(P, a, g, s)));
       break;
     case M_MULT:
       timer_begin(P, s, "resid_mult");
-      PW_DISPATCH(P->pw, st = (resid_go<double, M_MULT, PWV>(P, a, g, s)));
+      if (a.nsl > 1) {
+        // sliced update: every slice reads the old Xt, slice 0 writes the new one
+        if (!P->Xt2) MDSDP_HIP(hipMalloc((void**)&P->Xt2, (size_t)P->nslots * sizeof(double)));
+        a.Xt_out = P->Xt2;
+      }
+      SW_DISPATCH(P->pw, st = (resid_go<double, M_MULT, SWV>(P, a, g, s)));
+      if (a.nsl > 1) std::swap(P->Xt, P->Xt2);
       break;
     case M_XMV:
       timer_begin(P, s, "resid_xmv");
-      PW_DISPATCH(P->pw, st = (resid_go<double, M_XMV, PWV>(P, a, g, s)));
+      SW_DISPATCH(P->pw, st = (resid_go<double, M_XMV, SWV>(P, a, g, s)));
       break;
     default:
-      if (fp32) {
-        timer_begin(P, s, "resid_hvp32");
-        PW_DISPATCH(P->pw, st = (resid_go<float, M_HVP, PWV>(P, a, g, s)));
-      } else {
-        timer_begin(P, s, "resid_hvp64");
-        PW_DISPATCH(P->pw, st = (resid_go<double, M_HVP, PWV>(P, a, g, s)));
-      }
+      timer_begin(P, s, "resid_hvp64");
+      SW_DISPATCH(P->pw, st = (resid_go<double, M_HVP, SWV>(P, a, g, s)));
   }
   timer_end(P, s);
   if (st != MDSDP_OK) return st;
@@ -1958,19 +2077,18 @@ static RowArgs row_args(mdsdp_problem P, int p) {
   return ra;
 }
 
-mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* U, hipStream_t s) {
-  const int nblk = std::min(32, (P->n + 63) / 64);
-  timer_begin(P, s, "gram");
+mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* U, hipStream_t s,
+                         bool with_yy) {
   // the Gram width follows p itself (not the last staged width)
   const int gpw = pw_of(p);
+  const int nblk = std::min(gram_blocks(gpw), (P->n + 63) / 64);
+  timer_begin(P, s, "gram");
   P->gram_pw = gpw;
-  const int len = 2 * gpw * gpw;
-  int nparts = nblk;
-  PW_DISPATCH(gpw, {
-    k_gram_part<PWV><<<dim3(nblk, GramSplit<PWV>::NGRP), 256, 0, s>>>(P->n, p, Y, U, P->gpart + GP_GRAM);
-    nparts = nblk * GramSplit<PWV>::RS;
-  });
-  k_gram_final<<<(len + 3) / 4, 256, 0, s>>>(nparts, len, P->gpart + GP_GRAM, P->gram, gpw);
+  const GramSplit GS(gpw);
+  const int len = 2 * gpw * gpw, e0 = with_yy ? 0 : gpw * gpw;
+  const int nparts = nblk * GS.RS;
+  k_gram_part<<<dim3(nblk, GS.NGRP), 256, 0, s>>>(P->n, p, gpw, with_yy ? 1 : 0, Y, U, P->gpart + GP_GRAM);
+  k_gram_final<<<(len - e0 + 3) / 4, 256, 0, s>>>(nparts, len, e0, P->gpart + GP_GRAM, P->gram, gpw);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -1980,7 +2098,16 @@ mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, doubl
                                   double* f, hipStream_t s) {
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_grad");
-  k_row_grad<<<blocks_for((long long)P->n * 64, 256), 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
+  const unsigned nblk = blocks_for((long long)P->n * 64, 256);  // L * SPL = 64 lanes per row
+  const int rm = P->pw <= 64 ? 1 : P->pw / 64;
+  if (rm <= 1)
+    k_row_grad<1><<<nblk, 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
+  else if (rm <= 2)
+    k_row_grad<2><<<nblk, 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
+  else if (rm <= 4)
+    k_row_grad<4><<<nblk, 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
+  else
+    k_row_grad<8><<<nblk, 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
   k_scalars<<<1, 256, 0, s>>>(M_GRAD, P->wgpart, P->nseg, nullptr, 0, P->gpart + GP_BTY, 64, P->sigma, P->scal, f,
                               nullptr);
   timer_end(P, s);
@@ -1993,10 +2120,34 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_hvp");
   const unsigned nblk = blocks_for((long long)P->n * 64, 256);  // L * SPL = 64 lanes per row
-  if (fp32)
-    k_row_hvp<float><<<nblk, 256, 0, s>>>(ra, Y, U, P->gram, P->zvec, P->sigma, riem, HU);
-  else
-    k_row_hvp<double><<<nblk, 256, 0, s>>>(ra, Y, U, P->gram, P->zvec, P->sigma, riem, HU);
+  const double* lr = nullptr;
+  if (p > 64) {
+    const int ntiles = ((P->n + 15) / 16) * ((p + 15) / 16);
+    k_lowrank<<<(ntiles + 3) / 4, 256, 0, s>>>(P->n, p, P->gram_pw, Y, U, P->gram, P->lrbuf);
+    lr = P->lrbuf;
+  }
+  const int rm = P->pw <= 64 ? 1 : P->pw / 64;
+#define ROW_HVP(TT, RMV) k_row_hvp<TT, RMV><<<nblk, 256, 0, s>>>(ra, Y, U, P->gram, lr, P->zvec, P->sigma, riem, HU)
+  if (fp32) {
+    if (rm <= 1)
+      ROW_HVP(float, 1);
+    else if (rm <= 2)
+      ROW_HVP(float, 2);
+    else if (rm <= 4)
+      ROW_HVP(float, 4);
+    else
+      ROW_HVP(float, 8);
+  } else {
+    if (rm <= 1)
+      ROW_HVP(double, 1);
+    else if (rm <= 2)
+      ROW_HVP(double, 2);
+    else if (rm <= 4)
+      ROW_HVP(double, 4);
+    else
+      ROW_HVP(double, 8);
+  }
+#undef ROW_HVP
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -2070,10 +2221,25 @@ mdsdp_status vec_lincomb(long long len, double alpha, const double* x, double be
 mdsdp_status launch_tcg_update(int n, int p, const double* Y, double alpha, double rr_old, double* eta,
                                double* Heta, double* r, double* d, const double* Hd, double* part,
                                double* rr_beta_dev, hipStream_t s) {
-  const unsigned nb = blocks_for(n, 256);
-  k_tcg_update1<<<nb, 256, 0, s>>>(n, p, Y, alpha, eta, Heta, r, d, Hd, part);
-  k_rr_beta<<<1, 256, 0, s>>>((int)nb, part, rr_old, rr_beta_dev);
-  k_tcg_update2<<<nb, 256, 0, s>>>(n, p, Y, rr_beta_dev + 1, r, d);
+  int L = 1;
+  while (L < p && L < 64) L <<= 1;
+  const int rm = (p + L - 1) / L;
+  const unsigned nb = blocks_for((long long)n * L, 256);
+#define TCG_GO(RMV)                                                                                       \
+  do {                                                                                                    \
+    k_tcg_update1<RMV><<<nb, 256, 0, s>>>(n, p, L, Y, alpha, eta, Heta, r, d, Hd, part);                  \
+    k_rr_beta<<<1, 256, 0, s>>>((int)nb, part, rr_old, rr_beta_dev);                                      \
+    k_tcg_update2<RMV><<<nb, 256, 0, s>>>(n, p, L, Y, rr_beta_dev + 1, r, d);                             \
+  } while (0)
+  if (rm <= 1)
+    TCG_GO(1);
+  else if (rm <= 2)
+    TCG_GO(2);
+  else if (rm <= 4)
+    TCG_GO(4);
+  else
+    TCG_GO(8);
+#undef TCG_GO
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }

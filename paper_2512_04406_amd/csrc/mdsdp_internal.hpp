@@ -29,7 +29,7 @@ namespace mdsdp {
 
 constexpr int TS = 64;          // tile side
 constexpr int SB = 16;          // MFMA sub-block side
-constexpr int PMAX = 128;       // largest factor width (p <= 128)
+constexpr int PMAX = 512;       // largest factor width (p <= 512)
 constexpr int GRAM_U = PMAX * PMAX;  // offset of Y^T U in the Gram buffer
 constexpr int HBUF_LEN = 64 + PMAX * PMAX;  // pinned read-back buffer (doubles)
 constexpr int TSLOTS = TS * TS;  // slots per tile
@@ -38,10 +38,14 @@ constexpr int STAR_LG = 32;     // residue classes of l in the degree-2 BQP cont
 constexpr uint32_t CLS_MASK = 0x3FFFFFFFu;
 constexpr uint32_t OWNER_BIT = 0x40000000u;
 
-// carve of the `gpart` scratch (doubles): Gram partials (<= 32 blocks of
-// 2 x 128 x 128), b^T y partials, degree-0 BQP partials, host-built p x p matrix
+// Gram partials: gram_blocks(pw) row blocks, each 2 pw^2 doubles (at most
+// 4 blocks of 2 x 512 x 512, 2 x 32 x 64 x 64 or 32 x 4 x 2 x 16 x 16)
+inline int gram_blocks(int pw) { return pw <= 64 ? 32 : (pw <= 128 ? 16 : (pw <= 256 ? 8 : 4)); }
+constexpr size_t GRAM_PART_MAX = 4 * 2 * (size_t)PMAX * PMAX;
+// carve of the `gpart` scratch (doubles): Gram partials, b^T y partials,
+// degree-0 BQP partials, host-built p x p matrix
 constexpr size_t GP_GRAM = 0;
-constexpr size_t GP_BTY = 32 * 2 * PMAX * PMAX;
+constexpr size_t GP_BTY = GRAM_PART_MAX;
 constexpr size_t GP_BQP0 = GP_BTY + 64;
 constexpr size_t GP_M = GP_BQP0 + 4096;
 constexpr size_t GP_SIZE = GP_M + PMAX * PMAX;
@@ -81,6 +85,7 @@ struct mdsdp_problem_s {
   // device arrays
   uint32_t* cls = nullptr;      // nslots class words
   double* Xt = nullptr;         // nslots
+  double* Xt2 = nullptr;        // nslots, second multiplier buffer of the sliced update (allocated on first use)
   float* Xt32 = nullptr;        // nslots (FP32 shadow, refreshed on every Xt write)
   double* Ct = nullptr;         // nslots or null
   mdsdp::Seg* segs = nullptr;   // nseg
@@ -117,6 +122,9 @@ struct mdsdp_problem_s {
   int last_p = 0;
   int pw = 16;         // staged factor width for last_p: 16, 32 or 64
   int gram_pw = 16;    // row pitch of the last Gram matrices written to `gram`
+  bool gram_yy_valid = false;  // `gram` holds Y^T Y of the current Y (set by the HVP, cleared by S-passes)
+  int gram_yy_p = 0;           // factor width of that Y^T Y
+  double* lrbuf = nullptr;     // n x PMAX: low-rank part of the HVP for p > 64
   // solver / Lanczos workspace
   double* dotpart = nullptr;
   const double** dotptr = nullptr;  // unused (kept for layout stability)
@@ -170,7 +178,7 @@ mdsdp_status launch_bty(mdsdp_problem P, hipStream_t s);
 mdsdp_status launch_resid(mdsdp_problem P, int mode, bool fp32, hipStream_t s);
 mdsdp_status launch_hvp32(mdsdp_problem P, hipStream_t s);
 mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* U,
-                         hipStream_t s);
+                         hipStream_t s, bool with_yy = true);
 mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, double* egrad,
                                   double* rgrad, double* f, hipStream_t s);
 mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double* Y,

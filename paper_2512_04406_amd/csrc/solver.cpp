@@ -48,42 +48,97 @@ double secs(clk::time_point a, clk::time_point b) { return std::chrono::duration
 
 // ---- small host linear algebra ------------------------------------------------
 
-// cyclic Jacobi for a symmetric k x k matrix (k <= 128): A is overwritten,
-// eigenvalues in w, eigenvectors in the columns of V (row-major)
-void jacobi_eig(int k, double* A, double* w, double* V) {
+// Symmetric eigen-decomposition of a k x k row-major matrix A in O(k^3):
+// Householder reduction to tridiagonal form T = Q^T A Q, then the implicit-
+// shift QL iteration on T with the rotations accumulated into Q.  On return
+// w holds the eigenvalues and the columns of V (row-major k x k) the
+// eigenvectors; A is overwritten.
+void sym_eig(int k, double* A, double* w, double* V) {
+  std::vector<double> e(k, 0.0), v(k), pv(k), qv(k);
   for (int i = 0; i < k; ++i)
     for (int j = 0; j < k; ++j) V[i * k + j] = (i == j) ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0;
-    for (int i = 0; i < k; ++i)
-      for (int j = i + 1; j < k; ++j) off += A[i * k + j] * A[i * k + j];
-    if (off < 1e-30) break;
-    for (int pp = 0; pp < k; ++pp)
-      for (int q = pp + 1; q < k; ++q) {
-        const double apq = A[pp * k + q];
-        if (fabs(apq) < 1e-300) continue;
-        const double app = A[pp * k + pp], aqq = A[q * k + q];
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int r = 0; r < k; ++r) {
-          const double arp = A[r * k + pp], arq = A[r * k + q];
-          A[r * k + pp] = c * arp - s * arq;
-          A[r * k + q] = s * arp + c * arq;
-        }
-        for (int r = 0; r < k; ++r) {
-          const double apr = A[pp * k + r], aqr = A[q * k + r];
-          A[pp * k + r] = c * apr - s * aqr;
-          A[q * k + r] = s * apr + c * aqr;
-        }
-        for (int r = 0; r < k; ++r) {
-          const double vrp = V[r * k + pp], vrq = V[r * k + q];
-          V[r * k + pp] = c * vrp - s * vrq;
-          V[r * k + q] = s * vrp + c * vrq;
-        }
-      }
+  // Householder steps: zero column i below the subdiagonal
+  for (int i = 0; i + 2 < k; ++i) {
+    const int m = k - i - 1;  // length of x = A[i+1 .., i]
+    double nx = 0.0;
+    for (int r = 0; r < m; ++r) nx += A[(i + 1 + r) * k + i] * A[(i + 1 + r) * k + i];
+    nx = sqrt(nx);
+    if (nx == 0.0) continue;
+    const double x0 = A[(i + 1) * k + i];
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    for (int r = 0; r < m; ++r) v[r] = A[(i + 1 + r) * k + i];
+    v[0] -= alpha;
+    double nv = 0.0;
+    for (int r = 0; r < m; ++r) nv += v[r] * v[r];
+    nv = sqrt(nv);
+    if (nv == 0.0) continue;
+    for (int r = 0; r < m; ++r) v[r] /= nv;
+    // trailing block B -> B - 2 (v w^T + w v^T), w = B v - (v^T B v) v
+    for (int r = 0; r < m; ++r) {
+      double acc = 0.0;
+      for (int c = 0; c < m; ++c) acc += A[(i + 1 + r) * k + (i + 1 + c)] * v[c];
+      pv[r] = acc;
+    }
+    double K = 0.0;
+    for (int r = 0; r < m; ++r) K += v[r] * pv[r];
+    for (int r = 0; r < m; ++r) qv[r] = pv[r] - K * v[r];
+    for (int r = 0; r < m; ++r)
+      for (int c = 0; c < m; ++c) A[(i + 1 + r) * k + (i + 1 + c)] -= 2.0 * (v[r] * qv[c] + qv[r] * v[c]);
+    A[(i + 1) * k + i] = A[i * k + i + 1] = alpha;
+    for (int r = 1; r < m; ++r) A[(i + 1 + r) * k + i] = A[i * k + i + 1 + r] = 0.0;
+    // Q <- Q H on columns i+1 ..
+    for (int r = 0; r < k; ++r) {
+      double acc = 0.0;
+      for (int c = 0; c < m; ++c) acc += V[r * k + i + 1 + c] * v[c];
+      for (int c = 0; c < m; ++c) V[r * k + i + 1 + c] -= 2.0 * acc * v[c];
+    }
   }
   for (int i = 0; i < k; ++i) w[i] = A[i * k + i];
+  for (int i = 0; i + 1 < k; ++i) e[i] = A[(i + 1) * k + i];
+  // implicit-shift QL on (w, e); e[i] couples i and i + 1
+  for (int l = 0; l < k; ++l) {
+    for (int iter = 0; iter < 60; ++iter) {
+      int m = l;
+      for (; m + 1 < k; ++m) {
+        const double dd = fabs(w[m]) + fabs(w[m + 1]);
+        if (fabs(e[m]) <= 1e-15 * dd) break;
+      }
+      if (m == l) break;
+      double g = (w[l + 1] - w[l]) / (2.0 * e[l]);
+      double r = hypot(g, 1.0);
+      g = w[m] - w[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = m - 1;
+      bool early = false;
+      for (; i >= l; --i) {
+        const double f = s * e[i], b = c * e[i];
+        r = hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          w[i + 1] -= p;
+          e[m] = 0.0;
+          early = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = w[i + 1] - p;
+        r = (w[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        w[i + 1] = g + p;
+        g = c * r - b;
+        for (int row = 0; row < k; ++row) {
+          const double f2 = V[row * k + i + 1];
+          V[row * k + i + 1] = s * V[row * k + i] + c * f2;
+          V[row * k + i] = c * V[row * k + i] - s * f2;
+        }
+      }
+      if (early) continue;
+      w[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
 }
 
 // number of eigenvalues of the symmetric tridiagonal (a, b) below x (Sturm)
@@ -213,7 +268,8 @@ struct Work {
   mdsdp_status init(int n_) {
     n = n_;
     const size_t vec = (size_t)n * PMAX;
-    hipError_t e = hipMalloc((void**)&buf, (10 * vec + 4096) * sizeof(double));
+    const size_t npart = (size_t)n / 4 + 64;  // tCG partials: one per 256 threads of 64-lane rows
+    hipError_t e = hipMalloc((void**)&buf, (10 * vec + npart + 96) * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(solver work)");
     double* p = buf;
     Ynew = p; p += vec;
@@ -226,7 +282,7 @@ struct Work {
     Hd = p; p += vec;
     U = p; p += vec;
     tmp = p; p += vec;
-    part = p; p += 4000;
+    part = p; p += npart;
     rrb = p;
     return MDSDP_OK;
   }
@@ -517,7 +573,7 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->gamma = 2.0;
   o->kappa1 = 0.1;
   o->kappa2 = 10.0;
-  o->p_max = 128;
+  o->p_max = PMAX;
   o->n_neg = 4;
   o->tau_rank = 1e-4;
   o->gtol0 = 1e-2;
@@ -567,7 +623,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     return MDSDP_EINVAL;
   }
   if (opt->p_max < 1 || opt->p_max > PMAX || p0 < 1 || p0 > opt->p_max) {
-    set_error("need 1 <= p0 <= p_max <= 128");
+    set_error("need 1 <= p0 <= p_max <= " + std::to_string(PMAX));
     return MDSDP_EINVAL;
   }
   if (!(opt->gtol_decay > 0.0 && opt->gtol_decay <= 1.0)) {
@@ -575,7 +631,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     return MDSDP_EINVAL;
   }
   if (opt->n_neg < 0 || opt->n_neg > PMAX) {
-    set_error("need 0 <= n_neg <= 128");
+    set_error("need 0 <= n_neg <= " + std::to_string(PMAX));
     return MDSDP_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -688,12 +744,13 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     }
     // rank update: SVD of Y through its Gram matrix (p x p)
     CHK(launch_gram(P, p, Y, Y, s));
+    P->gram_yy_valid = false;  // Y changes below
     const int pw = P->gram_pw;
     std::vector<double> G((size_t)pw * pw), A((size_t)p * p), wv(p), Vv((size_t)p * p);
     CHK(read_dev(P, P->gram, pw * pw, G.data(), s));
     for (int i = 0; i < p; ++i)
       for (int j = 0; j < p; ++j) A[i * p + j] = G[(size_t)i * pw + j];
-    jacobi_eig(p, A.data(), wv.data(), Vv.data());
+    sym_eig(p, A.data(), wv.data(), Vv.data());
     std::vector<int> idx(p);
     for (int i = 0; i < p; ++i) idx[i] = i;
     std::sort(idx.begin(), idx.end(), [&](int x, int y) { return wv[x] > wv[y]; });

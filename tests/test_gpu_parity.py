@@ -238,3 +238,52 @@ def test_width_switching_on_one_problem():
         assert _rel(rg.cpu().numpy(), sub.rgrad(Y)) <= 1e-10
         assert _rel(h64.cpu().numpy(), sub.rhess(Y, U)) <= 1e-10
         assert _rel(h32.cpu().numpy(), sub.rhess(Y, U)) <= 1e-4
+
+
+@pytest.mark.parametrize("q,p,structured", [(12, 200, True), (20, 256, False), (30, 300, True), (12, 512, True),
+                                            (8, 130, False)])
+def test_wide_factors(q, p, structured):
+    """Factor widths above 64 (64-column slices, S tiles accumulated over
+    64-column chunks, the sliced multiplier update into a second buffer, the
+    MFMA low-rank term and the width-templated row finalisers), including
+    p > n: every output against the oracle."""
+    from paper_2512_04406_amd.problem import FP32, FP64
+
+    rel, sub, prob, Xt, Y, U, sigma = _case(q, p, structured=structured)
+    Yt, Ut = _t(Y), _t(U)
+    f, eg, rg = prob.cost_grad(Yt)
+    h64 = prob.hvp(Yt, Ut, FP64)
+    e64 = prob.hvp(Yt, Ut, FP64, riemannian=False)
+    h32 = prob.hvp(Yt, Ut, FP32)
+    h64b = prob.hvp(Yt, Ut, FP64)  # Y^T Y reused from the first HVP at this point
+    torch.cuda.synchronize()
+    f_ref = sub.cost(Y)
+    assert abs(f.item() - f_ref) <= 1e-10 * (1 + abs(f_ref))
+    assert _rel(eg.cpu().numpy(), sub.egrad(Y)) <= 1e-10
+    assert _rel(rg.cpu().numpy(), sub.rgrad(Y)) <= 1e-10
+    rh = sub.rhess(Y, U)
+    assert _rel(h64.cpu().numpy(), rh) <= 1e-10
+    assert _rel(e64.cpu().numpy(), sub.ehess(Y, U)) <= 1e-10
+    assert _rel(h32.cpu().numpy(), rh) <= 1e-4
+    assert torch.equal(h64, h64b)
+    # multiplier update and certificate matvec at this width
+    y, z, kkt = prob.update_multiplier(Yt)
+    torch.cuda.synchronize()
+    S = Y @ Y.T
+    y_ref = class_average(S, rel.cls, rel.counts)
+    R = Q_op(S, rel.cls, rel.counts)
+    Xt1 = Xt + sigma * R
+    D = D_matrix(rel.b, rel.cls, rel.counts)
+    z_ref = np.einsum("ij,ij->i", (Xt1 + D) @ Y, Y)
+    assert np.max(np.abs(y.cpu().numpy() - y_ref)) <= 1e-12
+    assert _rel(z.cpu().numpy(), z_ref) <= 1e-10
+    assert abs(kkt.cpu().numpy()[0] - np.linalg.norm(R)) <= 1e-10 * (1 + np.linalg.norm(R))
+    iu = np.triu_indices(rel.n)
+    assert _rel(prob.export_multiplier_packed(), Xt1[iu]) <= 1e-13
+    X = Xt1 + D - np.diag(z_ref)
+    V = gaussian(rel.n, 70, 77)
+    XV = prob.certificate_matvec(_t(V)).cpu().numpy()
+    assert _rel(XV, X @ V) <= 1e-10
+    # a second update (the sliced update alternates multiplier buffers)
+    prob.update_multiplier(Yt)
+    assert _rel(prob.export_multiplier_packed(), (Xt1 + sigma * R)[iu]) <= 1e-13
