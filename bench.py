@@ -34,11 +34,41 @@ HBM_PEAK_GBS = 8000.0
 
 
 def _alg_bytes_hvp_resid(ne: int, m: int, fp32: bool) -> float:
-    """Algorithmic HBM bytes of one HVP residual/product pass: the class id
-    (4 B) and the multiplier (8 B FP64 or 4 B FP32 shadow) of every packed
-    entry, plus the {D, y} pair and the HVP class average of every class
-    (3 x 8 B), each read once."""
-    return ne * (4 + (4 if fp32 else 8)) + 24.0 * m
+    """Algorithmic HBM bytes of one HVP product pass, each read once: per
+    packed entry the class word (4 B) and the multiplier (4 B FP32 shadow or
+    8 B FP64); per class the FP32 pair {D - sigma y, -sigma y'} (8 B), or in
+    FP64 the pair {D, y} and y' (24 B)."""
+    return ne * (4 + (4 if fp32 else 8)) + (8.0 if fp32 else 24.0) * m
+
+
+def _kernel_sources_sha() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2512_04406_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/<kernel>_traffic.txt: FETCH_SIZE and WRITE_SIZE, copy-
+    calibrated), or None when there is none or the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernels_sha") != _kernel_sources_sha():
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(q: int, p: int, budget_s: float) -> dict:
@@ -89,6 +119,8 @@ def main() -> int:
                     help="cap of each full time-to-KKT solve (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the isolated HVP rates of the q=40 and sparse q=120 instances")
     ap.add_argument("--profile-hvp-only", action="store_true",
                     help="only the isolated HVP loop (for rocprofv3 runs)")
     args = ap.parse_args()
@@ -137,7 +169,8 @@ def main() -> int:
 
     hvp_dt = hvp_rate(hvp_prec)
     hvp64_dt = hvp_rate(FP64) if hvp_prec != FP64 else hvp_dt
-    # per-kernel durations with HIP events on the launch stream
+    # per-kernel durations with HIP events on the launch stream (each kernel
+    # bracketed by its own events: small kernels read a few us long)
     prob.enable_timing(True)
     for _ in range(20):
         prob.hvp(Y, U, hvp_prec, out=HU)
@@ -147,10 +180,14 @@ def main() -> int:
     for name, ms in kt:
         per.setdefault(name, []).append(ms)
     kern_us = {k: 1e3 * float(np.mean(v)) for k, v in per.items()}
-    resid_name = "resid_hvp32" if hvp_prec == FP32 else "resid_hvp64"
-    resid_s = kern_us.get(resid_name, float("nan")) * 1e-6
+    # the dominant kernel: its launches back to back between two HIP events on
+    # the launch stream, after one full HVP at this point
+    resid_name = "k_hvp32<16>" if hvp_prec == FP32 else "k_resid<double,HVP,16>"
+    prob.hvp(Y, U, hvp_prec, out=HU)
+    resid_s = prob.time_product_pass(100) * 1e-6
     alg = _alg_bytes_hvp_resid(ne, m, hvp_prec == FP32)
     achieved = alg / resid_s / 1e9
+    traffic = _measured_traffic("hvp32_q100_p16" if hvp_prec == FP32 else "hvp64_q100_p16")
     print(f"[bench] isolated HVP {hvp_dt * 1e6:.1f} us ({args.prec}), {hvp64_dt * 1e6:.1f} us (fp64)",
           file=sys.stderr, flush=True)
     if args.profile_hvp_only:
@@ -160,9 +197,39 @@ def main() -> int:
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"hvp_us": hvp_dt * 1e6, "kernels_us": kern_us, "copy_bytes_each_way": src.numel() * 8,
-                          "alg_bytes_resid": alg, "ne": ne, "m": m}))
+        print(json.dumps({"hvp_us": hvp_dt * 1e6, "kernels_us": kern_us, "product_pass_us": resid_s * 1e6,
+                          "copy_bytes_each_way": src.numel() * 8, "alg_bytes_resid": alg, "ne": ne, "m": m,
+                          "kernels_sha": _kernel_sources_sha()}))
         return 0
+
+    other = {}
+    if not args.no_other_configs:
+        from synth import sparse_bqp_instance
+
+        for label, (Qo, co, po) in {"dense q=40 p=4": (*bqp_instance(40, args.seed), 4),
+                                    "sparse-Q (5%) q=120 p=16": (*sparse_bqp_instance(120, 0.05, args.seed), 16)
+                                    }.items():
+            po_prob = Problem.bqp(Qo, co, ORDER_COLEX)
+            Yo = torch.from_numpy(gaussian(po_prob.n, po, 21)).to(dev)
+            Yo /= Yo.norm(dim=1, keepdim=True)
+            Uo = torch.from_numpy(gaussian(po_prob.n, po, 22)).to(dev)
+            po_prob.set_multiplier(None, 1.0)
+            po_prob.update_multiplier(Yo)
+            po_prob.cost_grad(Yo)
+            HUo = torch.empty_like(Uo)
+            rates = {}
+            for pname, pr in (("fp32_tiles", FP32), ("fp64", FP64)):
+                for _ in range(5):
+                    po_prob.hvp(Yo, Uo, pr, out=HUo)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(50):
+                    po_prob.hvp(Yo, Uo, pr, out=HUo)
+                torch.cuda.synchronize()
+                rates[pname + "_hvp_per_s"] = 50 / (time.perf_counter() - t0)
+            other[label] = {"n": po_prob.n, "m": po_prob.m, **rates}
+            po_prob.close()
+        print(f"[bench] other configs: {other}", file=sys.stderr, flush=True)
 
     def options(prec, **kw):
         o = prob.default_options()
@@ -229,8 +296,9 @@ def main() -> int:
         "hvp_fp64_isolated_us": hvp64_dt * 1e6,
         "hvp_kernels_us": kern_us,
         "roofline": {"bound": "hbm", "kernel": resid_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alg_bytes_per_launch": alg, "avg_launch_us": resid_s * 1e6},
+        "other_configs": other,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(q, p, args.cpu_budget_s)

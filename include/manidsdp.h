@@ -237,6 +237,13 @@ mdsdp_status mdsdp_export_multiplier_packed(mdsdp_problem prob, double* Xt_host)
 mdsdp_status mdsdp_kernel_times(mdsdp_problem prob, double* ms_out, int32_t cap,
                                 int32_t* count);
 mdsdp_status mdsdp_enable_timing(mdsdp_problem prob, int32_t on);
+/* Average duration (microseconds) of the HVP product pass -- the per-entry
+ * residual/product kernel of the last mdsdp_hvp call, with that call's
+ * precision, factor width and staged inputs -- measured by re-launching it
+ * `reps` times back to back on `stream` between two HIP events.  Synchronous.
+ * The pass only rewrites its own partial sums, so the state is unchanged.
+ * EINVAL if no HVP has been evaluated yet. */
+mdsdp_status mdsdp_time_product_pass(mdsdp_problem prob, int32_t reps, double* us_out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -75,6 +75,7 @@ SIGNATURES = {
     "mdsdp_export_multiplier_packed": (_i32, [_vp, _vp]),
     "mdsdp_kernel_times": (_i32, [_vp, _vp, _i32, _pi32]),
     "mdsdp_enable_timing": (_i32, [_vp, _i32]),
+    "mdsdp_time_product_pass": (_i32, [_vp, _i32, _pf64, _vp]),
 }
 
 _lib = None

@@ -136,6 +136,7 @@ namespace mdsdp {
 
 static void free_problem(mdsdp_problem P) {
   if (!P) return;
+  blas_destroy(P);
   void* ptrs[] = {P->cls,      P->Xt,     P->Xt32,    P->Ct,      P->segs,   P->seg_start, P->cy,
                   P->Cavg,     P->yp,     P->ab32,    P->invc,    P->bvec,    P->sacc,   P->Yp,        P->Up,
                   P->bqp4_items, P->bqpT,     P->bqpStar,
@@ -525,6 +526,7 @@ mdsdp_status mdsdp_hvp(mdsdp_problem P, int32_t p, int32_t prec, const double* Y
   P->gram_yy_p = p;
   if ((st = launch_classsum_Z(P, fp32, s)) != MDSDP_OK) return st;
   if ((st = fp32 ? launch_hvp32(P, s) : launch_resid(P, M_HVP, false, s)) != MDSDP_OK) return st;
+  P->last_hvp_prec = prec;
   return launch_rowfinal_hvp(P, p, fp32, Y, U, HU, riemannian ? 1 : 0, s);
 }
 
@@ -618,6 +620,33 @@ mdsdp_status mdsdp_export_multiplier_packed(mdsdp_problem P, double* out) {
           out[pidx] = h[t * TSLOTS + sb * 256 + e];
         }
     }
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_time_product_pass(mdsdp_problem P, int32_t reps, double* us_out, void* stream) {
+  if (!P || !us_out) return einval("NULL argument");
+  if (reps < 1) return einval("reps must be >= 1");
+  if (P->last_hvp_prec < 0) return einval("call mdsdp_hvp first");
+  hipStream_t s = (hipStream_t)stream;
+  const bool fp32 = P->last_hvp_prec == MDSDP_FP32;
+  const bool was_on = P->timer.on;
+  P->timer.on = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MDSDP_HIP(hipEventCreate(&e0));
+  MDSDP_HIP(hipEventCreate(&e1));
+  mdsdp_status st = MDSDP_OK;
+  (void)hipEventRecord(e0, s);
+  for (int i = 0; i < reps && st == MDSDP_OK; ++i) st = fp32 ? launch_hvp32(P, s) : launch_resid(P, M_HVP, false, s);
+  (void)hipEventRecord(e1, s);
+  hipError_t e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->timer.on = was_on;
+  if (st != MDSDP_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+  *us_out = 1e3 * (double)ms / reps;
   return MDSDP_OK;
 }
 

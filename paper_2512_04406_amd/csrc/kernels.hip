@@ -38,6 +38,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <rocblas/rocblas.h>
+
 #include "mdsdp_internal.hpp"
 
 namespace mdsdp {
@@ -854,39 +856,6 @@ __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __res
   }
 }
 
-// Low-rank part of the HVP for wide factors, as an FP64 MFMA product:
-// LR (n x p) = Y W1 + U W2, W1 = Y^T U + U^T Y, W2 = Y^T Y (row pitch pw in
-// `gram`).  One wave per 16 x 16 output tile, contraction over p in steps of 4.
-__global__ __launch_bounds__(256) void k_lowrank(int n, int p, int pw, const double* __restrict__ Y,
-                                                 const double* __restrict__ U, const double* __restrict__ gram,
-                                                 double* __restrict__ LR) {
-  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  const int ntc = (p + 15) / 16;
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int rt = tile / ntc, ct = tile % ntc;
-  if (rt * 16 >= n) return;
-  const double* YtY = gram;
-  const double* YtU = gram + GRAM_U;
-  const int r = rt * 16 + li, c = ct * 16 + li;
-  const bool rok = r < n, cok = c < p;
-  v4d acc = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < p; k0 += 4) {
-    const int k = k0 + lk;
-    const bool kok = k < p;
-    const double ya = (rok && kok) ? Y[(size_t)r * p + k] : 0.0;
-    const double ua = (rok && kok) ? U[(size_t)r * p + k] : 0.0;
-    const double w1 = (cok && kok) ? YtU[k * pw + c] + YtU[c * pw + k] : 0.0;
-    const double w2 = (cok && kok) ? YtY[k * pw + c] : 0.0;
-    acc = mfma(ya, w1, acc);
-    acc = mfma(ua, w2, acc);
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int rr = rt * 16 + drow<double>(lk, v);
-    if (rr < n && cok) LR[(size_t)rr * p + c] = acc[v];
-  }
-}
-
 __global__ __launch_bounds__(256) void k_row_mult(RowArgs ra, const double* __restrict__ Y,
                                                   double* __restrict__ zmult, double* __restrict__ zout,
                                                   double* __restrict__ zpart) {
@@ -1050,17 +1019,26 @@ __global__ __launch_bounds__(256) void k_gram_part(int n, int p, int pw, int wit
 }
 
 __global__ __launch_bounds__(256) void k_gram_final(int nblk, int len, int e0, const double* __restrict__ part,
-                                                    double* __restrict__ gram, int pw) {
+                                                    double* __restrict__ gram, int pw, int per_thread) {
   // part: nblk x (2 pw^2); gram: Y^T Y at [0, pw^2), Y^T U at [GRAM_U, GRAM_U + pw^2).
-  // Elements e0 .. len - 1; one wave per element: lanes take every 64th
-  // partial, then a butterfly.
+  // Elements e0 .. len - 1.  per_thread = 0: one wave per element, lanes take
+  // every 64th partial, then a butterfly; 1: one thread per element, partials
+  // added in order.
+  const int pw2 = pw * pw;
+  if (per_thread) {
+    const int e = e0 + blockIdx.x * 256 + threadIdx.x;
+    if (e >= len) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * len + e];
+    gram[e < pw2 ? e : GRAM_U + (e - pw2)] = s;
+    return;
+  }
   const int e = e0 + blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (e >= len) return;
   double s = 0.0;
   for (int b = lane; b < nblk; b += 64) s += part[(size_t)b * len + e];
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-  const int pw2 = pw * pw;
   if (lane == 0) gram[e < pw2 ? e : GRAM_U + (e - pw2)] = s;
 }
 
@@ -2077,10 +2055,90 @@ static RowArgs row_args(mdsdp_problem P, int p) {
   return ra;
 }
 
+// rocBLAS handle of the problem on stream s (created on first use); the plain
+// FP64 GEMMs of wide factors (Gram matrices, low-rank HVP term) go through it,
+// with atomics off so that the results are reproducible.
+static mdsdp_status blas_on(mdsdp_problem P, hipStream_t s, rocblas_handle* h) {
+  if (!P->blas) {
+    rocblas_handle nh = nullptr;
+    if (rocblas_create_handle(&nh) != rocblas_status_success) {
+      set_error("rocblas_create_handle failed");
+      return MDSDP_EHIP;
+    }
+    (void)rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed);
+    P->blas = (void*)nh;
+  }
+  *h = (rocblas_handle)P->blas;
+  if (rocblas_set_stream(*h, s) != rocblas_status_success) {
+    set_error("rocblas_set_stream failed");
+    return MDSDP_EHIP;
+  }
+  return MDSDP_OK;
+}
+
+void blas_destroy(mdsdp_problem P) {
+  if (P->blas) (void)rocblas_destroy_handle((rocblas_handle)P->blas);
+  P->blas = nullptr;
+}
+
+#define BLAS_CHK(x)                              \
+  do {                                           \
+    if ((x) != rocblas_status_success) {         \
+      set_error(std::string("rocBLAS: ") + #x);  \
+      return MDSDP_EHIP;                         \
+    }                                            \
+  } while (0)
+
+// Row-major n x p factors are column-major p x n matrices with leading
+// dimension p.  C = A^T B (p x p, row-major with pitch pw) is, in column-major
+// terms, C^T = B^c (A^c)^T: dgemm(N, T, p, p, n, B, A).  The sum over the n
+// rows is split into nch chunks (one strided-batched call, each chunk's
+// product into its own partial of the Gram partial layout, offset `half`),
+// then added in a fixed order by k_gram_final.
+static mdsdp_status gram_blas(mdsdp_problem P, int p, int pw, int& nch, const double* A, const double* B,
+                              size_t half, hipStream_t s) {
+  rocblas_handle h;
+  mdsdp_status st = blas_on(P, s, &h);
+  if (st != MDSDP_OK) return st;
+  const double one = 1.0, zero = 0.0;
+  const int n = P->n;
+  int rows = (n + nch - 1) / nch;
+  if (n - (nch - 1) * rows < 1) {  // (not reached for nch <= ceil(n / 64))
+    nch = 1;
+    rows = n;
+  }
+  const int last = n - (nch - 1) * rows;
+  double* part = P->gpart + GP_GRAM + half;
+  const rocblas_stride sp = (rocblas_stride)2 * pw * pw, sy = (rocblas_stride)rows * p;
+  if (nch > 1)
+    BLAS_CHK(rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, p, p, rows, &one,
+                                           B, p, sy, A, p, sy, &zero, part, pw, sp, nch - 1));
+  BLAS_CHK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, p, p, last, &one,
+                         B + (size_t)(nch - 1) * rows * p, p, A + (size_t)(nch - 1) * rows * p, p, &zero,
+                         part + (size_t)(nch - 1) * sp, pw));
+  return MDSDP_OK;
+}
+
 mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* U, hipStream_t s,
                          bool with_yy) {
   // the Gram width follows p itself (not the last staged width)
   const int gpw = pw_of(p);
+  if (gpw > 64) {
+    timer_begin(P, s, "gram");
+    P->gram_pw = gpw;
+    const size_t pw2 = (size_t)gpw * gpw;
+    int nch = (int)std::max<size_t>(1, std::min<size_t>({64, GRAM_PART_MAX / (2 * pw2),
+                                                               (size_t)(P->n + 63) / 64}));
+    mdsdp_status st = MDSDP_OK;
+    if (with_yy) st = gram_blas(P, p, gpw, nch, Y, Y, 0, s);
+    if (st == MDSDP_OK) st = gram_blas(P, p, gpw, nch, Y, U, pw2, s);
+    if (st != MDSDP_OK) return st;
+    const int len = (int)(2 * pw2), e0 = with_yy ? 0 : (int)pw2;
+    k_gram_final<<<blocks_for(len - e0, 256), 256, 0, s>>>(nch, len, e0, P->gpart + GP_GRAM, P->gram, gpw, 1);
+    timer_end(P, s);
+    MDSDP_HIP(hipGetLastError());
+    return MDSDP_OK;
+  }
   const int nblk = std::min(gram_blocks(gpw), (P->n + 63) / 64);
   timer_begin(P, s, "gram");
   P->gram_pw = gpw;
@@ -2088,7 +2146,7 @@ mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* 
   const int len = 2 * gpw * gpw, e0 = with_yy ? 0 : gpw * gpw;
   const int nparts = nblk * GS.RS;
   k_gram_part<<<dim3(nblk, GS.NGRP), 256, 0, s>>>(P->n, p, gpw, with_yy ? 1 : 0, Y, U, P->gpart + GP_GRAM);
-  k_gram_final<<<(len - e0 + 3) / 4, 256, 0, s>>>(nparts, len, e0, P->gpart + GP_GRAM, P->gram, gpw);
+  k_gram_final<<<(len - e0 + 3) / 4, 256, 0, s>>>(nparts, len, e0, P->gpart + GP_GRAM, P->gram, gpw, 0);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -2122,8 +2180,20 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
   const unsigned nblk = blocks_for((long long)P->n * 64, 256);  // L * SPL = 64 lanes per row
   const double* lr = nullptr;
   if (p > 64) {
-    const int ntiles = ((P->n + 15) / 16) * ((p + 15) / 16);
-    k_lowrank<<<(ntiles + 3) / 4, 256, 0, s>>>(P->n, p, P->gram_pw, Y, U, P->gram, P->lrbuf);
+    // LR = Y (Y^T U + U^T Y) + U (Y^T Y); column-major: LR^c = M^T Y^c + M Y^c
+    // + (Y^T Y) U^c with M^c = the stored Y^T U (pitch gram_pw)
+    rocblas_handle h;
+    mdsdp_status st = blas_on(P, s, &h);
+    if (st != MDSDP_OK) return st;
+    const double one = 1.0, zero = 0.0;
+    const int gp = P->gram_pw, n = P->n;
+    const double* M = P->gram + GRAM_U;
+    BLAS_CHK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, p, n, p, &one, M, gp, Y, p, &zero,
+                           P->lrbuf, p));
+    BLAS_CHK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, p, n, p, &one, M, gp, Y, p, &one,
+                           P->lrbuf, p));
+    BLAS_CHK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, p, n, p, &one, P->gram, gp, U, p, &one,
+                           P->lrbuf, p));
     lr = P->lrbuf;
   }
   const int rm = P->pw <= 64 ? 1 : P->pw / 64;

@@ -124,7 +124,9 @@ struct mdsdp_problem_s {
   int gram_pw = 16;    // row pitch of the last Gram matrices written to `gram`
   bool gram_yy_valid = false;  // `gram` holds Y^T Y of the current Y (set by the HVP, cleared by S-passes)
   int gram_yy_p = 0;           // factor width of that Y^T Y
+  int last_hvp_prec = -1;      // tile precision of the last mdsdp_hvp call
   double* lrbuf = nullptr;     // n x PMAX: low-rank part of the HVP for p > 64
+  void* blas = nullptr;        // rocBLAS handle (wide-factor GEMMs), created on first use
   // solver / Lanczos workspace
   double* dotpart = nullptr;
   const double** dotptr = nullptr;  // unused (kept for layout stability)
@@ -187,6 +189,7 @@ mdsdp_status launch_rowfinal_mult(mdsdp_problem P, int p, const double* Y, doubl
                                   double* kkt, hipStream_t s);
 mdsdp_status launch_rowfinal_xmv(mdsdp_problem P, int k, const double* V, double* XV,
                                  hipStream_t s);
+void blas_destroy(mdsdp_problem P);
 mdsdp_status launch_retract(int n, int p, const double* Y, const double* V, double t,
                             double* Yout, hipStream_t s);
 mdsdp_status launch_project(int n, int p, const double* Y, const double* U, double* out,

@@ -574,7 +574,7 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->kappa1 = 0.1;
   o->kappa2 = 10.0;
   o->p_max = PMAX;
-  o->n_neg = 4;
+  o->n_neg = 16;
   o->tau_rank = 1e-4;
   o->gtol0 = 1e-2;
   o->gtol_min = 1e-10;

@@ -239,6 +239,14 @@ class Problem:
         call("mdsdp_export_multiplier_packed", self._h, _ptr(out))
         return out
 
+    def time_product_pass(self, reps: int = 50) -> float:
+        """Average duration in microseconds of the HVP product pass of the last
+        hvp() call, re-launched `reps` times between two HIP events on the
+        current stream."""
+        us = C.c_double()
+        call("mdsdp_time_product_pass", self._h, int(reps), C.byref(us), _stream())
+        return us.value
+
     def enable_timing(self, on: bool = True) -> None:
         call("mdsdp_enable_timing", self._h, 1 if on else 0)
 

@@ -1,4 +1,5 @@
-"""Parity at the full headline size: dense BQP q = 100 (n = 5051, m = 4,087,976).
+"""Parity at full size: dense BQP q = 100 (n = 5051, m = 4,087,976), the
+headline size, and sparse-Q BQP q = 120 (n = 7261, m = 8,502,671).
 
 The dense FP64 oracle handles this size in seconds (n x n arrays of 204 MB),
 so every output is compared element by element, not sampled.  The launch
@@ -113,4 +114,41 @@ def test_fullsize_class_average_and_multiplier_update(big):
     assert abs(k[2] - z_ref.sum()) <= 1e-10 * (1 + np.abs(z_ref).sum())
     iu = np.triu_indices(rel.n)
     assert _rel(prob.export_multiplier_packed(), Xt1[iu]) <= 1e-13
+    prob.close()
+
+
+def test_sparse_q120_fullsize():
+    """Sparse-Q BQP, q = 120 (n = 7261, m = 8,502,671; 5% of the off-diagonal
+    positions of Q nonzero): the same relaxation with a sparse b, at full
+    size, FP64 and FP32-tile HVP, cost and gradient against the oracle."""
+    from paper_2512_04406_amd.problem import FP32, FP64, ORDER_COLEX, Problem
+    from synth import sparse_bqp_instance
+
+    q, p = 120, 16
+    Q, c = sparse_bqp_instance(q, 0.05, 0)
+    rel = bqp.build_relaxation(Q, c, "colex")
+    print(f"[fullsize] sparse q={q} n={rel.n} m={rel.m} nnz(Q)={np.count_nonzero(Q)}", flush=True)
+    assert rel.n == 7261 and rel.m == 8502671
+    W = gaussian(rel.n, rel.n, 1200)
+    Xt = Q_op(0.05 * (W + W.T), rel.cls, rel.counts)
+    del W
+    Y = gaussian(rel.n, p, 1201)
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    U = proj_tangent(Y, gaussian(rel.n, p, 1202))
+    sub = Subproblem(rel.cls, rel.counts, rel.b, Xt, SIGMA)
+    prob = Problem.bqp(Q, c, ORDER_COLEX)
+    prob.set_multiplier(_t(Xt), SIGMA)
+    Yt, Ut = _t(Y), _t(U)
+    f, eg, rg = prob.cost_grad(Yt)
+    h64 = prob.hvp(Yt, Ut, FP64)
+    h32 = prob.hvp(Yt, Ut, FP32)
+    torch.cuda.synchronize()
+    f_ref = sub.cost(Y)
+    assert abs(f.item() - f_ref) <= 1e-10 * (1 + abs(f_ref))
+    assert _rel(rg.cpu().numpy(), sub.rgrad(Y)) <= 1e-10
+    rh = sub.rhess(Y, U)
+    assert _rel(h64.cpu().numpy(), rh) <= 1e-10
+    err32 = _rel(h32.cpu().numpy(), rh)
+    print(f"   fp32-tile HVP rel err {err32:.2e}", flush=True)
+    assert err32 <= 1e-4
     prob.close()
