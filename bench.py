@@ -12,10 +12,16 @@ the Lanczos certificate eigensolve, the KKT residuals and the rank/sigma
 updates.  `--warmup` outer iterations run first (untimed), then `--steps`
 outer iterations continue the same run (timed).  `value` = HVPs per second
 over the timed steps.  Also reported: the isolated Riemannian HVP throughput
-at a fixed point (FP32 tiles and FP64), the roofline of the dominant kernel
-(HIP events on its launch stream), the time to eta_max <= 1e-8 of a capped
-full solve in mixed precision and in FP64, and the FP64 oracle timed on the
-host CPU on a bounded sample.
+at a fixed point (FP32 tiles and FP64); the roofline of the dominant kernel,
+the HVP product pass (its average launch time from HIP events around 100
+back-to-back launches on its stream; the HBM traffic from the committed
+rocprofv3 counter summary when it matches the current kernel sources); the
+isolated HVP rates of the q = 40 and sparse-Q q = 120 instances; capped full
+solves to eta_max <= 1e-8 in mixed precision and in FP64; and the FP64 oracle
+timed on the host CPU on a bounded sample.
+
+`--kkt-only mixed,fp64 [--q Q --p P0] --kkt-time-limit-s T` runs only the full
+solves (time to KKT) and prints their JSON.
 """
 
 from __future__ import annotations
@@ -36,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 def _alg_bytes_hvp_resid(ne: int, m: int, fp32: bool) -> float:
     """Algorithmic HBM bytes of one HVP product pass, each read once: per
     packed entry the class word (4 B) and the multiplier (4 B FP32 shadow or
-    8 B FP64); per class the FP32 pair {D - sigma y, -sigma y'} (8 B), or in
-    FP64 the pair {D, y} and y' (24 B)."""
-    return ne * (4 + (4 if fp32 else 8)) + (8.0 if fp32 else 24.0) * m
+    8 B FP64); per class the pair {D - sigma y, -sigma y'} (8 B in FP32, 16 B
+    in FP64)."""
+    return ne * (4 + (4 if fp32 else 8)) + (8.0 if fp32 else 16.0) * m
 
 
 def _kernel_sources_sha() -> str:
@@ -119,6 +125,9 @@ def main() -> int:
                     help="cap of each full time-to-KKT solve (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--kkt-only", default="",
+                    help="only the capped time-to-KKT solves: 'mixed', 'fp64' or 'mixed,fp64'")
+    ap.add_argument("--verbose", action="store_true", help="one stderr line per outer iteration of the solves")
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the isolated HVP rates of the q=40 and sparse q=120 instances")
     ap.add_argument("--profile-hvp-only", action="store_true",
@@ -144,6 +153,43 @@ def main() -> int:
     ne = n * (n + 1) // 2
     hvp_prec = FP32 if args.prec == "mixed" else FP64
     print(f"[bench] q={q} n={n} m={m} p={p} prec={args.prec}", file=sys.stderr, flush=True)
+
+    def kkt_solves(which, cap):
+        """Full solves from Y0 (rank p0 = p) to eta_max <= 1e-8, capped at
+        `cap` seconds each, with FP32-tile HVPs (mixed) and FP64 HVPs."""
+        Y0k = torch.from_numpy(gaussian(n, p, 100 + args.seed)).to(dev)
+        res = {}
+        for name, prec in (("mixed", FP32), ("fp64", FP64)):
+            if name not in which:
+                continue
+            o = prob.default_options()
+            o.hvp_prec = prec
+            o.time_limit_s = cap
+            o.verbose = 1 if args.verbose else 0
+            if args.p_max > 0:
+                o.p_max = args.p_max
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = prob.solve(Y0k, o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[name] = {"converged": r.status == 0, "seconds": dt, "eta": list(r.eta), "eta_max": max(r.eta),
+                         "value": r.value, "outer_iters": r.outer_iters, "rtr_iters": r.rtr_iters, "hvps": r.hvps,
+                         "p_final": r.p_final, "p_max_reached": r.p_max_reached, "phases_s": r.phases,
+                         "time_cap_s": cap}
+            print(f"[bench] time-to-KKT {name}: {dt:.1f} s converged={r.status == 0} eta={max(r.eta):.2e} "
+                  f"value={r.value:.10f} outer={r.outer_iters} hvps={r.hvps} p_max={r.p_max_reached}",
+                  file=sys.stderr, flush=True)
+        if "mixed" in res and "fp64" in res and res["mixed"]["converged"] and res["fp64"]["converged"]:
+            res["speedup_mixed_vs_fp64"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
+            res["value_rel_diff"] = abs(res["mixed"]["value"] - res["fp64"]["value"]) / (1 + abs(res["fp64"]["value"]))
+        return res
+
+    if args.kkt_only:
+        out = {"workload": f"dense BQP q={q} n={n} m={m} seed {args.seed}, p0={p}",
+               "time_to_kkt": kkt_solves(args.kkt_only.split(","), args.kkt_time_limit_s)}
+        print(json.dumps(out))
+        return 0
 
     # ---- isolated HVP throughput at a fixed point (realistic multiplier) ----
     Y = torch.from_numpy(gaussian(n, p, 1)).to(dev)
@@ -255,22 +301,7 @@ def main() -> int:
           f"eta={max(r_t.eta):.2e}", file=sys.stderr, flush=True)
 
     # ---- time to eta_max <= 1e-8 (capped full solves) ----
-    kkt = None
-    if args.kkt_time_limit_s > 0:
-        kkt = {}
-        for name, prec in (("mixed", FP32), ("fp64", FP64)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = prob.solve(Y0, options(prec, time_limit_s=args.kkt_time_limit_s))
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            kkt[name] = {"converged": r.status == 0, "seconds": dt, "eta_max": max(r.eta), "value": r.value,
-                         "outer_iters": r.outer_iters, "hvps": r.hvps, "p_final": r.p_final,
-                         "p_max_reached": r.p_max_reached, "time_cap_s": args.kkt_time_limit_s}
-            print(f"[bench] time-to-KKT {name}: {dt:.1f} s converged={r.status == 0} eta={max(r.eta):.2e}",
-                  file=sys.stderr, flush=True)
-        if kkt["mixed"]["converged"] and kkt["fp64"]["converged"]:
-            kkt["speedup_mixed_vs_fp64"] = kkt["fp64"]["seconds"] / kkt["mixed"]["seconds"]
+    kkt = kkt_solves(("mixed", "fp64"), args.kkt_time_limit_s) if args.kkt_time_limit_s > 0 else None
 
     out = {
         "metric": "HVPs/s + time to KKT<=1e-8, mixed vs FP64, dense BQP q=100 (n=5051)",

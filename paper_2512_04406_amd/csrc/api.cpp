@@ -138,7 +138,7 @@ static void free_problem(mdsdp_problem P) {
   if (!P) return;
   blas_destroy(P);
   void* ptrs[] = {P->cls,      P->Xt,     P->Xt32,    P->Ct,      P->segs,   P->seg_start, P->cy,
-                  P->Cavg,     P->yp,     P->ab32,    P->invc,    P->bvec,    P->sacc,   P->Yp,        P->Up,
+                  P->Cavg,     P->ab64,   P->ab32,    P->invc,    P->bvec,    P->sacc,   P->Yp,        P->Up,
                   P->bqp4_items, P->bqpT,     P->bqpStar,
                   P->zvec,     P->zmult,  P->rowpart, P->colpart, P->wgpart, P->zpart,     P->gram,
                   P->gpart,    P->scal,   P->bound,   P->dotpart, (void*)P->dotptr, P->lz_V, P->lz_w,
@@ -303,7 +303,7 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   TRY(dalloc(&P->segs, P->nseg));
   TRY(dalloc(&P->seg_start, P->nb + 1));
   TRY(dalloc(&P->cy, m));
-  TRY(dalloc(&P->yp, m));
+  TRY(dalloc(&P->ab64, m));
   TRY(dalloc(&P->ab32, m));
   TRY(dalloc(&P->invc, m));
   TRY(dalloc(&P->bvec, m));
@@ -352,7 +352,7 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   if (C) CP(P->Cavg, hCavg.data(), m * sizeof(double));
 #undef CP
   TRY(hipMemset(P->sacc, 0, m * sizeof(long long)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
-  TRY(hipMemset(P->yp, 0, m * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
+  TRY(hipMemset(P->ab64, 0, m * sizeof(double2)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
   TRY(hipMemset(P->scal, 0, SC_COUNT * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
   TRY(hipMemset(P->zvec, 0, n * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
   TRY(hipMemset(P->zmult, 0, n * sizeof(double)) == hipSuccess ? MDSDP_OK : MDSDP_EHIP);
@@ -480,7 +480,7 @@ mdsdp_status mdsdp_problem_info(mdsdp_problem P, int32_t* n, int64_t* m, int64_t
 mdsdp_status mdsdp_set_multiplier(mdsdp_problem P, const double* Xt_dev, double sigma, void* stream) {
   if (!P) return einval("problem is NULL");
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return einval("sigma must be positive and finite");
-  if (sigma != P->sigma) P->a32_valid = false;
+  if (sigma != P->sigma) P->a32_valid = P->a64_valid = false;
   P->sigma = sigma;
   return launch_set_dense(P, Xt_dev, (hipStream_t)stream);
 }
@@ -493,7 +493,7 @@ mdsdp_status mdsdp_get_multiplier(mdsdp_problem P, double* Xt_dev, void* stream)
 mdsdp_status mdsdp_set_sigma(mdsdp_problem P, double sigma) {
   if (!P) return einval("problem is NULL");
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return einval("sigma must be positive and finite");
-  if (sigma != P->sigma) P->a32_valid = false;
+  if (sigma != P->sigma) P->a32_valid = P->a64_valid = false;
   P->sigma = sigma;
   return MDSDP_OK;
 }

@@ -11,9 +11,11 @@
 //      the sums are bit-reproducible whatever the scheduling); k_final_*
 //      turns them into class averages and clears the accumulator.  This is
 //      the path for any class map; BQP relaxations in colex order use the
-//      structured kernels k_bqp* instead (no class-map reads, no atomics).
+//      structured kernels k_bqp_sums / k_bqpFin instead (no class-map reads,
+//      no atomics).
 //
-//  k_resid<T, MODE>  per-entry coefficient and symmetric product pass:
+//  k_resid<T, MODE, SW>  per-entry coefficient and symmetric product pass
+//      (FP64 tiles; slices of SW <= 64 factor columns):
 //      GRAD: r = Z - y, G = Xt + D + sigma r (Lemma lm:suboptimality), cost
 //            terms sum w r^2, sum w Xt Z, b^T y (eq. reduced-ALM-subproblem);
 //            out = G Y.
@@ -21,7 +23,8 @@
 //            out = (Xt + D) Y for z = diag((Xt + D) S) (step 7).
 //      XMV : out = (Xt + D) V (certificate matvec without -Diag(z)).
 //      HVP : a = coefficient of U, b = coefficient of Y per entry, out = A U + B Y
-//            (the entry-wise part of 2 G U + 2 sigma Q(Y U^T + U Y^T) Y).
+//            (the entry-wise part of 2 G U + 2 sigma Q(Y U^T + U Y^T) Y); the
+//            FP32-tile version of this mode is k_hvp32.
 //      Each 16 x 16 coefficient block is written to LDS once and read back in
 //      the two MFMA operand layouts, giving both the row-side product
 //      (rows of the tile) and the column-side product (columns) of the packed
@@ -88,7 +91,7 @@ struct KArgs {
   const void* Yp;
   const void* Up;
   const double2* cy;    // {D, y}
-  const double* yp;     // class averages of Y U^T + U Y^T
+  const double2* ab64;  // FP64 HVP class coefficients {D - sigma y, -sigma y'}
   const double* Cavg;   // A(C)/|gamma| or null
   long long* sacc;      // generic fixed-point accumulator
   const unsigned long long* bound;  // [ymax, umax] bit patterns
@@ -337,8 +340,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
         else
           xv[sc][v] = (XT)a.Xt32[off];
       }
-    double2 dyv[4][4];
-    double yzv[4][4];
+    double2 dyv[4][4];  // {D, y}, or for the HVP {D - sigma y, -sigma y'}
 #pragma unroll
     for (int sc = 0; sc < 4; ++sc)
 #pragma unroll
@@ -346,8 +348,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
         const uint32_t cw = cwv[sc][v];
         const bool valid = !(cw & 0x80000000u);
         const uint32_t id = valid ? (cw & CLS_MASK) : 0u;
-        dyv[sc][v] = a.cy[id];
-        if (MODE == M_HVP) yzv[sc][v] = a.yp[id];
+        dyv[sc][v] = (MODE == M_HVP) ? a.ab64[id] : a.cy[id];
       }
     // S blocks of the four sub-blocks (MFMA from LDS, K = p)
     v4 Sbv[4];
@@ -420,8 +421,8 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
           } else if (MODE == M_XMV) {
             av = (T)((double)xv[sc][v] + dy.x);
           } else {  // HVP (FP64 tiles; the FP32-tile HVP is k_hvp32)
-            bv = (T)(-sigma * yzv[sc][v]);
-            av = (T)((double)xv[sc][v] + (dy.x - sigma * dy.y) + sigma * Ce);
+            bv = (T)dy.y;
+            av = (T)((double)xv[sc][v] + dy.x + sigma * Ce);
           }
         }
         tAw[rv * LP + li] = av;
@@ -1349,11 +1350,20 @@ __global__ __launch_bounds__(256) void k_final_S(long long m, long long* __restr
 
 __global__ __launch_bounds__(256) void k_final_Z(long long m, long long* __restrict__ sacc,
                                                  const double* __restrict__ invc, const double* __restrict__ scal,
-                                                 double* __restrict__ yp) {
+                                                 double sigma, double2* __restrict__ ab64) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= m) return;
-  yp[g] = (double)sacc[g] / scal[SC_SCALE_Z] * invc[g];
+  ab64[g].y = -sigma * ((double)sacc[g] / scal[SC_SCALE_Z] * invc[g]);
   sacc[g] = 0;
+}
+
+// FP64 HVP: class coefficient D - sigma y of U (y of the last S-pass)
+__global__ __launch_bounds__(256) void k_make_a64(long long m, const double2* __restrict__ cy, double sigma,
+                                                  double2* __restrict__ ab64) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m) return;
+  const double2 dy = cy[g];
+  ab64[g].x = dy.x - sigma * dy.y;
 }
 
 // FP32-tile HVP: class coefficient -sigma y' of Y
@@ -1453,18 +1463,20 @@ struct BqpArgs {
   double* T;           // n x (q + 1) table B(row r, row x), x in {}, {0}, ..., {q-1}
   double* star;        // STAR_LG x q x q partials of sum_l (il|jl)
   double* dst;         // output element g at dst[g * stride]
-  int stride;          // 2 for the .y field of cy, 1 for yp
+  int stride;          // 2: the .y field of cy (S-pass) or of ab64 (FP64 HVP)
   double* part;        // degree-0 partials
   float2* dst32;       // FP32-tile HVP: class coefficient -sigma y'_g written to dst32[g].y instead
   double scale32;      // -sigma
 };
 
-// final class average `val` of class g: FP64 slot, or the FP32-tile HVP
-// coefficient -sigma val
+// final class average `val` of class g: the S-pass class average (FP64), or
+// the HVP class coefficient -sigma val (FP64 or FP32)
 template <typename T, bool ZMODE>
 __device__ __forceinline__ void bqp_store(const BqpArgs& a, long long g, double val) {
   if (ZMODE && sizeof(T) == 4)
     a.dst32[g].y = (float)(a.scale32 * val);
+  else if (ZMODE)
+    a.dst[g * a.stride] = a.scale32 * val;
   else
     a.dst[g * a.stride] = val;
 }
@@ -1783,7 +1795,7 @@ static KArgs make_args(mdsdp_problem P) {
   a.Yp = P->Yp;
   a.Up = P->Up;
   a.cy = P->cy;
-  a.yp = P->yp;
+  a.ab64 = P->ab64;
   a.sacc = P->sacc;
   a.Cavg = P->Cavg;
   a.bound = P->bound;
@@ -1867,8 +1879,8 @@ static mdsdp_status launch_bqp(mdsdp_problem P, bool zmode, bool fp32, hipStream
   b.items = P->bqp4_items;
   b.T = P->bqpT;
   b.star = P->bqpStar;
-  b.dst = zmode ? P->yp : (double*)P->cy + 1;
-  b.stride = zmode ? 1 : 2;
+  b.dst = zmode ? (double*)P->ab64 + 1 : (double*)P->cy + 1;
+  b.stride = 2;
   b.part = P->gpart + GP_BQP0;
   b.dst32 = P->ab32;
   b.scale32 = -P->sigma;
@@ -1902,6 +1914,7 @@ static mdsdp_status launch_bqp(mdsdp_problem P, bool zmode, bool fp32, hipStream
 
 mdsdp_status launch_classsum_S(mdsdp_problem P, hipStream_t s) {
   P->a32_valid = false;
+  P->a64_valid = false;
   timer_begin(P, s, "classsum_S");
   if (P->bqp_q > 0) {
     mdsdp_status st = launch_bqp(P, false, false, s);
@@ -1930,7 +1943,7 @@ mdsdp_status launch_classsum_Z(mdsdp_problem P, bool fp32, hipStream_t s) {
     if (fp32)
       k_final_Z32<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->scal, P->sigma, P->ab32);
     else
-      k_final_Z<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->scal, P->yp);
+      k_final_Z<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->sacc, P->invc, P->scal, P->sigma, P->ab64);
   }
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
@@ -1983,6 +1996,10 @@ mdsdp_status launch_resid(mdsdp_problem P, int mode, bool fp32, hipStream_t s) {
       SW_DISPATCH(P->pw, st = (resid_go<double, M_XMV, SWV>(P, a, g, s)));
       break;
     default:
+      if (!P->a64_valid) {
+        k_make_a64<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->cy, P->sigma, P->ab64);
+        P->a64_valid = true;
+      }
       timer_begin(P, s, "resid_hvp64");
       SW_DISPATCH(P->pw, st = (resid_go<double, M_HVP, SWV>(P, a, g, s)));
   }

@@ -91,7 +91,8 @@ struct mdsdp_problem_s {
   mdsdp::Seg* segs = nullptr;   // nseg
   int* seg_start = nullptr;     // nb + 1: segments of column block J are seg_start[J]..seg_start[J+1]-1
   double2* cy = nullptr;        // m: {D_gamma, y_gamma} (y = class average of Z at the last S-pass)
-  double* yp = nullptr;         // m: class average of Y U^T + U Y^T at the last HVP
+  double2* ab64 = nullptr;      // m: FP64 HVP class coefficients {D - sigma y (of U), -sigma y' (of Y)}
+  bool a64_valid = false;       // ab64[].x matches the current y and sigma
   float2* ab32 = nullptr;       // m: FP32-tile HVP class coefficients {D - sigma y (of U), -sigma y' (of Y)}
   bool a32_valid = false;       // ab32[].x matches the current y and sigma
   double* invc = nullptr;       // m: 1 / |gamma|

@@ -13,7 +13,9 @@
 //  * the certificate Lanczos starts from the previous Ritz vector plus a
 //    random component and stops when the error estimate of theta_min
 //    (residual, or residual^2 / Ritz gap) is below eig_tol (1 + |theta_max|);
-//    when it stops unconverged, eta_d uses theta_min minus that estimate;
+//    when it stops unconverged, eta_d uses theta_min minus that estimate, and
+//    when eta_d is then the only residual above the tolerance the step budget
+//    of the next eigensolve doubles (up to n);
 //  * with sigma_hold, sigma is not decreased after an RTR call that stopped
 //    at its iteration cap (its gradient norm then measures the unfinished
 //    subproblem, not the dual residual of eq. sec5:eq1);
@@ -664,6 +666,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   double prim_ratio = INFINITY;  // ||R|| / (1 + ||b||) of the last outer step
   double stall_cap = INFINITY;   // tolerance cap after an RTR call that took no step
   bool have_evec = false;
+  int eig_budget = opt->eig_maxit;
   for (k = 0; k < opt->max_outer; ++k) {
     CHK(mdsdp_set_sigma(P, sigma));
     const int prec = (opt->polish_fp64 && eta_max < opt->polish_eta) ? MDSDP_FP64 : opt->hvp_prec;
@@ -705,7 +708,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     bool conv = false;
     int nfound = 0;
     double lres = 0.0;
-    CHK(lanczos(P, opt->eig_tol, opt->eig_maxit, opt->seed + (uint64_t)k, &lmin, &lmax, evec, &eit, &conv, s,
+    CHK(lanczos(P, opt->eig_tol, eig_budget, opt->seed + (uint64_t)k, &lmin, &lmax, evec, &eit, &conv, s,
                 std::max(1, opt->n_neg), 1e-12, &nfound, have_evec ? evec : nullptr, &lres, true));
     have_evec = true;
     C.eig_iters += eit;
@@ -718,6 +721,11 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     const double prim = cx + sumz;
     eta[2] = fabs(prim - bty) / (1.0 + fabs(prim) + fabs(bty));
     eta_max = std::max(eta[0], std::max(eta[1], eta[2]));
+    // when only the dual residual (an unconverged Lanczos estimate) stands
+    // between the iterate and the tolerance, give the next eigensolve more
+    // steps (it restarts from the current Ritz vector)
+    if (!conv && eta[1] > opt->tol && eta[0] <= opt->tol && eta[2] <= opt->tol)
+      eig_budget = std::min(n, 2 * eig_budget);
     value = bty;
     if (hist && k < hist_cap) {
       double* hrow = hist + (size_t)k * 8;

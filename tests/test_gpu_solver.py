@@ -4,9 +4,11 @@
 * full solves (dense BQP, q = 10, p0 = 2, FP64 and FP32-tile HVPs): eta_max
   <= 1e-8, value = brute-force minimum (rank-one case) = oracle value;
 * q = 20: value equals the brute-force minimum, FP64 and mixed agree to 1e-8;
-* q = 30 (n = 466, rank cap 64): the returned factor and multiplier satisfy
+* q = 30 (n = 466): the returned factor and multiplier satisfy
   eta_max <= 1e-8 when the oracle recomputes the residuals (eq. res) from
-  them with dense LAPACK.
+  them with dense LAPACK;
+* q = 40 (n = 821, p0 = 4): mixed and FP64 reach the oracle's stored optimal
+  value to 1e-8 and agree; the rounded sign vector certifies tightness.
 """
 
 import numpy as np
@@ -120,3 +122,33 @@ def rel_class_average(S, rel):
     from oracle.operators import class_average
 
     return class_average(S, rel.cls, rel.counts)
+
+
+def _golden_q40():
+    import os
+
+    vals = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bqp_q40_seed0_value.txt")
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = float(v)
+    return vals
+
+
+def test_solve_q40_mixed_and_fp64_match_oracle_value():
+    """Dense BQP q = 40 (n = 821), p0 = 4 with rank adjustment: FP32-tile HVPs
+    (mixed) and FP64 HVPs both reach eta_max <= 1e-8 and the FP64 oracle's
+    optimal value (stored by tests/golden/make_bqp_q40_value.py) to 1e-8
+    relative, and agree with each other; the sign vector rounded from the
+    GPU's rank-one factor attains the same value (tight relaxation)."""
+    gold = _golden_q40()
+    Q, c, r32 = _solve(40, 0, 1, p0=4)
+    _, _, r64 = _solve(40, 0, 0, p0=4)
+    for r in (r32, r64):
+        assert r.status == 0 and max(r.eta) <= 1e-8
+        assert abs(r.value - gold["value"]) <= 1e-8 * (1 + abs(gold["value"]))
+    assert abs(r32.value - r64.value) <= 1e-8 * (1 + abs(r64.value))
+    x, fx = alm.rank_one_rounding(r32.Y.cpu().numpy(), Q, c, None)
+    assert abs(fx - r32.value) <= 1e-8 * (1 + abs(fx))
