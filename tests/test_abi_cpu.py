@@ -73,3 +73,36 @@ def test_argument_validation_is_synchronous():
     assert L.mdsdp_bqp_sizes(0, None, None) == -1
     assert L.mdsdp_cost_grad(None, 2, None, None, None, None, None) == -1
     assert b"NULL" in L.mdsdp_last_error() or b"problem" in L.mdsdp_last_error()
+
+
+def _coo(n, cls_full, skip=None, dup=None, val=1.0):
+    """Upper-triangle COO of a dense class map (row <= col)."""
+    r, c = np.triu_indices(n)
+    k = cls_full[r, c].astype(np.int32)
+    v = np.full(r.size, val)
+    if skip is not None:
+        keep = np.ones(r.size, bool)
+        keep[skip] = False
+        r, c, k, v = r[keep], c[keep], k[keep], v[keep]
+    if dup is not None:
+        r, c, k, v = np.append(r, r[dup]), np.append(c, c[dup]), np.append(k, k[dup]), np.append(v, v[dup])
+    return k.astype(np.int32), r.astype(np.int32), c.astype(np.int32), v
+
+
+@pytest.mark.parametrize("case,code", [("overlap", -4), ("uncovered", -6), ("signed", -6)])
+def test_sparse_A_validation(case, code):
+    """Sparse 0/1 A: overlapping supports (AA* not diagonal) -> MDSDP_ENOTORTH;
+    uncovered entries or non-unit values -> MDSDP_EUNSUPPORTED; both found on
+    the host before any device work."""
+    from paper_2512_04406_amd import _lib
+
+    q = 4
+    Q, c = bqp_instance(q, 0)
+    rel = bqp.build_relaxation(Q, c, "colex")
+    kw = {"overlap": dict(dup=3), "uncovered": dict(skip=5), "signed": dict(val=-1.0)}[case]
+    k, r, cc, v = _coo(rel.n, rel.cls, **kw)
+    L = _lib.lib()
+    h = C.c_void_p()
+    p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    got = L.mdsdp_create_sparse_A(rel.n, rel.m, k.size, p(k), p(r), p(cc), p(v), p(rel.b), None, C.byref(h))
+    assert got == code, L.mdsdp_last_error()

@@ -287,3 +287,42 @@ def test_wide_factors(q, p, structured):
     # a second update (the sliced update alternates multiplier buffers)
     prob.update_multiplier(Yt)
     assert _rel(prob.export_multiplier_packed(), (Xt1 + sigma * R)[iu]) <= 1e-13
+
+
+def test_sparse_A_problem_matches_classmap_problem():
+    """A problem given as a sparse 0/1 A (COO triplets in shuffled order, lex
+    basis) builds the same device layout as the class-map constructor: cost,
+    gradient and HVPs bitwise equal, and equal to the oracle."""
+    from paper_2512_04406_amd.problem import FP32, FP64, Problem
+
+    q, p, sigma = 9, 5, 1.3
+    Q, c = bqp_instance(q, 4)
+    rel = bqp.build_relaxation(Q, c, "lex")
+    n = rel.n
+    r, cc = np.triu_indices(n)
+    k = rel.cls[r, cc].astype(np.int32)
+    perm = np.random.default_rng(5).permutation(r.size)
+    sp = Problem.from_sparse_A(n, rel.m, k[perm], r[perm].astype(np.int32), cc[perm].astype(np.int32),
+                               np.ones(r.size), rel.b)
+    cm = Problem.from_classmap(n, rel.cls[r, cc], rel.b)
+    W = gaussian(n, n, 31)
+    Xt = Q_op(0.1 * (W + W.T), rel.cls, rel.counts)
+    Y = gaussian(n, p, 32)
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    U = proj_tangent(Y, gaussian(n, p, 33))
+    sub = Subproblem(rel.cls, rel.counts, rel.b, Xt, sigma)
+    outs = []
+    for P in (sp, cm):
+        P.set_multiplier(_t(Xt), sigma)
+        f, eg, rg = P.cost_grad(_t(Y))
+        h64 = P.hvp(_t(Y), _t(U), FP64)
+        h32 = P.hvp(_t(Y), _t(U), FP32)
+        torch.cuda.synchronize()
+        outs.append((f.cpu(), rg.cpu(), h64.cpu(), h32.cpu()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+    f, rg, h64, h32 = outs[0]
+    assert abs(f.item() - sub.cost(Y)) <= 1e-10 * (1 + abs(sub.cost(Y)))
+    assert _rel(rg.numpy(), sub.rgrad(Y)) <= 1e-10
+    assert _rel(h64.numpy(), sub.rhess(Y, U)) <= 1e-10
+    assert _rel(h32.numpy(), sub.rhess(Y, U)) <= 1e-4
