@@ -377,6 +377,26 @@ static mdsdp_status check_p(mdsdp_problem P, int p) {
   return MDSDP_OK;
 }
 
+mdsdp_status hvp_impl(mdsdp_problem P, int p, int prec, const double* Y, const double* U, double* HU, int riem,
+                      hipStream_t s, double* dotpart, double* dot_out) {
+  mdsdp_status st = check_p(P, p);
+  if (st != MDSDP_OK) return st;
+  if (!Y || !U || !HU) return einval("NULL argument");
+  if (prec != MDSDP_FP64 && prec != MDSDP_FP32) return einval("bad precision");
+  const bool fp32 = prec == MDSDP_FP32;
+  if ((st = launch_stage(P, p, Y, U, fp32, s)) != MDSDP_OK) return st;
+  if ((st = launch_classsum_Z(P, fp32, s)) != MDSDP_OK) return st;
+  if ((st = fp32 ? launch_hvp32(P, s) : launch_resid(P, M_HVP, false, s)) != MDSDP_OK) return st;
+  P->last_hvp_prec = prec;
+  // the Gram matrices feed only the row finaliser: launched after the long
+  // passes, the host enqueues them while those run
+  const bool need_yy = !(P->gram_yy_valid && P->gram_yy_p == p);
+  if ((st = launch_gram(P, p, Y, U, s, need_yy)) != MDSDP_OK) return st;
+  P->gram_yy_valid = true;
+  P->gram_yy_p = p;
+  return launch_rowfinal_hvp(P, p, fp32, Y, U, HU, riem ? 1 : 0, s, dotpart, dot_out);
+}
+
 }  // namespace mdsdp
 
 extern "C" {
@@ -513,21 +533,7 @@ mdsdp_status mdsdp_cost_grad(mdsdp_problem P, int32_t p, const double* Y, double
 
 mdsdp_status mdsdp_hvp(mdsdp_problem P, int32_t p, int32_t prec, const double* Y, const double* U, double* HU,
                        int32_t riemannian, void* stream) {
-  mdsdp_status st = check_p(P, p);
-  if (st != MDSDP_OK) return st;
-  if (!Y || !U || !HU) return einval("NULL argument");
-  if (prec != MDSDP_FP64 && prec != MDSDP_FP32) return einval("bad precision");
-  const bool fp32 = prec == MDSDP_FP32;
-  hipStream_t s = (hipStream_t)stream;
-  if ((st = launch_stage(P, p, Y, U, fp32, s)) != MDSDP_OK) return st;
-  const bool need_yy = !(P->gram_yy_valid && P->gram_yy_p == p);
-  if ((st = launch_gram(P, p, Y, U, s, need_yy)) != MDSDP_OK) return st;
-  P->gram_yy_valid = true;
-  P->gram_yy_p = p;
-  if ((st = launch_classsum_Z(P, fp32, s)) != MDSDP_OK) return st;
-  if ((st = fp32 ? launch_hvp32(P, s) : launch_resid(P, M_HVP, false, s)) != MDSDP_OK) return st;
-  P->last_hvp_prec = prec;
-  return launch_rowfinal_hvp(P, p, fp32, Y, U, HU, riemannian ? 1 : 0, s);
+  return hvp_impl(P, p, prec, Y, U, HU, riemannian, (hipStream_t)stream);
 }
 
 mdsdp_status mdsdp_class_average(mdsdp_problem P, int32_t p, const double* Y, double* y, void* stream) {

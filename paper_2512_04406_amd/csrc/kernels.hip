@@ -806,12 +806,14 @@ __global__ __launch_bounds__(256) void k_row_grad(RowArgs ra, const double* __re
 }
 
 // lr (nullable, n x p): precomputed low-rank term (wide factors); otherwise
-// it is formed here from the Gram matrices
+// it is formed here from the Gram matrices.  dotpart (nullable): the block's
+// partial of <U, HU> (fixed-order tree over the block), for the tCG curvature.
 template <typename T, int RM>
 __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __restrict__ Y,
                                                  const double* __restrict__ U, const double* __restrict__ gram,
                                                  const double* __restrict__ lr_pre, const double* __restrict__ zvec,
-                                                 double sigma, int riem, double* __restrict__ HU) {
+                                                 double sigma, int riem, double* __restrict__ HU,
+                                                 double* __restrict__ dotpart) {
   const int pw = ra.pw, L = row_lanes(pw), spl = row_split(pw);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int part = idx % spl, rc = idx / spl;
@@ -847,14 +849,41 @@ __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __res
   }
   const double d = riem ? sum_row_split(dp, L, spl) : 0.0;
   const double zr = (riem && in) ? zvec[r] : 0.0;
+  double uh = 0.0;
 #pragma unroll
   for (int j = 0; j < RM; ++j) {
     const int k = c0 + j * L;
     if (in && part == 0 && k < ra.p && k < pw) {
       const double v = riem ? Ht[j] - d * y[j] - 2.0 * zr * u[j] : Ht[j];
       HU[(size_t)r * ra.p + k] = v;
+      uh += u[j] * v;
     }
   }
+  if (dotpart) {
+    __shared__ double red[256];
+    red[threadIdx.x] = uh;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) dotpart[blockIdx.x] = red[0];
+  }
+}
+
+// out[0] = sum of nblk partials in a fixed order (one block)
+__global__ __launch_bounds__(256) void k_sum_partials(int nblk, const double* __restrict__ part,
+                                                      double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 __global__ __launch_bounds__(256) void k_row_mult(RowArgs ra, const double* __restrict__ Y,
@@ -1152,24 +1181,6 @@ __global__ __launch_bounds__(256) void k_dots_final(int npairs, int nblk, const 
   if (threadIdx.x == 0) out[q] = red[0];
 }
 
-// rr_new = ||r||^2 and beta = rr_new / rr_old (tCG); out[0] = rr_new, out[1] = beta
-__global__ __launch_bounds__(256) void k_rr_beta(int nblk, const double* __restrict__ part, double rr_old,
-                                                 double* __restrict__ out) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += 256) acc += part[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[0] = red[0];
-    out[1] = red[0] / rr_old;
-  }
-}
-
 // h_j = <V_j, w> for j < k: one block per basis vector (fixed order)
 __global__ __launch_bounds__(256) void k_vt_w(int n, const double* __restrict__ V, const double* __restrict__ w,
                                               double* __restrict__ h) {
@@ -1200,16 +1211,24 @@ __global__ __launch_bounds__(256) void k_fill(long long len, double v, double* o
   if (i < len) out[i] = v;
 }
 
-// truncated-CG update (Steihaug-Toint step): L lanes per row (L = the
+// truncated-CG update (Steihaug-Toint step), from the iterate of step j
+// (suffix _c) into that of step j + 1 (suffix _n): L lanes per row (L = the
 // smallest power of two >= p, at most 64), lane c0 owns columns c0, c0 + L, ...
-// part 1: eta += alpha d; Heta += alpha Hd; r = P_Y(r + alpha Hd); partial ||r||^2
+// The step length alpha = rr / <d, Hd> is formed here from sc_c = {rr, <d, Hd>}
+// of step j, so the host can enqueue the update before it has read them.
+// part 1: eta_n = eta_c + alpha d; Heta_n = Heta_c + alpha Hd;
+// r_n = P_Y(r_c + alpha Hd); block partials of ||r_n||^2
 template <int RM>
 __global__ __launch_bounds__(256) void k_tcg_update1(int n, int p, int L, const double* __restrict__ Y,
-                                                     double alpha, double* __restrict__ eta,
-                                                     double* __restrict__ Heta, double* __restrict__ r,
-                                                     const double* __restrict__ d, const double* __restrict__ Hd,
+                                                     const double* __restrict__ sc_c,
+                                                     const double* __restrict__ eta_c,
+                                                     const double* __restrict__ Heta_c,
+                                                     const double* __restrict__ r_c, const double* __restrict__ d_c,
+                                                     const double* __restrict__ Hd_c, double* __restrict__ eta_n,
+                                                     double* __restrict__ Heta_n, double* __restrict__ r_n,
                                                      double* __restrict__ part) {
   __shared__ double red[256];
+  const double alpha = sc_c[0] / sc_c[1];
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = idx / L, c0 = idx % L;
   const bool in = i < n;
@@ -1221,9 +1240,9 @@ __global__ __launch_bounds__(256) void k_tcg_update1(int n, int p, int L, const 
     rn[j] = 0.0;
     if (in && k < p) {
       const size_t o = (size_t)i * p + k;
-      eta[o] += alpha * d[o];
-      Heta[o] += alpha * Hd[o];
-      rn[j] = r[o] + alpha * Hd[o];
+      eta_n[o] = eta_c[o] + alpha * d_c[o];
+      Heta_n[o] = Heta_c[o] + alpha * Hd_c[o];
+      rn[j] = r_c[o] + alpha * Hd_c[o];
       dr += rn[j] * Y[o];
     }
   }
@@ -1235,28 +1254,44 @@ __global__ __launch_bounds__(256) void k_tcg_update1(int n, int p, int L, const 
     if (in && k < p) {
       const size_t o = (size_t)i * p + k;
       rn[j] -= dr * Y[o];
-      r[o] = rn[j];
+      r_n[o] = rn[j];
       rr += rn[j] * rn[j];
     }
   }
   red[threadIdx.x] = rr;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// part 2: d = P_Y(-r + beta d) with beta read from device memory
+// part 2: rr_n = ||r_n||^2 from part 1's nblk partials (every block sums them
+// in the same fixed order), beta = rr_n / rr_c, d_n = P_Y(-r_n + beta d_c);
+// block 0 writes sc_n[0] = rr_n
 template <int RM>
-__global__ __launch_bounds__(256) void k_tcg_update2(int n, int p, int L, const double* __restrict__ Y,
-                                                     const double* __restrict__ beta_dev,
-                                                     const double* __restrict__ r, double* __restrict__ d) {
+__global__ __launch_bounds__(256) void k_tcg_update2(int n, int p, int L, const double* __restrict__ Y, int nblk,
+                                                     const double* __restrict__ part,
+                                                     const double* __restrict__ sc_c, double* __restrict__ sc_n,
+                                                     const double* __restrict__ r_n,
+                                                     const double* __restrict__ d_c, double* __restrict__ d_n) {
+  __shared__ double red[256];
+  {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 256) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+  }
+  const double rr_new = red[0], beta = rr_new / sc_c[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc_n[0] = rr_new;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = idx / L, c0 = idx % L;
   const bool in = i < n;
-  const double beta = *beta_dev;
   double dn[RM];
   double dd = 0.0;
 #pragma unroll
@@ -1265,7 +1300,7 @@ __global__ __launch_bounds__(256) void k_tcg_update2(int n, int p, int L, const 
     dn[j] = 0.0;
     if (in && k < p) {
       const size_t o = (size_t)i * p + k;
-      dn[j] = -r[o] + beta * d[o];
+      dn[j] = -r_n[o] + beta * d_c[o];
       dd += dn[j] * Y[o];
     }
   }
@@ -1275,7 +1310,7 @@ __global__ __launch_bounds__(256) void k_tcg_update2(int n, int p, int L, const 
     const int k = c0 + j * L;
     if (in && k < p) {
       const size_t o = (size_t)i * p + k;
-      d[o] = dn[j] - dd * Y[o];
+      d_n[o] = dn[j] - dd * Y[o];
     }
   }
 }
@@ -1461,7 +1496,7 @@ struct BqpArgs {
   const void* Up;
   const int4* items;   // k_bqp4 work items (c, d0, a0, b0)
   double* T;           // n x (q + 1) table B(row r, row x), x in {}, {0}, ..., {q-1}
-  double* star;        // STAR_LG x q x q partials of sum_l (il|jl)
+  double* star;        // STAR_LG x q x q partials of sum_l (il|jl), as [lg][j][i]
   double* dst;         // output element g at dst[g * stride]
   int stride;          // 2: the .y field of cy (S-pass) or of ab64 (FP64 HVP)
   double* part;        // degree-0 partials
@@ -1665,7 +1700,9 @@ __device__ __forceinline__ void bqpT_tile(const BqpArgs& a, int n, int bx, int b
 }
 
 // star partials: sum over l = lg, lg + STAR_LG, ... of (il|jl) for the 16 x 16
-// tile (I, J), I <= J, of (i, j); the term l = i or l = j is left out
+// tile (I, J), I <= J, of (i, j); the term l = i or l = j is left out.  Stored
+// as star[lg][j][i], so that the finisher's threads (consecutive i at fixed j)
+// read consecutive addresses.
 template <typename T, bool ZMODE>
 __device__ __forceinline__ void bqpStar_tile(const BqpArgs& a, int tile, int lg, int lane) {
   typedef typename V4<T>::type v4;
@@ -1701,7 +1738,7 @@ __device__ __forceinline__ void bqpStar_tile(const BqpArgs& a, int tile, int lg,
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int ii = 16 * I + drow<T>(lk, v);
-    if (ii < q && j < q) a.star[((size_t)lg * q + ii) * q + j] = (double)acc[v];
+    if (ii < q && j < q) a.star[((size_t)lg * q + j) * q + ii] = (double)acc[v];
   }
 }
 
@@ -1756,7 +1793,7 @@ __global__ __launch_bounds__(256) void k_bqpFin(BqpArgs a, int n, int nblkT, int
     const int j = inv_c2(t), i = (int)(t - c2(j));
     double sp[STAR_LG];
 #pragma unroll
-    for (int lg = 0; lg < STAR_LG; ++lg) sp[lg] = a.star[((size_t)lg * q + i) * q + j];
+    for (int lg = 0; lg < STAR_LG; ++lg) sp[lg] = a.star[((size_t)lg * q + j) * q + i];
     double s = Tt[(size_t)prow(q, i, j) * ldT] + Tt[(size_t)(1 + i) * ldT + 1 + j];
 #pragma unroll
     for (int lg = 0; lg < STAR_LG; ++lg) s += sp[lg];
@@ -2156,10 +2193,13 @@ mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* 
     MDSDP_HIP(hipGetLastError());
     return MDSDP_OK;
   }
-  const int nblk = std::min(gram_blocks(gpw), (P->n + 63) / 64);
+  // row blocks: about 16 rows each (short dependent load/MFMA chains), within
+  // the partial buffer
+  const GramSplit GS(gpw);
+  const int nblk = (int)std::max<size_t>(
+      1, std::min<size_t>({(size_t)256, (size_t)(P->n + 15) / 16, GRAM_PART_MAX / ((size_t)GS.RS * 2 * gpw * gpw)}));
   timer_begin(P, s, "gram");
   P->gram_pw = gpw;
-  const GramSplit GS(gpw);
   const int len = 2 * gpw * gpw, e0 = with_yy ? 0 : gpw * gpw;
   const int nparts = nblk * GS.RS;
   k_gram_part<<<dim3(nblk, GS.NGRP), 256, 0, s>>>(P->n, p, gpw, with_yy ? 1 : 0, Y, U, P->gpart + GP_GRAM);
@@ -2191,7 +2231,7 @@ mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, doubl
 }
 
 mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double* Y, const double* U,
-                                 double* HU, int riem, hipStream_t s) {
+                                 double* HU, int riem, hipStream_t s, double* dotpart, double* dot_out) {
   RowArgs ra = row_args(P, p);
   timer_begin(P, s, "row_hvp");
   const unsigned nblk = blocks_for((long long)P->n * 64, 256);  // L * SPL = 64 lanes per row
@@ -2214,7 +2254,8 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
     lr = P->lrbuf;
   }
   const int rm = P->pw <= 64 ? 1 : P->pw / 64;
-#define ROW_HVP(TT, RMV) k_row_hvp<TT, RMV><<<nblk, 256, 0, s>>>(ra, Y, U, P->gram, lr, P->zvec, P->sigma, riem, HU)
+#define ROW_HVP(TT, RMV) \
+  k_row_hvp<TT, RMV><<<nblk, 256, 0, s>>>(ra, Y, U, P->gram, lr, P->zvec, P->sigma, riem, HU, dot_out ? dotpart : nullptr)
   if (fp32) {
     if (rm <= 1)
       ROW_HVP(float, 1);
@@ -2235,6 +2276,7 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
       ROW_HVP(double, 8);
   }
 #undef ROW_HVP
+  if (dot_out) k_sum_partials<<<1, 256, 0, s>>>((int)nblk, dotpart, dot_out);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -2305,18 +2347,17 @@ mdsdp_status vec_lincomb(long long len, double alpha, const double* x, double be
   return MDSDP_OK;
 }
 
-mdsdp_status launch_tcg_update(int n, int p, const double* Y, double alpha, double rr_old, double* eta,
-                               double* Heta, double* r, double* d, const double* Hd, double* part,
-                               double* rr_beta_dev, hipStream_t s) {
+mdsdp_status launch_tcg_update(int n, int p, const double* Y, const double* sc_c, double* sc_n, const TcgIter& c,
+                               const TcgIter& nx, double* part, hipStream_t s) {
   int L = 1;
   while (L < p && L < 64) L <<= 1;
   const int rm = (p + L - 1) / L;
   const unsigned nb = blocks_for((long long)n * L, 256);
-#define TCG_GO(RMV)                                                                                       \
-  do {                                                                                                    \
-    k_tcg_update1<RMV><<<nb, 256, 0, s>>>(n, p, L, Y, alpha, eta, Heta, r, d, Hd, part);                  \
-    k_rr_beta<<<1, 256, 0, s>>>((int)nb, part, rr_old, rr_beta_dev);                                      \
-    k_tcg_update2<RMV><<<nb, 256, 0, s>>>(n, p, L, Y, rr_beta_dev + 1, r, d);                             \
+#define TCG_GO(RMV)                                                                                          \
+  do {                                                                                                       \
+    k_tcg_update1<RMV><<<nb, 256, 0, s>>>(n, p, L, Y, sc_c, c.eta, c.Heta, c.r, c.d, c.Hd, nx.eta, nx.Heta,  \
+                                          nx.r, part);                                                       \
+    k_tcg_update2<RMV><<<nb, 256, 0, s>>>(n, p, L, Y, (int)nb, part, sc_c, sc_n, nx.r, c.d, nx.d);           \
   } while (0)
   if (rm <= 1)
     TCG_GO(1);

@@ -184,8 +184,14 @@ mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* 
                          hipStream_t s, bool with_yy = true);
 mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, double* egrad,
                                   double* rgrad, double* f, hipStream_t s);
+// dot_out (nullable): <U, HU> written there (block partials in dotpart, at
+// least n / 4 + 1 doubles)
 mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double* Y,
-                                 const double* U, double* HU, int riem, hipStream_t s);
+                                 const double* U, double* HU, int riem, hipStream_t s,
+                                 double* dotpart = nullptr, double* dot_out = nullptr);
+// the HVP of mdsdp_hvp, optionally with <U, HU> left on the device
+mdsdp_status hvp_impl(mdsdp_problem P, int p, int prec, const double* Y, const double* U, double* HU,
+                      int riem, hipStream_t s, double* dotpart = nullptr, double* dot_out = nullptr);
 mdsdp_status launch_rowfinal_mult(mdsdp_problem P, int p, const double* Y, double* z,
                                   double* kkt, hipStream_t s);
 mdsdp_status launch_rowfinal_xmv(mdsdp_problem P, int k, const double* V, double* XV,
@@ -209,9 +215,14 @@ mdsdp_status vec_dots(const DotPtrs& dp, int npairs, long long len, double* out_
 mdsdp_status vec_lincomb(long long len, double alpha, const double* x, double beta,
                          const double* y, double* out, hipStream_t s);
 mdsdp_status vec_fill(long long len, double v, double* out, hipStream_t s);
-mdsdp_status launch_tcg_update(int n, int p, const double* Y, double alpha, double rr_old, double* eta,
-                               double* Heta, double* r, double* d, const double* Hd, double* part,
-                               double* rr_beta_dev, hipStream_t s);
+// one truncated-CG iterate (n x p each)
+struct TcgIter {
+  double *eta, *Heta, *r, *d, *Hd;
+};
+// c -> nx with alpha = sc_c[0] / sc_c[1] (rr, <d, Hd> of c); writes
+// sc_n[0] = ||r_nx||^2 (part: n / 4 + 1 doubles of scratch)
+mdsdp_status launch_tcg_update(int n, int p, const double* Y, const double* sc_c, double* sc_n, const TcgIter& c,
+                               const TcgIter& nx, double* part, hipStream_t s);
 mdsdp_status launch_vt_w(int n, int k, const double* V, const double* w, double* h, hipStream_t s);
 mdsdp_status launch_rightmul(int n, int p, int q, const double* Yin, const double* M, bool normalize,
                              double* Yout, hipStream_t s);

@@ -266,12 +266,14 @@ mdsdp_status read_dev(mdsdp_problem P, const double* dev, int cnt, double* host,
 struct Work {
   int n = 0;
   double* buf = nullptr;
-  double *Ynew, *g, *gnew, *eta, *Heta, *r, *d, *Hd, *U, *tmp, *part, *rrb;
+  double *Ynew, *g, *gnew, *eta, *Heta, *r, *d, *Hd, *U, *tmp, *part, *dpart, *rrb;
+  TcgIter it2;  // the second truncated-CG iterate (double buffering)
+  hipEvent_t ev[2] = {nullptr, nullptr};
   mdsdp_status init(int n_) {
     n = n_;
     const size_t vec = (size_t)n * PMAX;
     const size_t npart = (size_t)n / 4 + 64;  // tCG partials: one per 256 threads of 64-lane rows
-    hipError_t e = hipMalloc((void**)&buf, (10 * vec + npart + 96) * sizeof(double));
+    hipError_t e = hipMalloc((void**)&buf, (15 * vec + 2 * npart + 96) * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(solver work)");
     double* p = buf;
     Ynew = p; p += vec;
@@ -284,11 +286,21 @@ struct Work {
     Hd = p; p += vec;
     U = p; p += vec;
     tmp = p; p += vec;
+    it2.eta = p; p += vec;
+    it2.Heta = p; p += vec;
+    it2.r = p; p += vec;
+    it2.d = p; p += vec;
+    it2.Hd = p; p += vec;
     part = p; p += npart;
+    dpart = p; p += npart;
     rrb = p;
+    for (auto& x : ev)
+      if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
     return MDSDP_OK;
   }
   ~Work() {
+    for (auto& x : ev)
+      if (x) (void)hipEventDestroy(x);
     if (buf) (void)hipFree(buf);
   }
 };
@@ -313,65 +325,88 @@ enum { TCG_NEG = 0, TCG_BOUND = 1, TCG_CONV = 2, TCG_MAXIT = 3 };
 
 mdsdp_status tcg(mdsdp_problem P, int p, const double* Y, const double* g, double gn, double Delta, int prec,
                  int maxinner, Work& W, Counters& C, int* stop, hipStream_t s) {
-  // Steihaug-Toint truncated CG.  Host state at the top of step j:
-  // rr = ||r||^2, e_Pe = <eta, eta>, e_Pd = <eta, d>, d_Pd = <d, d>.
-  // The device update of step j also computes ||r_new||^2 and beta and
-  // applies d = P_Y(-r + beta d); the host reads those two scalars together
-  // with <d, Hd> of step j + 1 (one synchronisation per step).  A convergence
-  // detected there discards that last HVP; eta is the one of step j.
+  // Steihaug-Toint truncated CG, pipelined one step ahead.  Iterate j lives in
+  // buffer j % 2 (it[0] = the caller's W.eta / W.Heta).  The device scalars
+  // sc[j % 2] = {rr_j = ||r_j||^2, <d_j, H d_j>}; the update j -> j + 1 forms
+  // alpha and beta from them on the device.  The host enqueues the update of
+  // step j and the HVP of step j + 1 before it reads step j's scalars (one
+  // event wait per step), then takes the same decisions as the plain loop
+  // from host copies of the same scalars:
+  //   rr_j = ||r_j||^2 <= tol^2  -> stop at eta_j (converged),
+  //   <d, Hd> <= 0 or ||eta_j + alpha d_j|| >= Delta -> stop on the boundary,
+  // tracking <eta, eta>, <eta, d>, <d, d> by their recurrences.  When it stops
+  // at step j the work already enqueued for step j + 1 went into the other
+  // buffer and is discarded (one HVP).
   const int n = P->n;
   const long long len = (long long)n * p;
   const double kappa = 0.1, theta = 1.0;
-  CHK(vec_fill(len, 0.0, W.eta, s));
-  CHK(vec_fill(len, 0.0, W.Heta, s));
-  CHK(vec_lincomb(len, 1.0, g, 0.0, nullptr, W.r, s));
-  CHK(vec_lincomb(len, -1.0, g, 0.0, nullptr, W.d, s));
-  double rr = gn * gn;
-  const double tol = gn * std::min(pow(gn, theta), kappa);
-  double e_Pe = 0.0, e_Pd = 0.0, d_Pd = rr;
-  bool pending = false;
-  double e_part = 0.0, d_Pd_old = 0.0;
   *stop = TCG_MAXIT;
-  DotPtrs dp{};
-  dp.a[0] = W.d;
-  dp.b[0] = W.Hd;
+  TcgIter it[2] = {{W.eta, W.Heta, W.r, W.d, W.Hd}, W.it2};
+  double* sc[2] = {W.rrb, W.rrb + 4};
+  const double* hs[2] = {P->hbuf + 40, P->hbuf + 44};
+  CHK(vec_fill(len, 0.0, it[0].eta, s));
+  CHK(vec_fill(len, 0.0, it[0].Heta, s));
+  CHK(vec_lincomb(len, 1.0, g, 0.0, nullptr, it[0].r, s));
+  CHK(vec_lincomb(len, -1.0, g, 0.0, nullptr, it[0].d, s));
+  double rr = gn * gn;
+  CHK(vec_fill(1, rr, sc[0], s));
+  if (maxinner <= 0) return MDSDP_OK;
+  const double tol = gn * std::min(pow(gn, theta), kappa);
+  double e_Pe = 0.0, e_Pd = 0.0, d_Pd = rr, e_part = 0.0, d_Pd_old = 0.0;
+  auto t0 = clk::now();
+  CHK(hvp_impl(P, p, prec, Y, it[0].d, it[0].Hd, 1, s, W.dpart, sc[0] + 1));
+  C.hvps++;
+  MDSDP_HIP(hipMemcpyAsync((void*)hs[0], sc[0], 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  MDSDP_HIP(hipEventRecord(W.ev[0], s));
+  int cur = 0;
+  // moves the result of iterate `k` into it[0]
+  auto finish = [&](int k) -> mdsdp_status {
+    if (k != 0) {
+      CHK(vec_lincomb(len, 1.0, it[k].eta, 0.0, nullptr, it[0].eta, s));
+      CHK(vec_lincomb(len, 1.0, it[k].Heta, 0.0, nullptr, it[0].Heta, s));
+    }
+    return MDSDP_OK;
+  };
   for (int j = 0; j < maxinner; ++j) {
-    auto t0 = clk::now();
-    CHK(mdsdp_hvp(P, p, prec, Y, W.d, W.Hd, 1, s));
-    C.hvps++;
-    CHK(vec_dots(dp, 1, len, P->scal + SC_DOTS, P->dotpart, P->dot_nblk, s));
-    MDSDP_HIP(hipMemcpyAsync(P->hbuf, P->scal + SC_DOTS, sizeof(double), hipMemcpyDeviceToHost, s));
-    if (pending) MDSDP_HIP(hipMemcpyAsync(P->hbuf + 1, W.rrb, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    MDSDP_HIP(hipStreamSynchronize(s));
-    C.t_hvp += secs(t0, clk::now());
-    const double dHd = P->hbuf[0];
-    if (pending) {
-      const double rr_new = P->hbuf[1], beta = P->hbuf[2];
-      if (sqrt(rr_new) <= tol) {
+    const int nxt = cur ^ 1;
+    // speculative: the update of step j, and the HVP of step j + 1
+    CHK(launch_tcg_update(n, p, Y, sc[cur], sc[nxt], it[cur], it[nxt], W.part, s));
+    if (j + 1 < maxinner) {
+      CHK(hvp_impl(P, p, prec, Y, it[nxt].d, it[nxt].Hd, 1, s, W.dpart, sc[nxt] + 1));
+      C.hvps++;
+      MDSDP_HIP(hipMemcpyAsync((void*)hs[nxt], sc[nxt], 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      MDSDP_HIP(hipEventRecord(W.ev[nxt], s));
+    }
+    MDSDP_HIP(hipEventSynchronize(W.ev[cur]));
+    const double rr_j = hs[cur][0], dHd = hs[cur][1];
+    if (j > 0) {
+      if (sqrt(rr_j) <= tol) {
+        C.t_hvp += secs(t0, clk::now());
         *stop = TCG_CONV;
-        return MDSDP_OK;
+        return finish(cur);
       }
+      const double beta = rr_j / rr;  // the device's beta: the same operands
       e_Pd = beta * e_part;
-      d_Pd = rr_new + beta * beta * d_Pd_old;
-      rr = rr_new;
-      pending = false;
+      d_Pd = rr_j + beta * beta * d_Pd_old;
+      rr = rr_j;
     }
     const double alpha = (dHd != 0.0) ? rr / dHd : INFINITY;
     const double e_Pe_new = e_Pe + 2.0 * alpha * e_Pd + alpha * alpha * d_Pd;
     if (dHd <= 0.0 || e_Pe_new >= Delta * Delta) {
       const double tau = (-e_Pd + sqrt(std::max(0.0, e_Pd * e_Pd + d_Pd * (Delta * Delta - e_Pe)))) / d_Pd;
-      CHK(vec_lincomb(len, tau, W.d, 1.0, W.eta, W.eta, s));
-      CHK(vec_lincomb(len, tau, W.Hd, 1.0, W.Heta, W.Heta, s));
+      CHK(vec_lincomb(len, tau, it[cur].d, 1.0, it[cur].eta, it[0].eta, s));
+      CHK(vec_lincomb(len, tau, it[cur].Hd, 1.0, it[cur].Heta, it[0].Heta, s));
+      C.t_hvp += secs(t0, clk::now());
       *stop = dHd <= 0.0 ? TCG_NEG : TCG_BOUND;
       return MDSDP_OK;
     }
     e_Pe = e_Pe_new;
-    CHK(launch_tcg_update(n, p, Y, alpha, rr, W.eta, W.Heta, W.r, W.d, W.Hd, W.part, W.rrb, s));
-    pending = true;
     e_part = e_Pd + alpha * d_Pd;
     d_Pd_old = d_Pd;
+    cur = nxt;
   }
-  return MDSDP_OK;
+  C.t_hvp += secs(t0, clk::now());
+  return finish(cur);
 }
 
 // ---- Riemannian trust region -------------------------------------------------------
