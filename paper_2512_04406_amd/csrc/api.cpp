@@ -139,7 +139,7 @@ static void free_problem(mdsdp_problem P) {
   blas_destroy(P);
   void* ptrs[] = {P->cls,      P->Xt,     P->Xt32,    P->Ct,      P->segs,   P->seg_start, P->cy,
                   P->Cavg,     P->ab64,   P->ab32,    P->invc,    P->bvec,    P->sacc,   P->Yp,        P->Up,
-                  P->bqp4_items, P->bqpT,     P->bqpStar,
+                  P->bqp4_items, P->bqp1_items, P->bqp2_items, P->bqpP1, P->bqpT, P->bqpStar,
                   P->zvec,     P->zmult,  P->rowpart, P->colpart, P->wgpart, P->zpart,     P->gram,
                   P->gpart,    P->scal,   P->bound,   P->dotpart, (void*)P->dotptr, P->lz_V, P->lz_w,
                   P->lz_h,     P->lz_hpart, P->work,   P->Xt2,     P->lrbuf};
@@ -422,21 +422,48 @@ mdsdp_status mdsdp_create_bqp(int32_t q, int32_t order, const double* Q, const d
   mdsdp_problem P = nullptr;
   if ((st = create_from_packed(n, m, cls.data(), b.data(), nullptr, &P)) != MDSDP_OK) return st;
   if (order == MDSDP_ORDER_COLEX && q >= 1) {
-    // structured class-sum kernels: degree-4 work items (c, d0, a0, b0) with
-    // 16-blocks of d > c, of b < c and of a <= b
+    // structured class-sum kernels.  Degree-4 pass 1: items (d, c0, t0), a
+    // 16-block of c < d and 64 pair rows t below C(c0 + 15, 2); pass 2: one
+    // item per (c, d), 2 <= c < d < q, the largest c (most work) first.
     P->bqp_q = q;
     bqp_offsets(q, P->bqp_off);
-    std::vector<int4> items;
+    std::vector<int4> items1;
+    for (int d = 3; d < q; ++d)
+      for (int c0 = 0; c0 < d; c0 += 16) {
+        const long long cm = std::min(c0 + 15, d - 1);
+        if (cm < 2) continue;
+        const long long nt = cm * (cm - 1) / 2;
+        for (long long t0 = 0; t0 < nt; t0 += 64) items1.push_back(make_int4(d, c0, (int)t0, 0));
+      }
+    std::vector<int4> items4;  // single-pass items: 16-blocks of d > c, of b < c and of a <= b
     for (int cc = 2; cc <= q - 2; ++cc)
       for (int d0 = cc + 1; d0 < q; d0 += 16)
         for (int b0 = 0; b0 < cc; b0 += 16)
-          for (int a0 = 0; a0 <= b0; a0 += 16) items.push_back(make_int4(cc, d0, a0, b0));
-    P->bqp4_n = (int)items.size();
+          for (int a0 = 0; a0 <= b0; a0 += 16) items4.push_back(make_int4(cc, d0, a0, b0));
+    std::vector<int2> items2;
+    for (int cc = q - 2; cc >= 2; --cc)
+      for (int d = cc + 1; d < q; ++d) items2.push_back(make_int2(cc, d));
+    P->bqp4_n = (int)items4.size();
+    P->bqp1_n = (int)items1.size();
+    P->bqp2_n = (int)items2.size();
+    const long long n4 = std::max<long long>(1, (long long)q * (q - 1) * (q - 2) * (q - 3) / 24);
     hipError_t e = hipSuccess;
-    if (!items.empty()) {
-      e = hipMalloc((void**)&P->bqp4_items, items.size() * sizeof(int4));
-      if (e == hipSuccess) e = hipMemcpy(P->bqp4_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (!items4.empty()) {
+      e = hipMalloc((void**)&P->bqp4_items, items4.size() * sizeof(int4));
+      if (e == hipSuccess)
+        e = hipMemcpy(P->bqp4_items, items4.data(), items4.size() * sizeof(int4), hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess && !items1.empty()) {
+      e = hipMalloc((void**)&P->bqp1_items, items1.size() * sizeof(int4));
+      if (e == hipSuccess)
+        e = hipMemcpy(P->bqp1_items, items1.data(), items1.size() * sizeof(int4), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && !items2.empty()) {
+      e = hipMalloc((void**)&P->bqp2_items, items2.size() * sizeof(int2));
+      if (e == hipSuccess)
+        e = hipMemcpy(P->bqp2_items, items2.data(), items2.size() * sizeof(int2), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&P->bqpP1, (size_t)n4 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&P->bqpT, (size_t)n * (q + 1) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&P->bqpStar, (size_t)STAR_LG * q * q * sizeof(double));
     if (e != hipSuccess) {

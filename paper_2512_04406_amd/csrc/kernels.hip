@@ -11,7 +11,7 @@
 //      the sums are bit-reproducible whatever the scheduling); k_final_*
 //      turns them into class averages and clears the accumulator.  This is
 //      the path for any class map; BQP relaxations in colex order use the
-//      structured kernels k_bqp_sums / k_bqpFin instead (no class-map reads,
+//      structured kernels k_bqp_pass1 / k_bqp_pass2 / k_bqpFin instead (no class-map reads,
 //      no atomics).
 //
 //  k_resid<T, MODE, SW>  per-entry coefficient and symmetric product pass
@@ -1449,18 +1449,27 @@ __global__ __launch_bounds__(256) void k_bty_part(long long range, const double*
 //   {i<j}    : ({}|ij) + (i|j) + sum_l (il|jl)     |gamma| = 2q
 //   {i}      : ({}|i) + sum_j (j|ij)              |gamma| = 2q
 //   {}       : sum_alpha B(alpha, alpha)          |gamma| = n
-// Degree 4 (96% of the classes): k_bqp4 takes one (c, 16 d's, 16 a's, 16 b's)
-// block; (ab|cd) is an MFMA tile in (a, d) for each b, (ac|bd) + (ad|bc) an
-// MFMA tile in (a, b) for each d, and the first is transposed through LDS
-// onto the second.  Ids base4(c, d) + a + C(b, 2) are written once each.
+// Degree 4 (96% of the classes), two passes over the pair rows of the basis
+// (in colex order the rows {x, c}, x < c, are consecutive, and so are the
+// pair rows t = C(b, 2) + a themselves):
+// (for factors of at most 32 columns a single-pass kernel, bqp4_block, is
+// used instead: see there)
+//   pass 1 (k_bqp_pass1): (ab|cd) for fixed d is an MFMA GEMM of the rows
+//     {c, d} of a 16-block of c against 64 consecutive pair rows t, masked to
+//     t < C(c, 2); kept in p1[C(d, 4) + C(c, 3) + t] (the degree-4 local id);
+//   pass 2 (k_bqp_pass2): one workgroup per (c, d) forms the full c x c matrix
+//     M[x][y] = (xc|yd) from LDS-staged chunks of the rows {x, c} and {y, d};
+//     then (ac|bd) + (ad|bc) = M[a][b] + M[b][a], transposed through LDS, is
+//     added to p1 and each class {a<b<c<d} is written once.
 // Degrees 0-3 read the table T[r][x] = B(row r, row x) of every basis row r
-// against the rows {} and {i} (one small GEMM, k_bqpT), and the contraction
-// star[i][j] = sum_l (il|jl) (k_bqpStar, partials over residues of l), and
-// are finished by k_bqpFin.  No class map is read, no atomics are used, every
-// sum has a fixed order.  MFMA operands come straight from the staged rows:
-// lane (i, k) loads the 4-vector of columns 4k..4k+3 of row i, and the four
-// MFMAs of a 16-column chunk use its four components (a permutation of the
-// contraction index shared by both operands).
+// against the rows {} and {i} (one small GEMM, the k_bqpT tasks), and the
+// contraction star[i][j] = sum_l (il|jl) (the k_bqpStar tasks, partials over
+// residues of l), both launched with pass 1, and are finished by k_bqpFin.
+// No class map is read, no atomics are used, every sum has a fixed order.
+// MFMA operands come straight from the staged rows: lane (i, k) loads the
+// W-vector of columns W k .. W k + W - 1 of row i, and the W MFMAs of a
+// 4W-column chunk use its W components (a permutation of the contraction
+// index shared by both operands).
 // ---------------------------------------------------------------------------
 // binomials without 64-bit integer division (emulated on the GPU): x <= 362
 __device__ __forceinline__ long long c2(long long x) { return (x * (x - 1)) >> 1; }
@@ -1494,7 +1503,10 @@ struct BqpArgs {
   long long off2, off3, off4;
   const void* Yp;
   const void* Up;
-  const int4* items;   // k_bqp4 work items (c, d0, a0, b0)
+  const int4* items4;  // single-pass work items (c, d0, a0, b0)
+  const int4* items;   // pass-1 work items (d, c0, t0, 0)
+  const int2* items2;  // pass-2 work items (c, d)
+  void* p1;            // pass-1 results (T), C(q, 4) of them
   double* T;           // n x (q + 1) table B(row r, row x), x in {}, {0}, ..., {q-1}
   double* star;        // STAR_LG x q x q partials of sum_l (il|jl), as [lg][j][i]
   double* dst;         // output element g at dst[g * stride]
@@ -1552,12 +1564,17 @@ __device__ __forceinline__ void bform_mfma(const T* Y, const T* U, size_t ra, si
   }
 }
 
+// Single-pass degree-4 variant for narrow factors (p <= 32, where the two
+// passes below are bound by latency rather than by the matrix cores): one
+// (c, 16 d's, 16 a's, 16 b's) block per workgroup; (ab|cd) is an MFMA tile in
+// (a, d) for each b, (ac|bd) + (ad|bc) an MFMA tile in (a, b) for each d, and
+// the first is transposed through LDS onto the second.
 template <typename T, bool ZMODE>
 __device__ __forceinline__ void bqp4_block(const BqpArgs& a, int item) {
   typedef typename V4<T>::type v4;
   constexpr int DB = 2;            // d values whose operands are loaded together
   __shared__ T t1s[16 * 16 * 17];  // (ab|cd) as [b][a][d]
-  const int4 it = a.items[item];
+  const int4 it = a.items4[item];
   const int c = it.x, d0 = it.y, a0 = it.z, b0 = it.w;
   const int q = a.q, pw = a.pw, nkc = a.nkc;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
@@ -1666,6 +1683,186 @@ __device__ __forceinline__ void bqp4_block(const BqpArgs& a, int item) {
   }
 }
 
+// pass 1: (ab|cd) for the 16 pairs {c, d}, c = c0 .. c0 + 15 (A operand rows,
+// loaded once per chunk), against the pair rows t = t0 .. t0 + 63 (four B
+// operand tiles); one wave per item
+template <typename T, bool ZMODE>
+__device__ __forceinline__ void bqp1_item(const BqpArgs& a, int4 it, int lane) {
+  typedef typename V4<T>::type v4;
+  const int q = a.q, pw = a.pw, li = lane & 15, lk = lane >> 4;
+  const int d = it.x, c0 = it.y;
+  const long long t0 = it.z, npair = c2(q);
+  const T* Y = (const T*)a.Yp;
+  const T* U = (const T*)a.Up;
+  const int cl = c0 + li;
+  const size_t ra = (size_t)(cl < d ? prow(q, cl, d) : 0) * pw;
+  size_t rb[4];
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const long long tl = t0 + 16 * s4 + li;
+    rb[s4] = (size_t)(tl < npair ? 1 + q + tl : 0) * pw;
+  }
+  v4 acc[4];
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) acc[s4] = v4{0, 0, 0, 0};
+  for (int kc = 0; kc < a.nkc; ++kc) {
+    const int k0 = 16 * kc + 4 * lk;
+    const v4 ya = ld4(Y + ra + k0);
+    const v4 ua = ZMODE ? ld4(U + ra + k0) : ya;
+    v4 yb[4], ub[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      yb[s4] = ld4(Y + rb[s4] + k0);
+      ub[s4] = ZMODE ? ld4(U + rb[s4] + k0) : yb[s4];
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (ZMODE) {
+          acc[s4] = mfma(ya[e], ub[s4][e], acc[s4]);
+          acc[s4] = mfma(ua[e], yb[s4][e], acc[s4]);
+        } else {
+          acc[s4] = mfma(ya[e], yb[s4][e], acc[s4]);
+        }
+      }
+  }
+  T* p1 = (T*)a.p1;
+  const long long base_d = c4(d);
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const long long tl = t0 + 16 * s4 + li;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int cc = c0 + drow<T>(lk, v);
+      if (cc >= 2 && cc < d && tl < c2(cc)) p1[base_d + c3(cc) + tl] = acc[s4][v];
+    }
+  }
+}
+
+// pair index pi -> (A, B), A <= B, pi = B (B + 1) / 2 + A
+__device__ __forceinline__ void pair_of(int pi, int& A, int& B) {
+  B = (int)((sqrtf(8.0f * (float)pi + 1.0f) - 1.0f) * 0.5f);
+  while (B * (B + 1) / 2 > pi) --B;
+  while ((B + 1) * (B + 2) / 2 <= pi) ++B;
+  A = pi - B * (B + 1) / 2;
+}
+
+// pass 2: one workgroup per (c, d).  R >= 16 ceil(c / 16) staged rows per
+// array, chunks of KC = 4 W columns, NP 16-block pairs (A <= B) per wave and
+// pass; tiles (A, B) and (B, A) of M are accumulated together.
+template <typename T, bool ZMODE, int R, int W, int NP>
+__global__ __launch_bounds__(256) void k_bqp_pass2(BqpArgs a) {
+  typedef T vw __attribute__((ext_vector_type(W)));
+  typedef typename V4<T>::type v4;
+  constexpr int KC = 4 * W;
+  constexpr int STR = KC + 16 / (int)sizeof(T);  // padded LDS row (16 bytes of padding)
+  constexpr int NA = ZMODE ? 4 : 2;               // staged arrays Yc, Yd (, Uc, Ud)
+  constexpr int OPS = NA * R * STR;
+  constexpr int SCR = 4 * 2 * 16 * 17;            // per-wave transpose tiles
+  constexpr int UPR = KC * (int)sizeof(T) / 16;   // 16-byte units per staged row
+  __shared__ __align__(16) T lds[OPS > SCR ? OPS : SCR];
+  const int2 it = a.items2[blockIdx.x];
+  const int c = it.x, d = it.y, q = a.q, pw = a.pw;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int nT = (c + 15) >> 4, npair = nT * (nT + 1) / 2, nrow = 16 * nT;
+  const int nchunk = a.nkc * 16 / KC;
+  const T* Y = (const T*)a.Yp;
+  const T* U = (const T*)a.Up;
+  const size_t rowc = (size_t)prow(q, 0, c), rowd = (size_t)prow(q, 0, d);
+  T* Yc = lds;
+  T* Yd = lds + R * STR;
+  T* Uc = lds + 2 * R * STR;
+  T* Ud = lds + 3 * R * STR;
+  const T* p1 = (const T*)a.p1;
+  const long long base4 = c4(d) + c3(c);  // degree-4 local id of {a, b, c, d} minus C(b, 2) + a
+  for (int pass = 0; pass * 4 * NP < npair; ++pass) {
+    v4 acc[NP][2];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) acc[j][0] = acc[j][1] = v4{0, 0, 0, 0};
+    for (int ch = 0; ch < nchunk; ++ch) {
+      __syncthreads();
+      // staged rows x < c of the four arrays (zeros below 16 nT), 16-byte units
+      for (int u = tid; u < NA * nrow * UPR; u += 256) {
+        const int arr = u / (nrow * UPR), rem = u - arr * (nrow * UPR), x = rem / UPR, part = rem - x * UPR;
+        uint4 val = {0u, 0u, 0u, 0u};
+        if (x < c) {
+          const T* src = (arr < 2 ? Y : U) + ((arr & 1 ? rowd : rowc) + x) * pw + ch * KC;
+          val = ((const uint4*)src)[part];
+        }
+        ((uint4*)(lds + (size_t)arr * R * STR + x * STR))[part] = val;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        const int pi = pass * 4 * NP + j * 4 + w;
+        if (pi < npair) {
+          int A, B;
+          pair_of(pi, A, B);
+          const int oa = (16 * A + li) * STR + W * lk, ob = (16 * B + li) * STR + W * lk;
+          const vw yca = *(const vw*)(Yc + oa), ydb = *(const vw*)(Yd + ob);
+          const vw ycb = *(const vw*)(Yc + ob), yda = *(const vw*)(Yd + oa);
+          if (ZMODE) {
+            const vw uca = *(const vw*)(Uc + oa), udb = *(const vw*)(Ud + ob);
+            const vw ucb = *(const vw*)(Uc + ob), uda = *(const vw*)(Ud + oa);
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+              acc[j][0] = mfma(yca[e], udb[e], acc[j][0]);
+              acc[j][0] = mfma(uca[e], ydb[e], acc[j][0]);
+            }
+            if (A != B) {
+#pragma unroll
+              for (int e = 0; e < W; ++e) {
+                acc[j][1] = mfma(ycb[e], uda[e], acc[j][1]);
+                acc[j][1] = mfma(ucb[e], yda[e], acc[j][1]);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int e = 0; e < W; ++e) acc[j][0] = mfma(yca[e], ydb[e], acc[j][0]);
+            if (A != B) {
+#pragma unroll
+              for (int e = 0; e < W; ++e) acc[j][1] = mfma(ycb[e], yda[e], acc[j][1]);
+            }
+          }
+        }
+      }
+    }
+    // M[a][b] + M[b][a] through the wave's two 16 x 17 transpose tiles
+    __syncthreads();
+    T* S1 = lds + w * 2 * 16 * 17;
+    T* S2 = S1 + 16 * 17;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int pi = pass * 4 * NP + j * 4 + w;
+      int A = 0, B = 0;
+      if (pi < npair) {
+        pair_of(pi, A, B);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          S1[drow<T>(lk, v) * 17 + li] = acc[j][0][v];  // S1[a'][b'] = M[16 A + a'][16 B + b']
+          S2[drow<T>(lk, v) * 17 + li] = acc[j][1][v];  // S2[b'][a'] = M[16 B + b'][16 A + a']
+        }
+      }
+      __syncthreads();
+      if (pi < npair) {
+        const T* St = A != B ? S2 : S1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ao = li, bo = 4 * lk + v;
+          const int an = 16 * A + ao, bn = 16 * B + bo;
+          if (an < bn && bn < c) {
+            const T m2 = S1[ao * 17 + bo] + St[bo * 17 + ao];
+            const long long g4 = base4 + c2(bn) + an;
+            bqp_store<T, ZMODE>(a, a.off4 + g4, ((double)p1[g4] + (double)m2) * (1.0 / 3.0));
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // T[r][x] = B(row r, row x) for every basis row r and x in 0..q (row x is {}
 // for x = 0 and {x-1} otherwise); blocks with blockIdx.y = 0 also write the
 // partial sum of B(row r, row r) over their 16 rows (class {})
@@ -1742,16 +1939,22 @@ __device__ __forceinline__ void bqpStar_tile(const BqpArgs& a, int tile, int lg,
   }
 }
 
-// One launch for the whole structured class-sum pass before its finisher:
-// blocks [0, n4) take degree-4 items, the blocks after them give one T or star
-// tile to each of their four waves (those start as the degree-4 blocks drain).
+// Pass 1 and the degree 0-3 tables in one launch: blocks [0, nb1) give one
+// pass-1 item (of n1) to each wave, the blocks after them one T or star tile.
+// With single = 1 the first n1 blocks take single-pass degree-4 items instead.
 template <typename T, bool ZMODE>
-__global__ __launch_bounds__(256) void k_bqp_sums(BqpArgs a, int n, int n4, int nTx, int nTy, int nS) {
-  if ((int)blockIdx.x < n4) {
-    bqp4_block<T, ZMODE>(a, blockIdx.x);
+__global__ __launch_bounds__(256) void k_bqp_pass1(BqpArgs a, int n, int n1, int nTx, int nTy, int nS, int single) {
+  const int nb1 = single ? n1 : (n1 + 3) / 4;
+  if ((int)blockIdx.x < nb1) {
+    if (single) {
+      bqp4_block<T, ZMODE>(a, blockIdx.x);
+      return;
+    }
+    const int item = (int)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (item < n1) bqp1_item<T, ZMODE>(a, a.items[item], threadIdx.x & 63);
     return;
   }
-  const int task = ((int)blockIdx.x - n4) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int task = ((int)blockIdx.x - nb1) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int nT = nTx * nTy;
   if (task < nT)
     bqpT_tile<T, ZMODE>(a, n, task % nTx, task / nTx, lane);
@@ -1913,7 +2116,10 @@ static mdsdp_status launch_bqp(mdsdp_problem P, bool zmode, bool fp32, hipStream
   b.off4 = P->bqp_off[4];
   b.Yp = P->Yp;
   b.Up = P->Up;
-  b.items = P->bqp4_items;
+  b.items4 = P->bqp4_items;
+  b.items = P->bqp1_items;
+  b.items2 = P->bqp2_items;
+  b.p1 = P->bqpP1;
   b.T = P->bqpT;
   b.star = P->bqpStar;
   b.dst = zmode ? (double*)P->ab64 + 1 : (double*)P->cy + 1;
@@ -1926,13 +2132,32 @@ static mdsdp_status launch_bqp(mdsdp_problem P, bool zmode, bool fp32, hipStream
   const unsigned nqt = (unsigned)((q + 15) / 16), ntile = nqt * (nqt + 1) / 2;
   const int nS = (int)ntile;
   const long long ntask = (long long)nblkT * ncolT + (long long)nS * STAR_LG;
-  const unsigned nsum = (unsigned)P->bqp4_n + (unsigned)((ntask + 3) / 4);
+  // narrow factors (one or two 16-column chunks): the single-pass kernel
+  const bool single = b.nkc <= 2;
+  const int n1 = single ? P->bqp4_n : P->bqp1_n;
+  const unsigned nsum = (unsigned)(single ? n1 : (n1 + 3) / 4) + (unsigned)((ntask + 3) / 4);
+  const int rneed = 16 * ((std::max(q - 2, 1) + 15) / 16);  // rows {x, c}, x < c <= q - 2
   const int nb01 = (q + 1 + 3) / 4;
   const unsigned nfin = (unsigned)nb01 + blocks_for(b.off4 - b.off2, 256);
+#define PASS2(TT, ZZ, RR, WW, NPP) k_bqp_pass2<TT, ZZ, RR, WW, NPP><<<P->bqp2_n, 256, 0, s>>>(b)
+#define PASS2_R(TT, ZZ, NP32, NP64)                                                                         \
+  do {                                                                                                      \
+    if (P->bqp2_n > 0) {                                                                                    \
+      if (rneed <= 64)                                                                                      \
+        PASS2(TT, ZZ, 64, 4, (sizeof(TT) == 4 ? NP32 : NP64));                                              \
+      else if (rneed <= 128)                                                                                \
+        PASS2(TT, ZZ, 128, 4, (sizeof(TT) == 4 ? NP32 : NP64));                                             \
+      else if (rneed <= 256)                                                                                \
+        PASS2(TT, ZZ, 256, (sizeof(TT) == 4 ? 4 : 2), (sizeof(TT) == 4 ? NP32 : NP64));                     \
+      else                                                                                                  \
+        PASS2(TT, ZZ, 368, (sizeof(TT) == 4 ? 4 : 2), (sizeof(TT) == 4 ? NP32 : NP64));                     \
+    }                                                                                                       \
+  } while (0)
 #define BQP_LAUNCH(TT, ZZ)                                                                                  \
   do {                                                                                                      \
     timer_begin(P, s, "bqp_sums");                                                                          \
-    k_bqp_sums<TT, ZZ><<<nsum, 256, 0, s>>>(b, n, P->bqp4_n, (int)nblkT, (int)ncolT, nS);                   \
+    k_bqp_pass1<TT, ZZ><<<nsum, 256, 0, s>>>(b, n, n1, (int)nblkT, (int)ncolT, nS, single ? 1 : 0);        \
+    if (!single) PASS2_R(TT, ZZ, 7, 4);                                                                     \
     timer_end(P, s);                                                                                        \
     timer_begin(P, s, "bqp_fin");                                                                           \
     k_bqpFin<TT, ZZ><<<nfin, 256, 0, s>>>(b, n, (int)nblkT, nb01);                                          \
@@ -1945,6 +2170,8 @@ static mdsdp_status launch_bqp(mdsdp_problem P, bool zmode, bool fp32, hipStream
   else
     BQP_LAUNCH(double, true);
 #undef BQP_LAUNCH
+#undef PASS2_R
+#undef PASS2
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }

@@ -103,8 +103,13 @@ struct mdsdp_problem_s {
   // structured BQP path (colex basis and class order), q = 0 when generic
   int bqp_q = 0;
   long long bqp_off[6] = {0, 0, 0, 0, 0, 0};
-  int4* bqp4_items = nullptr;   // (c, d0, a0, b0) work items of the degree-4 pass
+  int4* bqp4_items = nullptr;   // (c, d0, a0, b0) work items of the single-pass degree-4 kernel
   int bqp4_n = 0;
+  int4* bqp1_items = nullptr;   // (d, c0, t0, 0) work items of degree-4 pass 1
+  int bqp1_n = 0;
+  int2* bqp2_items = nullptr;   // (c, d) work items of degree-4 pass 2
+  int bqp2_n = 0;
+  double* bqpP1 = nullptr;      // C(q, 4) pass-1 results
   double* bqpT = nullptr;       // n x (q + 1) table of the degree 0..3 pass
   double* bqpStar = nullptr;    // STAR_LG x q x q partials of the degree-2 contraction
   // staging / workspace
