@@ -2420,11 +2420,12 @@ mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* 
     MDSDP_HIP(hipGetLastError());
     return MDSDP_OK;
   }
-  // row blocks: about 16 rows each (short dependent load/MFMA chains), within
-  // the partial buffer
+  // row blocks: short dependent load/MFMA chains per wave, at most 256
+  // partials per Gram element for the final sum, within the partial buffer
   const GramSplit GS(gpw);
   const int nblk = (int)std::max<size_t>(
-      1, std::min<size_t>({(size_t)256, (size_t)(P->n + 15) / 16, GRAM_PART_MAX / ((size_t)GS.RS * 2 * gpw * gpw)}));
+      1, std::min<size_t>({(size_t)(256 / GS.RS), (size_t)(P->n + 15) / 16,
+                           GRAM_PART_MAX / ((size_t)GS.RS * 2 * gpw * gpw)}));
   timer_begin(P, s, "gram");
   P->gram_pw = gpw;
   const int len = 2 * gpw * gpw, e0 = with_yy ? 0 : gpw * gpw;

@@ -192,11 +192,15 @@ def test_nonzero_C_parity():
     assert _rel(H.cpu().numpy(), sub.rhess(Y, U)) <= 1e-10
 
 
-@pytest.mark.parametrize("q,p", [(4, 3), (9, 16), (25, 5), (9, 29), (25, 64), (9, 128)])
+@pytest.mark.parametrize("q,p", [(4, 3), (9, 16), (25, 5), (9, 29), (25, 64), (9, 128),
+                                 (4, 33), (5, 48), (18, 33), (34, 40), (17, 32)])
 def test_structured_matches_generic_class_sums(q, p):
     """The class-map-free BQP kernels and the generic fixed-point class map
     path give the same class averages (both are within rounding of the
-    oracle); HVP class averages compared through the HVP output."""
+    oracle); HVP class averages compared through the HVP output.  Widths up
+    to 32 take the single-pass degree-4 kernel, wider ones the two passes;
+    q = 4, 5 have one and five degree-4 classes, q = 17, 18, 34 put c on
+    either side of a 16-row block boundary."""
     from paper_2512_04406_amd.problem import FP64, ORDER_COLEX, Problem
 
     Q, c = bqp_instance(q, 8)
