@@ -13,7 +13,7 @@ Steps per outer iteration k (Algorithm alg1, section "The ManiDSDP algorithm"):
 and the KKT residuals eta_p, eta_d, eta_g of eq. res with the stop at
 eta_max <= tol.
 
-Readings of points the paper leaves open (each also listed in the design doc):
+Readings of points the paper leaves open:
 * Y^0: the paper writes the zero matrix, which is not on the manifold; we take
   the given row-normalised Gaussian start.
 * "supplied with the carried direction": from Yhat = [Y, 0] we backtrack
