@@ -90,6 +90,29 @@ def test_solve_q10_matches_brute_force(seed, prec):
     assert abs(res.value - orc.value) <= 1e-8 * (1 + abs(orc.value))
 
 
+@pytest.mark.parametrize("maxinner", [2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_with_short_truncated_cg(maxinner, prec):
+    """Truncated CG capped at 2 or 3 steps: most inner solves end at the cap,
+    on either of the pipelined loop's two iterate buffers, and the result
+    must still be the brute-force optimum."""
+    from paper_2512_04406_amd.problem import ORDER_COLEX, Problem
+
+    Q, c = bqp_instance(10, 4)
+    prob = Problem.bqp(Q, c, ORDER_COLEX)
+    opts = prob.default_options()
+    opts.tol = 1e-8
+    opts.hvp_prec = prec
+    opts.tcg_maxinner = maxinner
+    print(f"[solve] q=10 seed=4 prec={prec} tcg_maxinner={maxinner}", flush=True)
+    res = prob.solve(_t(gaussian(prob.n, 2, 104)), opts)
+    print(f"   value={res.value:.10f} eta={res.eta} outer={res.outer_iters} hvps={res.hvps}", flush=True)
+    fmin, _ = brute.brute_force_min(Q, c)
+    assert res.status == 0
+    assert max(res.eta) <= 1e-8
+    assert abs(res.value - fmin) <= 1e-8 * (1 + abs(fmin))
+
+
 def test_solve_q20_fp64_and_mixed_agree_with_brute_force():
     Q, c, r64 = _solve(20, 0, 0)
     _, _, r32 = _solve(20, 0, 1)
