@@ -208,7 +208,9 @@ typedef struct {
 typedef struct {
   int32_t status;       /* mdsdp_status of the solve */
   int32_t outer_iters;
-  int64_t rtr_iters, hvps, cost_grads, eig_iters;
+  int64_t rtr_iters, hvps, cost_grads, eig_iters;  /* hvps: HVPs whose result the solver used (the one
+                                                      speculative HVP a truncated-CG stop discards is
+                                                      not counted; its time is) */
   int32_t p_final, p_max_reached;
   double value;         /* b^T y */
   double eta_p, eta_d, eta_g;

@@ -336,7 +336,7 @@ mdsdp_status tcg(mdsdp_problem P, int p, const double* Y, const double* g, doubl
   //   <d, Hd> <= 0 or ||eta_j + alpha d_j|| >= Delta -> stop on the boundary,
   // tracking <eta, eta>, <eta, d>, <d, d> by their recurrences.  When it stops
   // at step j the work already enqueued for step j + 1 went into the other
-  // buffer and is discarded (one HVP).
+  // buffer and is discarded; that HVP is not counted.
   const int n = P->n;
   const long long len = (long long)n * p;
   const double kappa = 0.1, theta = 1.0;
@@ -382,6 +382,7 @@ mdsdp_status tcg(mdsdp_problem P, int p, const double* Y, const double* g, doubl
     if (j > 0) {
       if (sqrt(rr_j) <= tol) {
         C.t_hvp += secs(t0, clk::now());
+        if (j + 1 < maxinner) C.hvps--;  // the discarded speculative HVP
         *stop = TCG_CONV;
         return finish(cur);
       }
@@ -397,6 +398,7 @@ mdsdp_status tcg(mdsdp_problem P, int p, const double* Y, const double* g, doubl
       CHK(vec_lincomb(len, tau, it[cur].d, 1.0, it[cur].eta, it[0].eta, s));
       CHK(vec_lincomb(len, tau, it[cur].Hd, 1.0, it[cur].Heta, it[0].Heta, s));
       C.t_hvp += secs(t0, clk::now());
+      if (j + 1 < maxinner) C.hvps--;  // the discarded speculative HVP
       *stop = dHd <= 0.0 ? TCG_NEG : TCG_BOUND;
       return MDSDP_OK;
     }
