@@ -22,7 +22,8 @@
 //  * carried direction: backtracking t = sqrt(n), sqrt(n)/2, ... along
 //    R_[Y,0](t [0, v]) until Psi_k decreases, then RTR;
 //  * rank rule: drop singular directions of Y below tau_rank * s_1, then add
-//    one zero column for the negative eigenvector (p <= p_max);
+//    one zero column per carried negative eigenvector (at most n_neg per
+//    outer step, p <= p_max);
 //  * sigma rule eq. sec5:eq1 with ||R|| = ||Q(Z)||_F and the final ||grad||.
 #include <math.h>
 #include <string.h>
