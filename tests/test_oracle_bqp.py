@@ -5,7 +5,9 @@
   and class ids come from sorting all subsets of size <= 4 by (size, colex);
 * class count == eq. bqp-number-moments, moment count == eq.
   bqp-moment-number-constraints (golden file from the printed formulas);
-* class sizes per degree; b reproduces f(x) on every sign vector.
+* class sizes per degree; b reproduces f(x) on every sign vector;
+* the class sums of a symmetric bilinear form of basis rows, per class degree,
+  equal the pairing sums that the structured GPU class-sum kernels evaluate.
 """
 
 import itertools
@@ -115,3 +117,58 @@ def test_orders_are_a_permutation():
     # colex lists pairs by larger index first
     pairs = colex[1 + q:]
     assert np.all(np.diff(pairs[:, 1]) >= 0)
+
+
+@pytest.mark.parametrize("q", [4, 6, 9])
+def test_class_sums_by_pairings(q):
+    """The identities the structured class-sum kernels evaluate, checked
+    against the oracle's class map: for a symmetric bilinear form
+    B(r, s) = y_r . u_s + u_r . y_s of two basis rows (colex basis; rows
+    indexed by index sets of size <= 2), the ordered class sum over the
+    entries (r, s) with r ^ s = gamma equals
+      {}         : sum_r B(r, r)
+      {i}        : 2 [B({}, {i}) + sum_{j != i} B({j}, {i, j})]
+      {i<j}      : 2 [B({}, {i,j}) + B({i}, {j}) + sum_{l != i,j} B({i,l}, {j,l})]
+      {a<b<c}    : 2 [B({a}, {b,c}) + B({b}, {a,c}) + B({c}, {a,b})]
+      {a<b<c<d}  : 2 [B({a,b}, {c,d}) + B({a,c}, {b,d}) + B({a,d}, {b,c})]."""
+    rng = np.random.default_rng(q)
+    rows = bqp.basis(q, "colex")
+    n = rows.shape[0]
+    mons = []
+    for r in range(n):
+        mons.append(frozenset(int(v) for v in rows[r] if v >= 0))
+    row_of = {s: r for r, s in enumerate(mons)}
+    p = 3
+    Y = rng.standard_normal((n, p))
+    U = rng.standard_normal((n, p))
+    Bm = Y @ U.T + U @ Y.T
+
+    def B(s1, s2):
+        return Bm[row_of[frozenset(s1)], row_of[frozenset(s2)]]
+
+    cls = bqp.class_map_full(q, "colex")
+    m = int(cls.max()) + 1
+    sums = np.zeros(m)
+    np.add.at(sums, cls.ravel(), Bm.ravel())
+    off = bqp.class_offsets(q)
+    subsets = [frozenset(s) for d in range(5) for s in itertools.combinations(range(q), d)]
+    subsets.sort(key=lambda s: (len(s), sorted(s, reverse=True)))
+    assert len(subsets) == m
+    for g, s in enumerate(subsets):
+        e = sorted(s)
+        if len(e) == 0:
+            ref = float(np.trace(Bm))
+        elif len(e) == 1:
+            i = e[0]
+            ref = 2 * (B((), (i,)) + sum(B((j,), (i, j)) for j in range(q) if j != i))
+        elif len(e) == 2:
+            i, j = e
+            ref = 2 * (B((), (i, j)) + B((i,), (j,)) + sum(B((i, l), (j, l)) for l in range(q) if l not in (i, j)))
+        elif len(e) == 3:
+            a, b, c = e
+            ref = 2 * (B((a,), (b, c)) + B((b,), (a, c)) + B((c,), (a, b)))
+        else:
+            a, b, c, d = e
+            ref = 2 * (B((a, b), (c, d)) + B((a, c), (b, d)) + B((a, d), (b, c)))
+        assert abs(sums[g] - ref) <= 1e-12 * (1 + abs(ref)), (g, e)
+    assert off[-1] == m
