@@ -16,7 +16,8 @@ at a fixed point (FP32 tiles and FP64); the roofline of the dominant kernel,
 the HVP product pass (its average launch time from HIP events around 100
 back-to-back launches on its stream; the HBM traffic from the committed
 rocprofv3 counter summary when it matches the current kernel sources); the
-isolated HVP rates of the q = 40 and sparse-Q q = 120 instances; capped full
+isolated HVP rates of the q = 40 and sparse-Q q = 120 instances, with a full
+solve of the q = 40 instance to eta_max <= 1e-8 in both precisions; capped full
 solves to eta_max <= 1e-8 in mixed precision and in FP64; and the FP64 oracle
 timed on the host CPU on a bounded sample.
 
@@ -154,15 +155,18 @@ def main() -> int:
     hvp_prec = FP32 if args.prec == "mixed" else FP64
     print(f"[bench] q={q} n={n} m={m} p={p} prec={args.prec}", file=sys.stderr, flush=True)
 
-    def kkt_solves(which, cap):
-        """Full solves from Y0 (rank p0 = p) to eta_max <= 1e-8, capped at
-        `cap` seconds each, with FP32-tile HVPs (mixed) and FP64 HVPs."""
-        Y0k = torch.from_numpy(gaussian(n, p, 100 + args.seed)).to(dev)
+    def kkt_solves(which, cap, pr=None, p0=None):
+        """Full solves from Y0 (rank p0, default p) to eta_max <= 1e-8, capped
+        at `cap` seconds each, with FP32-tile HVPs (mixed) and FP64 HVPs, on
+        problem `pr` (default: the benchmark instance)."""
+        pr = pr or prob
+        p0 = p0 or p
+        Y0k = torch.from_numpy(gaussian(pr.n, p0, 100 + args.seed)).to(dev)
         res = {}
         for name, prec in (("mixed", FP32), ("fp64", FP64)):
             if name not in which:
                 continue
-            o = prob.default_options()
+            o = pr.default_options()
             o.hvp_prec = prec
             o.time_limit_s = cap
             o.verbose = 1 if args.verbose else 0
@@ -170,7 +174,7 @@ def main() -> int:
                 o.p_max = args.p_max
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = prob.solve(Y0k, o)
+            r = pr.solve(Y0k, o)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             res[name] = {"converged": r.status == 0, "seconds": dt, "eta": list(r.eta), "eta_max": max(r.eta),
@@ -274,6 +278,9 @@ def main() -> int:
                 torch.cuda.synchronize()
                 rates[pname + "_hvp_per_s"] = 50 / (time.perf_counter() - t0)
             other[label] = {"n": po_prob.n, "m": po_prob.m, **rates}
+            if label.startswith("dense q=40"):
+                # a converged time to KKT <= 1e-8 on the small dense instance (p0 = 4)
+                other[label]["time_to_kkt"] = kkt_solves(("mixed", "fp64"), 120.0, pr=po_prob, p0=po)
             po_prob.close()
         print(f"[bench] other configs: {other}", file=sys.stderr, flush=True)
 
