@@ -24,18 +24,29 @@ Readings of points the paper leaves open:
   after each subproblem, drop singular directions of Y below tau_rank * s_1
   (Y <- Y V_r, rows renormalised), then append one zero column per carried
   eigenvector (at most n_neg of them, p <= p_max).
-* inner tolerance: RTR stops at ||grad|| <= max(gtol_min, min(gtol0, 0.1 eta_max^k,
-  gtol_decay * previous tolerance, gtol_ratio ||R^k|| / (1 + ||b||))); the decay keeps
-  the tolerances of an inexact ALM going to zero when the residuals stall, the
-  ratio term ties the tolerance to the primal measure of the sigma rule, and
-  whenever RTR starts below its tolerance (takes no step) every later tolerance
-  is capped at gtol_stall * ||grad|| (otherwise the multiplier update alone
-  repeats without moving Y).
+* inner tolerance: RTR for subproblem k stops at ||grad|| <= gtol_k with
+  gtol_k = max(gtol_min, min(gtol0, gtol_ratio ||R^k|| / (1 + ||b||))), i.e. the
+  subproblem is solved to a fixed fraction of the same scaled primal residual
+  that eq. sec5:eq1 weighs against ||grad||; for k = 0 (no R yet) gtol0.  Then
+  the two sides of eq. sec5:eq1 are measured on one scale, and the rule
+  raises sigma when an outer step leaves the primal residual about where it
+  was and lowers it when RTR stops short of its tolerance.  (With
+  gtol_ratio <= 0 the older form min(gtol0, 0.1 eta_max^k, gtol_decay * previous)
+  is used; there ||grad|| scales with eta_p while the rule divides ||R|| by
+  1 + ||b||, so the decrease branch fires whenever 1 + ||b|| is large.)
+  Optional stall cap: whenever RTR starts below its tolerance (takes no
+  step) every later tolerance is capped at gtol_stall * ||grad|| (off by
+  default).
 * sigma constants: sigma_0 = 1, sigma_min = 1e-3, sigma_max = 1e6, gamma = 2,
-  kappa_1 = 0.1, kappa_2 = 10 (the paper states none); with sigma_hold the
-  decrease branch of eq. sec5:eq1 is skipped after an RTR call that stopped at
-  its iteration cap (its gradient norm then measures the unfinished
-  subproblem rather than a dual residual).
+  kappa_1 = 0.1, kappa_2 = 10 (the paper states none); eq. sec5:eq1 is applied
+  as printed after every outer step.  Option sigma_hold (off by default)
+  skips its decrease branch after an RTR call that stopped at its iteration
+  cap.
+* carried direction (step 9): the paper introduces the direction of Theorem
+  sec5:thm1 to escape stationary points whose certificate is not PSD; with
+  escape_when_solved (default) it is formed, and the zero columns added, only
+  after an RTR call that reached its tolerance -- an unfinished subproblem is
+  not such a point, and RTR continues from it along the gradient.
 * eigenvector sign: the largest-magnitude component is made positive.
 
 Parity: not pinned on iterates; the result is pinned by brute force (q <= 16,
@@ -67,15 +78,16 @@ class ALMOptions:
     gamma: float = 2.0
     kappa1: float = 0.1
     kappa2: float = 10.0
-    p_max: int = 64
-    n_neg: int = 4
+    p_max: int = 512
+    n_neg: int = 16
     tau_rank: float = 1e-4
     gtol0: float = 1e-2
     gtol_min: float = 1e-10
     gtol_decay: float = 1.0
-    gtol_ratio: float = 0.0
-    gtol_stall: float = 0.1
-    sigma_hold: bool = True
+    gtol_ratio: float = 0.1
+    gtol_stall: float = 0.0
+    sigma_hold: bool = False
+    escape_when_solved: bool = True
     rtr_maxiter: int = 50
     neg_tol: float = 1e-12
 
@@ -147,9 +159,10 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
         sub = Subproblem(cls, counts, b, Xt, sigma, C)
         if U is not None:
             Y = _escape(sub, Y, U)
-        g = min(opts.gtol0, 0.1 * eta_max, opts.gtol_decay * gtol)
-        if opts.gtol_ratio > 0.0 and prim_ratio is not None:
-            g = min(g, opts.gtol_ratio * prim_ratio)
+        if opts.gtol_ratio > 0.0:
+            g = opts.gtol0 if prim_ratio is None else min(opts.gtol0, opts.gtol_ratio * prim_ratio)
+        else:
+            g = min(opts.gtol0, 0.1 * eta_max, opts.gtol_decay * gtol)
         gtol = max(opts.gtol_min, min(g, stall_cap))
         res = rtr(sub, Y, gtol, maxiter=opts.rtr_maxiter)
         if opts.gtol_stall > 0.0 and res.iters == 0 and res.gradnorm > 0.0:
@@ -171,8 +184,11 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
                          lmin=lmin, lmax=lmax))
         if eta_max <= opts.tol:
             break
+        unsolved = res.gradnorm > gtol  # RTR stopped at its iteration cap
         # negative-curvature directions (Theorem sec5:thm1)
         neg = np.nonzero(evals < -opts.neg_tol * (1.0 + abs(lmax)))[0][: opts.n_neg]
+        if opts.escape_when_solved and unsolved:
+            neg = neg[:0]
         V = evecs[:, neg]
         for j in range(V.shape[1]):
             i = int(np.argmax(np.abs(V[:, j])))
@@ -193,7 +209,6 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
         # sigma rule, eq. sec5:eq1
         ratio = float(np.linalg.norm(Rq)) / (1.0 + normb)
         prim_ratio = ratio
-        unsolved = res.gradnorm > gtol  # RTR stopped at its iteration cap
         if ratio < opts.kappa1 * res.gradnorm and not (opts.sigma_hold and unsolved):
             sigma = max(sigma / opts.gamma, opts.sigma_min)
         elif ratio > opts.kappa2 * res.gradnorm:
