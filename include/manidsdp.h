@@ -108,10 +108,16 @@ mdsdp_status mdsdp_create_classmap(int32_t n, int64_t m, const int32_t* cls_host
  * the generic class-map path to rounding.  Errors as mdsdp_create_classmap. */
 mdsdp_status mdsdp_create_bqp(int32_t q, int32_t order, const double* Q_host, const double* c_host,
                               mdsdp_problem* out);
-/* Sparse A given as a list of (class, row, col, value) with row <= col; values
- * must all be 1 (0/1 indicators) and every (row, col) of the upper triangle
- * must be covered exactly once (disjoint supports; AA* diagonal).  Overlaps:
- * ENOTORTH; uncovered entries or non-unit values: EUNSUPPORTED. */
+/* Sparse A given as a list of (class, row, col, value) with row <= col: the
+ * entry (row, col) and its mirror have coefficient `value` in A_class.  Values
+ * must be +1 or -1 (signed unit coefficients, as in the real embedding of a
+ * Hermitian moment matrix, whose imaginary parts appear with opposite signs in
+ * the two off-diagonal blocks); supports must be pairwise disjoint, so that
+ * AA* = Diag(sum of squared coefficients per class) (remarks after Algorithm
+ * alg1).  An entry no triplet covers belongs to no class: A*(y) is zero there,
+ * so the constraint S = A*(y) - C fixes S_e = -C_e.  Overlaps: ENOTORTH; other
+ * values: EUNSUPPORTED; non-finite values: ENONFINITE; a class with no entry:
+ * EINVAL.  All checked on the host before any device work. */
 mdsdp_status mdsdp_create_sparse_A(int32_t n, int64_t m, int64_t nnz, const int32_t* cls_host,
                                    const int32_t* row_host, const int32_t* col_host,
                                    const double* val_host, const double* b_host,
@@ -122,12 +128,22 @@ mdsdp_status mdsdp_problem_info(mdsdp_problem prob, int32_t* n, int64_t* m, int6
 
 /* ---- multiplier and penalty ------------------------------------------------
  * set: Xt_dev = dense symmetric n x n row-major FP64 device matrix, or NULL for
- * Xt = 0.  Writing the subproblem residual as Q(S + C) - lambda/sigma, the
+ * Xt = 0; it clears the non-finite flag (mdsdp_sync_status).  Writing the subproblem residual as Q(S + C) - lambda/sigma, the
  * multiplier lambda is -Xt.  get: writes the same layout. */
 mdsdp_status mdsdp_set_multiplier(mdsdp_problem prob, const double* Xt_dev, double sigma,
                                   void* stream);
 mdsdp_status mdsdp_get_multiplier(mdsdp_problem prob, double* Xt_dev, void* stream);
 mdsdp_status mdsdp_set_sigma(mdsdp_problem prob, double sigma);
+
+/* ---- device status (non-finite guard) --------------------------------------
+ * Kernels raise a sticky flag in device memory when they meet a non-finite
+ * value: the multiplier given to mdsdp_set_multiplier, the cost, an HVP
+ * output, or ||Q(Z)|| / sum z in the multiplier update.  mdsdp_set_multiplier
+ * clears it (a new multiplier starts a new state).  sync_status synchronises
+ * `stream` and returns MDSDP_ENONFINITE if the flag is raised, else MDSDP_OK.
+ * Host inputs (b, C, Q, c) are checked when a problem is created:
+ * MDSDP_ENONFINITE before any device work. */
+mdsdp_status mdsdp_sync_status(mdsdp_problem prob, void* stream);
 
 /* ---- subproblem evaluation -------------------------------------------------
  * cost_grad at Y (dev, n x p): f_dev (1 double, nullable), egrad_dev and
@@ -164,14 +180,30 @@ mdsdp_status mdsdp_update_multiplier(mdsdp_problem prob, int32_t p, const double
  * k <= 512), with z from the last update_multiplier.  FP64. */
 mdsdp_status mdsdp_certificate_matvec(mdsdp_problem prob, int32_t k, const double* V_dev,
                                       double* XV_dev, void* stream);
-/* Smallest eigenpair and largest eigenvalue of X = Xt + D - Diag(z) by
- * Lanczos with full reorthogonalisation (eq. res, step 9 of Algorithm alg1).
- * Synchronous.  evec_dev: n doubles (nullable).  Stops when the residual of
- * the smallest Ritz pair is <= tol (1 + |lambda_max|) or after maxit steps
- * (then returns MDSDP_ENOCONV with the best estimate written). */
-mdsdp_status mdsdp_min_eigpair(mdsdp_problem prob, double tol, int32_t maxit, uint64_t seed,
-                               double* lambda_min, double* lambda_max, double* evec_dev,
+/* The k smallest eigenpairs and the largest eigenvalue of the certificate
+ * X = Xt + D - Diag(z) (eq. res; step 9 of Algorithm alg1, where the
+ * eigenvectors of negative eigenvalues form the direction of Theorem
+ * sec5:thm1), by Lanczos with full reorthogonalisation.  Synchronous.
+ * evals_host: k doubles, ascending; lambda_max_host: 1 double; evecs_dev
+ * (nullable): n*k doubles, eigenvector i at offset i*n (unit norm).  Stops when
+ * the residuals ||X v_i - theta_i v_i|| of all k smallest Ritz pairs are
+ * <= tol (1 + |lambda_max|), or after maxit steps: then MDSDP_ENOCONV with the
+ * best estimates written.  EINVAL: k < 1, k > n, maxit < k + 2, tol <= 0. */
+mdsdp_status mdsdp_min_eigpair(mdsdp_problem prob, int32_t k, double tol, int32_t maxit, uint64_t seed,
+                               double* evals_host, double* lambda_max_host, double* evecs_dev,
                                int32_t* iters, void* stream);
+/* The certificate spectrum estimate the solver uses for eta_d (eq. res):
+ * Lanczos from `warm_dev` (n doubles, nullable: a random start) plus a small
+ * random component, stopping when the error estimate of theta_min -- its
+ * residual, or residual^2 / gap when the gap theta_2 - residual_2 - theta_min
+ * is positive -- is <= tol (1 + |theta_max|), or after maxit steps.
+ * out_host[4] = {theta_min, theta_max, error estimate, converged (0/1)};
+ * evec_dev (nullable, n doubles) receives the Ritz vector of theta_min.  The
+ * solver takes max(0, -(theta_min - error)) / (1 + |theta_max|) for eta_d
+ * when the run did not converge.  Synchronous; MDSDP_OK either way. */
+mdsdp_status mdsdp_certificate_estimate(mdsdp_problem prob, double tol, int32_t maxit, uint64_t seed,
+                                        const double* warm_dev, double* out_host, double* evec_dev,
+                                        int32_t* iters, void* stream);
 /* Adjoint of the optimal value w.r.t. C: dv/dC = X + Diag z = Xt + D
  * (Lagrangian duality, dual problem PSDP).  Writes a dense n x n FP64 device
  * matrix. */
@@ -185,13 +217,16 @@ typedef struct {
   int32_t p_max;       /* largest factor width, 1..512 (default 512) */
   int32_t n_neg;       /* negative-curvature directions added per outer step (Theorem sec5:thm1) */
   double tau_rank;     /* drop singular directions below tau_rank * s_1 */
-  double gtol0, gtol_min;  /* inner tolerance max(gtol_min, min(gtol0, 0.1 eta, gtol_decay * previous)) */
-  double gtol_decay;   /* in (0, 1]; 1 = tolerance follows eta alone */
-  double gtol_ratio;   /* > 0: also cap the tolerance at gtol_ratio ||R|| / (1 + ||b||), the primal
-                          measure of the sigma rule (eq. sec5:eq1); <= 0: no such cap */
+  double gtol0, gtol_min;  /* inner tolerance of subproblem k (see gtol_ratio); default 1e-2, 1e-10 */
+  double gtol_decay;   /* in (0, 1]; used only when gtol_ratio <= 0 */
+  double gtol_ratio;   /* > 0 (default 0.1): RTR for subproblem k stops at
+                          ||grad|| <= max(gtol_min, min(gtol0, gtol_ratio ||R^k|| / (1 + ||b||))), the
+                          scaled primal residual that eq. sec5:eq1 weighs against ||grad|| (gtol0 at
+                          k = 0); <= 0: max(gtol_min, min(gtol0, 0.1 eta_max, gtol_decay * previous)) */
   double gtol_stall;   /* > 0: when an RTR call starts below its tolerance (takes no step), cap all
-                          later tolerances at gtol_stall * ||grad||; default 0.1; <= 0: off */
-  int32_t sigma_hold;  /* 1: do not decrease sigma after an RTR call that stopped at rtr_maxiter */
+                          later tolerances at gtol_stall * ||grad||; default 0 (off) */
+  int32_t sigma_hold;  /* 1: do not decrease sigma after an RTR call that stopped at rtr_maxiter;
+                          default 0 (eq. sec5:eq1 as printed) */
   int32_t rtr_maxiter, tcg_maxinner;
   int32_t hvp_prec;    /* mdsdp_prec for tCG HVPs */
   int32_t polish_fp64; /* switch HVPs to FP64 once eta_max < polish_eta */
@@ -203,6 +238,10 @@ typedef struct {
   uint64_t seed;
   int32_t resume;      /* 0: start from Xt = 0, sigma = sigma0; 1: continue from the problem's current
                           multiplier Xt with sigma = sigma0 (e.g. the sigma a previous solve returned) */
+  int32_t escape_when_solved; /* 1 (default): form the carried direction of Theorem sec5:thm1 and add
+                          its zero columns only after an RTR call that reached its tolerance (the
+                          direction escapes stationary points whose certificate is not PSD); 0: after
+                          every outer step */
 } mdsdp_options;
 
 typedef struct {

@@ -105,11 +105,11 @@ class ALMResult:
     history: list = field(default_factory=list)
 
 
-def kkt_residuals(S, y, X, z, b, cls, C=None):
+def kkt_residuals(S, y, X, z, b, cls, C=None, w=None):
     """eq. res: eta_p, eta_d, eta_g (Frobenius norms; eigenvalues by LAPACK)."""
     n = S.shape[0]
     Cm = np.zeros((n, n)) if C is None else C
-    R = A_adj(y, cls) - S - Cm
+    R = A_adj(y, cls, w) - S - Cm
     eta_p = float(np.linalg.norm(R) / (1.0 + np.linalg.norm(Cm)))
     ev = np.linalg.eigvalsh(X)
     eta_d = float(max(0.0, -ev[0]) / (1.0 + abs(ev[-1])))
@@ -139,13 +139,14 @@ def rank_one_rounding(Y: np.ndarray, Q: np.ndarray, c: np.ndarray, order_basis: 
 
 
 def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
-          opts: ALMOptions | None = None, C: np.ndarray | None = None) -> ALMResult:
+          opts: ALMOptions | None = None, C: np.ndarray | None = None,
+          w: np.ndarray | None = None) -> ALMResult:
     opts = opts or ALMOptions()
     n = cls.shape[0]
     Xt = np.zeros((n, n))
     sigma = opts.sigma0
     Y = Y0 / np.linalg.norm(Y0, axis=1, keepdims=True)
-    D = D_matrix(b, cls, counts)
+    D = D_matrix(b, cls, counts, w)
     U = None
     eta_max = 1.0
     gtol = opts.gtol0 / opts.gtol_decay
@@ -156,7 +157,7 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
     y = z = X = None
     eta = (np.inf, np.inf, np.inf)
     for k in range(opts.max_outer):
-        sub = Subproblem(cls, counts, b, Xt, sigma, C)
+        sub = Subproblem(cls, counts, b, Xt, sigma, C, w)
         if U is not None:
             Y = _escape(sub, Y, U)
         if opts.gtol_ratio > 0.0:
@@ -170,14 +171,14 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
         Y = res.Y
         S = Y @ Y.T
         Z = S if C is None else S + C
-        y = class_average(Z, cls, counts)
-        Rq = Q_op(Z, cls, counts)  # = -(A* y - S - C)
+        y = class_average(Z, cls, counts, w)
+        Rq = Q_op(Z, cls, counts, w)  # = -(A* y - S - C)
         Xt = Xt + sigma * Rq
         z = rowdot((Xt + D) @ Y, Y)
         X = Xt + D - np.diag(z)
         evals, evecs = np.linalg.eigh(X)
         lmin, lmax = float(evals[0]), float(evals[-1])
-        eta = kkt_residuals(S, y, X, z, b, cls, C)
+        eta = kkt_residuals(S, y, X, z, b, cls, C, w)
         eta_max = max(eta)
         hist.append(dict(k=k, p=Y.shape[1], sigma=sigma, eta=eta, value=float(b @ y),
                          gradnorm=res.gradnorm, rtr_iters=res.iters, n_hvp=res.n_hvp,

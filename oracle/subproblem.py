@@ -58,9 +58,10 @@ class Subproblem:
     Xt: np.ndarray  # dense symmetric n x n
     sigma: float
     C: np.ndarray | None = None
+    w: np.ndarray | None = None  # signed unit coefficients of the A_gamma (None: 0/1 indicators)
 
     def __post_init__(self):
-        self.D = D_matrix(self.b, self.cls, self.counts)
+        self.D = D_matrix(self.b, self.cls, self.counts, self.w)
 
     # --- plain definitions -------------------------------------------------
     def Z(self, Y: np.ndarray) -> np.ndarray:
@@ -69,12 +70,12 @@ class Subproblem:
 
     def cost(self, Y: np.ndarray) -> float:
         Z = self.Z(Y)
-        R = Q_op(Z, self.cls, self.counts)
+        R = Q_op(Z, self.cls, self.counts, self.w)
         return float(np.sum((self.D + self.Xt) * Z) + 0.5 * self.sigma * np.sum(R * R))
 
     def G(self, Y: np.ndarray) -> np.ndarray:
         Z = self.Z(Y)
-        return self.Xt + self.D + self.sigma * Q_op(Z, self.cls, self.counts)
+        return self.Xt + self.D + self.sigma * Q_op(Z, self.cls, self.counts, self.w)
 
     def egrad(self, Y: np.ndarray) -> np.ndarray:
         return 2.0 * self.G(Y) @ Y
@@ -92,7 +93,7 @@ class Subproblem:
 
     def ehess(self, Y: np.ndarray, U: np.ndarray) -> np.ndarray:
         Zu = Y @ U.T + U @ Y.T
-        return 2.0 * self.G(Y) @ U + 2.0 * self.sigma * Q_op(Zu, self.cls, self.counts) @ Y
+        return 2.0 * self.G(Y) @ U + 2.0 * self.sigma * Q_op(Zu, self.cls, self.counts, self.w) @ Y
 
     def rhess(self, Y: np.ndarray, U: np.ndarray) -> np.ndarray:
         Ht = self.ehess(Y, U)
@@ -100,4 +101,4 @@ class Subproblem:
 
     def class_avg(self, Y: np.ndarray) -> np.ndarray:
         """y(S) = class averages of Z."""
-        return class_average(self.Z(Y), self.cls, self.counts)
+        return class_average(self.Z(Y), self.cls, self.counts, self.w)

@@ -35,7 +35,7 @@ class Options(C.Structure):
                 ("rtr_maxiter", _i32), ("tcg_maxinner", _i32), ("hvp_prec", _i32),
                 ("polish_fp64", _i32), ("polish_eta", _f64), ("eig_tol", _f64), ("eig_maxit", _i32),
                 ("time_limit_s", _f64), ("verbose", _i32), ("seed", _u64),
-                ("resume", _i32)]
+                ("resume", _i32), ("escape_when_solved", _i32)]
 
 
 class Result(C.Structure):
@@ -67,7 +67,9 @@ SIGNATURES = {
     "mdsdp_project_tangent": (_i32, [_i32, _i32, _vp, _vp, _vp, _vp]),
     "mdsdp_update_multiplier": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp]),
     "mdsdp_certificate_matvec": (_i32, [_vp, _i32, _vp, _vp, _vp]),
-    "mdsdp_min_eigpair": (_i32, [_vp, _f64, _i32, _u64, _pf64, _pf64, _vp, _pi32, _vp]),
+    "mdsdp_min_eigpair": (_i32, [_vp, _i32, _f64, _i32, _u64, _vp, _pf64, _vp, _pi32, _vp]),
+    "mdsdp_sync_status": (_i32, [_vp, _vp]),
+    "mdsdp_certificate_estimate": (_i32, [_vp, _f64, _i32, _u64, _vp, _vp, _vp, _pi32, _vp]),
     "mdsdp_adjoint_C": (_i32, [_vp, _vp, _vp]),
     "mdsdp_default_options": (None, [C.POINTER(Options)]),
     "mdsdp_solve": (_i32, [_vp, C.POINTER(Options), _i32, _vp, C.POINTER(Result), _vp, _i32, _vp]),

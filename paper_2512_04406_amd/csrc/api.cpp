@@ -186,15 +186,26 @@ static mdsdp_status check_device() {
 }
 
 // Builds the device problem from a packed-upper class map (row-major).
-static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, const double* b,
-                                       const double* C, mdsdp_problem* out) {
+// coef (nullable = all +1): coefficient of each packed entry in its A_gamma,
+// +1, -1, or 0 for an entry in no class (its class id is then ignored)
+static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, const int8_t* coef,
+                                       const double* b, const double* C, mdsdp_problem* out) {
   if (!out) return einval("out is NULL");
   *out = nullptr;
   if (n < 1 || n >= 65536) return einval("n must be in [1, 65535]");
   if (m < 1 || m > (long long)CLS_MASK) return einval("m out of range");
   if (!cls || !b) return einval("cls and b are required");
-  mdsdp_status st = check_device();
-  if (st != MDSDP_OK) return st;
+  for (long long g = 0; g < m; ++g)
+    if (!std::isfinite(b[g])) {
+      set_error("b has a non-finite entry at " + std::to_string(g));
+      return MDSDP_ENONFINITE;
+    }
+  if (C)
+    for (long long i = 0; i < (long long)n * n; ++i)
+      if (!std::isfinite(C[i])) {
+        set_error("C has a non-finite entry at " + std::to_string(i));
+        return MDSDP_ENONFINITE;
+      }
 
   const long long ne = (long long)n * (n + 1) / 2;
   std::vector<long long> cnt(m, 0);
@@ -202,9 +213,10 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
     long long idx = 0;
     for (long long r = 0; r < n; ++r)
       for (long long c = r; c < n; ++c, ++idx) {
+        if (coef && coef[idx] == 0) continue;
         const long long g = cls[idx];
         if (g < 0 || g >= m) return einval("class id out of range at packed index " + std::to_string(idx));
-        cnt[g] += (r == c) ? 1 : 2;
+        cnt[g] += (r == c) ? 1 : 2;  // sum of w_e^2 over the ordered entries, w_e = +-1
       }
   }
   long long kmax = 0;
@@ -212,8 +224,8 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
     if (cnt[g] == 0) return einval("class " + std::to_string(g) + " is empty (AA* singular)");
     kmax = std::max(kmax, cnt[g]);
   }
-  for (long long g = 0; g < m; ++g)
-    if (!std::isfinite(b[g])) return einval("b is not finite");
+  mdsdp_status st = check_device();
+  if (st != MDSDP_OK) return st;
 
   mdsdp_problem P = new mdsdp_problem_s();
   (void)hipGetDevice(&P->device);
@@ -249,11 +261,12 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
           }
           const long long rr = std::min(r, c), cc = std::max(r, c);
           const long long pidx = rr * n - rr * (rr - 1) / 2 + (cc - rr);
-          const uint32_t g = (uint32_t)cls[pidx];
-          uint32_t wv = g;
+          const int8_t we = coef ? coef[pidx] : (int8_t)1;
+          const uint32_t g = we == 0 ? 0u : (uint32_t)cls[pidx];
+          uint32_t wv = g | (we == 0 ? FREE_BIT : (we < 0 ? NEG_BIT : 0u));
           // owner: first slot of the class in slot order (diagonal tiles hold
           // both (r, c) and (c, r); either may own)
-          if (!seen[g]) {
+          if (we != 0 && !seen[g]) {
             seen[g] = 1;
             wv |= OWNER_BIT;
           }
@@ -281,7 +294,10 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
     hCavg.assign(m, 0.0);
     long long idx = 0;
     for (long long r = 0; r < n; ++r)
-      for (long long c = r; c < n; ++c, ++idx) hCavg[cls[idx]] += (r == c ? 1.0 : 2.0) * C[(size_t)r * n + c];
+      for (long long c = r; c < n; ++c, ++idx) {
+        const double we = coef ? (double)coef[idx] : 1.0;
+        if (we != 0.0) hCavg[cls[idx]] += we * (r == c ? 1.0 : 2.0) * C[(size_t)r * n + c];
+      }
     for (long long g = 0; g < m; ++g) hCavg[g] /= (double)cnt[g];
   }
 
@@ -403,7 +419,7 @@ extern "C" {
 
 mdsdp_status mdsdp_create_classmap(int32_t n, int64_t m, const int32_t* cls, const double* b, const double* C,
                                    mdsdp_problem* out) {
-  return create_from_packed(n, m, cls, b, C, out);
+  return create_from_packed(n, m, cls, nullptr, b, C, out);
 }
 
 mdsdp_status mdsdp_create_bqp(int32_t q, int32_t order, const double* Q, const double* c, mdsdp_problem* out) {
@@ -415,12 +431,22 @@ mdsdp_status mdsdp_create_bqp(int32_t q, int32_t order, const double* Q, const d
   if (st != MDSDP_OK) return st;
   if (order != MDSDP_ORDER_LEX && order != MDSDP_ORDER_COLEX) return einval("bad basis order");
   if (!Q || !c) return einval("Q and c are required");
+  for (long long i = 0; i < (long long)q * q; ++i)
+    if (!std::isfinite(Q[i])) {
+      set_error("Q has a non-finite entry at " + std::to_string(i));
+      return MDSDP_ENONFINITE;
+    }
+  for (int i = 0; i < q; ++i)
+    if (!std::isfinite(c[i])) {
+      set_error("c has a non-finite entry at " + std::to_string(i));
+      return MDSDP_ENONFINITE;
+    }
   std::vector<int32_t> cls((size_t)n * (n + 1) / 2);
   std::vector<double> b(m);
   if ((st = mdsdp_bqp_classmap(q, order, cls.data())) != MDSDP_OK) return st;
   if ((st = mdsdp_bqp_b(q, Q, c, b.data())) != MDSDP_OK) return st;
   mdsdp_problem P = nullptr;
-  if ((st = create_from_packed(n, m, cls.data(), b.data(), nullptr, &P)) != MDSDP_OK) return st;
+  if ((st = create_from_packed(n, m, cls.data(), nullptr, b.data(), nullptr, &P)) != MDSDP_OK) return st;
   if (order == MDSDP_ORDER_COLEX && q >= 1) {
     // structured class-sum kernels.  Degree-4 pass 1: items (d, c0, t0), a
     // 16-block of c < d and 64 pair rows t below C(c0 + 15, 2); pass 2: one
@@ -485,27 +511,37 @@ mdsdp_status mdsdp_create_sparse_A(int32_t n, int64_t m, int64_t nnz, const int3
   if (nnz < 0 || !cls || !row || !col || !val) return einval("sparse A arrays required");
   const long long ne = (long long)n * (n + 1) / 2;
   std::vector<int32_t> packed(ne, -1);
+  std::vector<int8_t> coef(ne, 0);  // entries no triplet covers stay in no class
+  bool unit = true;
   for (long long t = 0; t < nnz; ++t) {
     const long long r = row[t], c = col[t];
     if (r < 0 || c < r || c >= n) return einval("sparse A entry not in the upper triangle");
     if (cls[t] < 0 || cls[t] >= m) return einval("sparse A class out of range");
-    if (val[t] != 1.0) {
-      set_error("only 0/1 class-indicator constraint matrices are supported");
+    if (!std::isfinite(val[t])) {
+      set_error("sparse A has a non-finite value at triplet " + std::to_string(t));
+      return MDSDP_ENONFINITE;
+    }
+    if (val[t] != 1.0 && val[t] != -1.0) {
+      set_error("only coefficients +1 and -1 are supported in the A_gamma (value " + std::to_string(val[t]) +
+                " at triplet " + std::to_string(t) + ")");
       return MDSDP_EUNSUPPORTED;
     }
+    if (val[t] != 1.0) unit = false;
     const long long pidx = r * n - r * (r - 1) / 2 + (c - r);
     if (packed[pidx] >= 0) {
       set_error("sparse A supports overlap at (" + std::to_string(r) + ", " + std::to_string(c) + ")");
       return MDSDP_ENOTORTH;
     }
     packed[pidx] = cls[t];
+    coef[pidx] = val[t] > 0.0 ? 1 : -1;
   }
+  bool covered = true;
   for (long long i = 0; i < ne; ++i)
     if (packed[i] < 0) {
-      set_error("sparse A leaves matrix entries uncovered");
-      return MDSDP_EUNSUPPORTED;
+      covered = false;
+      packed[i] = 0;
     }
-  return create_from_packed(n, m, packed.data(), b, C, out);
+  return create_from_packed(n, m, packed.data(), (unit && covered) ? nullptr : coef.data(), b, C, out);
 }
 
 mdsdp_status mdsdp_destroy(mdsdp_problem P) {
@@ -529,7 +565,26 @@ mdsdp_status mdsdp_set_multiplier(mdsdp_problem P, const double* Xt_dev, double 
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return einval("sigma must be positive and finite");
   if (sigma != P->sigma) P->a32_valid = P->a64_valid = false;
   P->sigma = sigma;
+  // a new multiplier starts a new state: clear the sticky non-finite flag
+  // (a fill kernel, so that the call can be recorded into a HIP graph)
+  mdsdp_status st = vec_fill(1, 0.0, P->scal + SC_NONFIN, (hipStream_t)stream);
+  if (st != MDSDP_OK) return st;
   return launch_set_dense(P, Xt_dev, (hipStream_t)stream);
+}
+
+mdsdp_status mdsdp_sync_status(mdsdp_problem P, void* stream) {
+  if (!P) return einval("problem is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  double flag = 0.0;
+  MDSDP_HIP(hipMemcpyAsync(P->hbuf + 56, P->scal + SC_NONFIN, sizeof(double), hipMemcpyDeviceToHost, s));
+  MDSDP_HIP(hipStreamSynchronize(s));
+  flag = P->hbuf[56];
+  if (flag != 0.0) {
+    set_error("a non-finite value was met (multiplier, cost, Hessian-vector product or multiplier update) "
+              "since the last mdsdp_set_multiplier");
+    return MDSDP_ENONFINITE;
+  }
+  return MDSDP_OK;
 }
 
 mdsdp_status mdsdp_get_multiplier(mdsdp_problem P, double* Xt_dev, void* stream) {

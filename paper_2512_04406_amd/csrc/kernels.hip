@@ -118,6 +118,11 @@ __device__ __forceinline__ double bound_val(const unsigned long long* b, int i) 
   return __longlong_as_double((long long)b[i]);
 }
 
+// coefficient w_e of a slot in its A_gamma: +1, -1, or 0 (no class)
+__device__ __forceinline__ double coef_of(uint32_t cw) {
+  return (cw & FREE_BIT) ? 0.0 : ((cw & NEG_BIT) ? -1.0 : 1.0);
+}
+
 __device__ __forceinline__ int seg_of_block(int b, int per, int nseg) {
   int s = (b & 7) * per + (b >> 3);
   return s < nseg ? s : -1;
@@ -218,9 +223,9 @@ __global__ __launch_bounds__(256) void k_classsum(KArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const uint32_t cw = cb[drow<T>(lk, v) * 16];
-        if (!(cw & 0x80000000u)) {
+        if (!(cw & (0x80000000u | FREE_BIT))) {
           const uint32_t id = cw & CLS_MASK;
-          const long long qv = llrint(wgt * (double)acc[v] * scale);
+          const long long qv = llrint(coef_of(cw) * wgt * (double)acc[v] * scale);
           atomicAdd((unsigned long long*)&acc_t[id], (unsigned long long)qv);
         }
       }
@@ -399,7 +404,9 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
         const bool valid = !(cw & 0x80000000u);
         T av = 0, bv = 0;
         if (valid) {
-          const double2 dy = dyv[sc][v];  // {D, y}
+          // class data times the slot's coefficient w_e: {w D, w y} (or the HVP pair)
+          const double we = coef_of(cw);
+          const double2 dy = make_double2(we * dyv[sc][v].x, we * dyv[sc][v].y);
           const double Ce = a.Ct ? a.Ct[off] : 0.0;
           if (MODE == M_GRAD || MODE == M_MULT) {
             const double Zv = (double)Sbv[sc][v] + Ce;
@@ -639,10 +646,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SW == 16 ? 
         const bool valid = !(cw & 0x80000000u);
         const uint32_t id = valid ? (cw & CLS_MASK) : 0u;
         const float2 ab = a.ab32[id];
-        float A = xv[sc][v] + ab.x;
+        const float we = (float)coef_of(cw);  // coefficient of the slot in A_gamma
+        float A = xv[sc][v] + we * ab.x;
         if (a.Ct) A += sigma * (float)a.Ct[tb + sc * 256 + (4 * lk + v) * 16];
         av[sc][v] = valid ? A : 0.0f;
-        bv[sc][v] = valid ? ab.y : 0.0f;
+        bv[sc][v] = valid ? we * ab.y : 0.0f;
       }
 #pragma unroll
     for (int sc = 0; sc < 4; ++sc) {
@@ -813,7 +821,7 @@ __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __res
                                                  const double* __restrict__ U, const double* __restrict__ gram,
                                                  const double* __restrict__ lr_pre, const double* __restrict__ zvec,
                                                  double sigma, int riem, double* __restrict__ HU,
-                                                 double* __restrict__ dotpart) {
+                                                 double* __restrict__ dotpart, double* __restrict__ nonfin) {
   const int pw = ra.pw, L = row_lanes(pw), spl = row_split(pw);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int part = idx % spl, rc = idx / spl;
@@ -855,6 +863,7 @@ __global__ __launch_bounds__(256) void k_row_hvp(RowArgs ra, const double* __res
     const int k = c0 + j * L;
     if (in && part == 0 && k < ra.p && k < pw) {
       const double v = riem ? Ht[j] - d * y[j] - 2.0 * zr * u[j] : Ht[j];
+      if (!isfinite(v)) *nonfin = 1.0;  // sticky non-finite flag
       HU[(size_t)r * ra.p + k] = v;
       uh += u[j] * v;
     }
@@ -1106,7 +1115,8 @@ __global__ __launch_bounds__(256) void k_y_export(long long m, const double2* __
 
 // dense <-> tile layout for Xt
 __global__ __launch_bounds__(256) void k_set_dense(int n, int nb, long long nslots, const double* __restrict__ X,
-                                                   double* __restrict__ Xt, float* __restrict__ Xt32) {
+                                                   double* __restrict__ Xt, float* __restrict__ Xt32,
+                                                   double* __restrict__ nonfin) {
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nslots) return;
   const long long t = s / TSLOTS;
@@ -1121,6 +1131,7 @@ __global__ __launch_bounds__(256) void k_set_dense(int n, int nb, long long nslo
   const int c = J * 64 + (sb & 3) * 16 + (e & 15);
   double v = 0.0;
   if (r < n && c < n) v = X ? X[(size_t)r * n + c] : 0.0;
+  if (!isfinite(v)) *nonfin = 1.0;  // sticky non-finite flag
   Xt[s] = v;
   Xt32[s] = (float)v;
 }
@@ -1141,7 +1152,7 @@ __global__ __launch_bounds__(256) void k_get_dense(int n, int nb, long long nslo
   const int c = J * 64 + (sb & 3) * 16 + (e & 15);
   if (r >= n || c >= n) return;
   double v = Xt[s];
-  if (add_D) v += cy[cls[s] & CLS_MASK].x;
+  if (add_D) v += coef_of(cls[s]) * cy[cls[s] & CLS_MASK].x;
   X[(size_t)r * n + c] = v;
   X[(size_t)c * n + r] = v;
 }
@@ -1622,7 +1633,10 @@ __device__ __forceinline__ void bqp4_block(const BqpArgs& a, int item) {
   const size_t rbc = (size_t)pair_row(q, b0 + li, c) * pw;
   const long long base_c = a.off4 + c3(c);
   const int bn = b0 + li;
-  v4 accd[4];
+  // FP32 tiles: (ac|bd) and (ad|bc) are two entries of the class and get their
+  // own accumulators, so that the class sum itself is formed in FP64
+  constexpr bool SPLIT = sizeof(T) == 4;
+  v4 accd[4], accd2[4];
   for (int dh = 0; dh < 4; dh += DB) {
     size_t rad[DB], rbd[DB];
 #pragma unroll
@@ -1631,9 +1645,9 @@ __device__ __forceinline__ void bqp4_block(const BqpArgs& a, int item) {
       rad[u] = (size_t)pair_row(q, a0 + li, d) * pw;
       rbd[u] = (size_t)pair_row(q, bn, d) * pw;
     }
-    v4 acc[DB];
+    v4 acc[DB], acc2[DB];
 #pragma unroll
-    for (int u = 0; u < DB; ++u) acc[u] = v4{0, 0, 0, 0};
+    for (int u = 0; u < DB; ++u) acc[u] = acc2[u] = v4{0, 0, 0, 0};
     for (int kc = 0; kc < nkc; ++kc) {
       const int k0 = 16 * kc + 4 * lk;
       const v4 yac = ld4(Y + rac + k0), ybc = ld4(Y + rbc + k0);
@@ -1653,16 +1667,27 @@ __device__ __forceinline__ void bqp4_block(const BqpArgs& a, int item) {
           if (ZMODE) {
             acc[u] = mfma(yac[e], ubd[u][e], acc[u]);
             acc[u] = mfma(uac[e], ybd[u][e], acc[u]);
-            acc[u] = mfma(yad[u][e], ubc[e], acc[u]);
-            acc[u] = mfma(uad[u][e], ybc[e], acc[u]);
+            if (SPLIT) {
+              acc2[u] = mfma(yad[u][e], ubc[e], acc2[u]);
+              acc2[u] = mfma(uad[u][e], ybc[e], acc2[u]);
+            } else {
+              acc[u] = mfma(yad[u][e], ubc[e], acc[u]);
+              acc[u] = mfma(uad[u][e], ybc[e], acc[u]);
+            }
           } else {
             acc[u] = mfma(yac[e], ybd[u][e], acc[u]);
-            acc[u] = mfma(yad[u][e], ybc[e], acc[u]);
+            if (SPLIT)
+              acc2[u] = mfma(yad[u][e], ybc[e], acc2[u]);
+            else
+              acc[u] = mfma(yad[u][e], ybc[e], acc[u]);
           }
         }
     }
 #pragma unroll
-    for (int u = 0; u < DB; ++u) accd[dh + u] = acc[u];
+    for (int u = 0; u < DB; ++u) {
+      accd[dh + u] = acc[u];
+      accd2[dh + u] = acc2[u];
+    }
   }
   // stores last (vector memory counters retire in order: a store ahead of a
   // load would make the load's wait include it)
@@ -1676,7 +1701,8 @@ __device__ __forceinline__ void bqp4_block(const BqpArgs& a, int item) {
         const int al = drow<T>(lk, v), an = a0 + al;
         if (an < bn && bn < c) {
           const double t1 = (double)t1s[(li * 16 + al) * 17 + 4 * w + dd];
-          bqp_store<T, ZMODE>(a, base + c2(bn) + an, (t1 + (double)accd[dd][v]) * (1.0 / 3.0));
+          const double t23 = SPLIT ? (double)accd[dd][v] + (double)accd2[dd][v] : (double)accd[dd][v];
+          bqp_store<T, ZMODE>(a, base + c2(bn) + an, (t1 + t23) * (1.0 / 3.0));
         }
       }
     }
@@ -1852,9 +1878,10 @@ __global__ __launch_bounds__(256) void k_bqp_pass2(BqpArgs a) {
           const int ao = li, bo = 4 * lk + v;
           const int an = 16 * A + ao, bn = 16 * B + bo;
           if (an < bn && bn < c) {
-            const T m2 = S1[ao * 17 + bo] + St[bo * 17 + ao];
+            // the three entries of class {a, b, c, d}, summed in FP64
+            const double m2 = (double)S1[ao * 17 + bo] + (double)St[bo * 17 + ao];
             const long long g4 = base4 + c2(bn) + an;
-            bqp_store<T, ZMODE>(a, a.off4 + g4, ((double)p1[g4] + (double)m2) * (1.0 / 3.0));
+            bqp_store<T, ZMODE>(a, a.off4 + g4, ((double)p1[g4] + m2) * (1.0 / 3.0));
           }
         }
       }
@@ -1911,8 +1938,12 @@ __device__ __forceinline__ void bqpStar_tile(const BqpArgs& a, int tile, int lg,
   const T* Y = (const T*)a.Yp;
   const T* U = (const T*)a.Up;
   const int i = 16 * I + li, j = 16 * J + li;
+  // each l gives one entry (il|jl) of class {i, j}: FP32 tiles fold it into
+  // an FP64 sum after its dot product
+  double accs[4] = {0.0, 0.0, 0.0, 0.0};
   v4 acc = {0, 0, 0, 0};
   for (int l = lg; l < q; l += STAR_LG) {
+    if (sizeof(T) == 4) acc = v4{0, 0, 0, 0};
     const bool iok = i < q && i != l, jok = j < q && j != l;
     const size_t ri = (size_t)pair_row(q, i, l) * pw, rj = (size_t)pair_row(q, j, l) * pw;
     for (int kc = 0; kc < a.nkc; ++kc) {
@@ -1931,11 +1962,17 @@ __device__ __forceinline__ void bqpStar_tile(const BqpArgs& a, int tile, int lg,
         for (int e = 0; e < 4; ++e) acc = mfma(yi[e], yj[e], acc);
       }
     }
+    if (sizeof(T) == 4)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) accs[v] += (double)acc[v];
   }
+  if (sizeof(T) != 4)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) accs[v] = (double)acc[v];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int ii = 16 * I + drow<T>(lk, v);
-    if (ii < q && j < q) a.star[((size_t)lg * q + j) * q + ii] = (double)acc[v];
+    if (ii < q && j < q) a.star[((size_t)lg * q + j) * q + ii] = accs[v];
   }
 }
 
@@ -2483,7 +2520,8 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
   }
   const int rm = P->pw <= 64 ? 1 : P->pw / 64;
 #define ROW_HVP(TT, RMV) \
-  k_row_hvp<TT, RMV><<<nblk, 256, 0, s>>>(ra, Y, U, P->gram, lr, P->zvec, P->sigma, riem, HU, dot_out ? dotpart : nullptr)
+  k_row_hvp<TT, RMV><<<nblk, 256, 0, s>>>(ra, Y, U, P->gram, lr, P->zvec, P->sigma, riem, HU, dot_out ? dotpart : nullptr, \
+                                             P->scal + SC_NONFIN)
   if (fp32) {
     if (rm <= 1)
       ROW_HVP(float, 1);
@@ -2548,7 +2586,8 @@ mdsdp_status launch_y_export(mdsdp_problem P, double* y, hipStream_t s) {
 }
 
 mdsdp_status launch_set_dense(mdsdp_problem P, const double* X, hipStream_t s) {
-  k_set_dense<<<blocks_for(P->nslots, 256), 256, 0, s>>>(P->n, P->nb, P->nslots, X, P->Xt, P->Xt32);
+  k_set_dense<<<blocks_for(P->nslots, 256), 256, 0, s>>>(P->n, P->nb, P->nslots, X, P->Xt, P->Xt32,
+                                                         P->scal + SC_NONFIN);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }

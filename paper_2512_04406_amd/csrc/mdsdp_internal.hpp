@@ -35,8 +35,13 @@ constexpr int HBUF_LEN = 64 + PMAX * PMAX;  // pinned read-back buffer (doubles)
 constexpr int TSLOTS = TS * TS;  // slots per tile
 constexpr int LP = 17;          // LDS row pitch (elements) for 16-wide rows
 constexpr int STAR_LG = 32;     // residue classes of l in the degree-2 BQP contraction
-constexpr uint32_t CLS_MASK = 0x3FFFFFFFu;
+// class word of a slot: bit 31 padding slot (outside the matrix), bit 30
+// first slot of its class, bit 29 coefficient -1 in A_gamma, bit 28 no class
+// (coefficient 0: A*(y) is zero there), bits 0..27 the class id
+constexpr uint32_t CLS_MASK = 0x0FFFFFFFu;
 constexpr uint32_t OWNER_BIT = 0x40000000u;
+constexpr uint32_t NEG_BIT = 0x20000000u;
+constexpr uint32_t FREE_BIT = 0x10000000u;
 
 // Gram partials: gram_blocks(pw) row blocks, each 2 pw^2 doubles (at most
 // 4 blocks of 2 x 512 x 512, 2 x 32 x 64 x 64 or 32 x 4 x 2 x 16 x 16)

@@ -7,20 +7,30 @@
 // Readings of points the paper leaves open (same as the oracle's):
 //  * RTR constants rho' = 0.1, kappa = 0.1, theta = 1, Delta_bar = pi sqrt(n),
 //    Delta_0 = Delta_bar / 8 (Absil-Baker-Gallivan trust region);
-//  * inner tolerance max(gtol_min, min(gtol0, 0.1 eta_max, gtol_decay * previous tolerance,
-//    gtol_ratio ||R|| / (1 + ||b||), stall cap)); the stall cap becomes
-//    gtol_stall ||grad|| whenever an RTR call starts below its tolerance;
+//  * inner tolerance of subproblem k: max(gtol_min, min(gtol0, gtol_ratio ||R^k|| / (1 + ||b||)))
+//    (gtol0 at k = 0), the scaled primal residual that eq. sec5:eq1 weighs
+//    against ||grad||, so both sides of that rule are on one scale: sigma
+//    rises when an outer step leaves the primal residual about where it was
+//    and falls when RTR stops short of its tolerance.  With gtol_ratio <= 0
+//    the older form max(gtol_min, min(gtol0, 0.1 eta_max, gtol_decay * previous))
+//    is used.  Optional stall cap (gtol_stall > 0): after an RTR call that
+//    starts below its tolerance every later tolerance is at most
+//    gtol_stall ||grad||;
 //  * the certificate Lanczos starts from the previous Ritz vector plus a
 //    random component and stops when the error estimate of theta_min
 //    (residual, or residual^2 / Ritz gap) is below eig_tol (1 + |theta_max|);
 //    when it stops unconverged, eta_d uses theta_min minus that estimate, and
 //    when eta_d is then the only residual above the tolerance the step budget
 //    of the next eigensolve doubles (up to n);
-//  * with sigma_hold, sigma is not decreased after an RTR call that stopped
-//    at its iteration cap (its gradient norm then measures the unfinished
-//    subproblem, not the dual residual of eq. sec5:eq1);
+//  * eq. sec5:eq1 is applied as printed after every outer step (option
+//    sigma_hold, off by default, skips its decrease branch after an RTR call
+//    that stopped at its iteration cap);
 //  * carried direction: backtracking t = sqrt(n), sqrt(n)/2, ... along
-//    R_[Y,0](t [0, v]) until Psi_k decreases, then RTR;
+//    R_[Y,0](t [0, v]) until Psi_k decreases, then RTR.  With
+//    escape_when_solved (default) the direction, and the zero columns it
+//    needs, are formed only after an RTR call that reached its tolerance: the
+//    paper brings in Theorem sec5:thm1 to leave stationary points whose
+//    certificate is not PSD, and an unfinished subproblem is not one;
 //  * rank rule: drop singular directions of Y below tau_rank * s_1, then add
 //    one zero column per carried negative eigenvector (at most n_neg per
 //    outer step, p <= p_max);
@@ -432,6 +442,10 @@ mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, i
     CHK(dots(P, 1, a, a, len, &gg, s));
   }
   double gn = sqrt(gg);
+  if (!std::isfinite(f) || !std::isfinite(gn)) {
+    set_error("non-finite cost or gradient at the start of a subproblem (NaN or Inf in Y or the multiplier)");
+    return MDSDP_ENONFINITE;
+  }
   int it = 0;
   for (; it < maxiter; ++it) {
     if (gn <= gtol) break;
@@ -487,10 +501,13 @@ mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, i
 static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t seed, double* lmin, double* lmax,
                             double* evec, int* iters, bool* converged, hipStream_t s, int nvec = 1,
                             double neg_rel = 0.0, int* nfound = nullptr, const double* warm = nullptr,
-                            double* resid_out = nullptr, bool use_gap = false) {
+                            double* resid_out = nullptr, bool use_gap = false, int kconv = 1,
+                            double* evals_out = nullptr, double* ext = nullptr) {
   const int n = P->n;
   maxit = std::max(2, std::min(maxit, n));
-  if (P->lz_cap < maxit + 1) {
+  // basis V (n x (maxit + 1)), w (n), h (2 maxit + 8): the caller's fixed
+  // scratch `ext` if given, else buffers of the problem (grown on demand)
+  if (!ext && P->lz_cap < maxit + 1) {
     if (P->lz_V) (void)hipFree(P->lz_V);
     P->lz_V = nullptr;
     MDSDP_HIP(hipMalloc((void**)&P->lz_V, (size_t)n * (maxit + 1) * sizeof(double)));
@@ -499,9 +516,9 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
     if (P->lz_h) (void)hipFree(P->lz_h);
     MDSDP_HIP(hipMalloc((void**)&P->lz_h, (size_t)(2 * maxit + 8) * sizeof(double)));
   }
-  double* V = P->lz_V;
-  double* w = P->lz_w;
-  double* h = P->lz_h;
+  double* V = ext ? ext : P->lz_V;
+  double* w = ext ? ext + (size_t)n * (maxit + 1) : P->lz_w;
+  double* h = ext ? w + n : P->lz_h;
   std::vector<double> v0(n);
   gaussian_fill(seed ^ 0x5DEECE66Dull, v0);
   double nrm = 0.0;
@@ -556,16 +573,28 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
     th_min = tridiag_eig(k, al.data(), be.data(), 0);
     th_max = tridiag_eig(k, al.data(), be.data(), k - 1);
     tridiag_evec(k, al.data(), be.data(), th_min, sv);
-    // error estimate of theta_min: the residual, or residual^2 / gap with the
-    // Ritz gap to the next Ritz value when that is smaller
+    // error estimate of theta_min: the residual, or residual^2 / gap when the
+    // gap to the rest of the spectrum is certified: theta_2 minus its own
+    // residual still lies above theta_min (then the interval of theta_2
+    // excludes theta_min's eigenvalue and resid^2 / gap bounds its error)
     const double resid = bj * fabs(sv[k - 1]);
     double err = resid;
     if (use_gap && k >= 2) {
-      const double gap = tridiag_eig(k, al.data(), be.data(), 1) - th_min;
+      const double th2 = tridiag_eig(k, al.data(), be.data(), 1);
+      std::vector<double> s2;
+      tridiag_evec(k, al.data(), be.data(), th2, s2);
+      const double gap = th2 - bj * fabs(s2[k - 1]) - th_min;
       if (gap > 0.0) err = std::min(resid, resid * resid / gap);
     }
+    // the other pairs that must converge (kconv > 1): their residuals
+    double err_all = err;
+    for (int i = 1; i < std::min(kconv, k); ++i) {
+      std::vector<double> si;
+      tridiag_evec(k, al.data(), be.data(), tridiag_eig(k, al.data(), be.data(), i), si);
+      err_all = std::max(err_all, bj * fabs(si[k - 1]));
+    }
     if (resid_out) *resid_out = err;
-    if (k >= 3 && err <= tol * (1.0 + fabs(th_max))) {
+    if (k >= std::max(3, kconv + 2) && err_all <= tol * (1.0 + fabs(th_max))) {
       *converged = true;
       break;
     }
@@ -579,12 +608,15 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
   *lmin = th_min;
   *lmax = th_max;
   *iters = k;
+  if (evals_out)
+    for (int i = 0; i < kconv; ++i) evals_out[i] = i < k ? tridiag_eig(k, al.data(), be.data(), i) : NAN;
   int found = 0;
   if (evec && nvec >= 1) {
-    // Ritz vectors V s_i for the smallest Ritz values (the first always)
+    // Ritz vectors V s_i for the smallest Ritz values (the first always; with
+    // neg_rel >= 0 the others only while negative)
     for (int i = 0; i < std::min(nvec, k); ++i) {
       const double th = i == 0 ? th_min : tridiag_eig(k, al.data(), be.data(), i);
-      if (i > 0 && !(th < -neg_rel * (1.0 + fabs(th_max)))) break;
+      if (i > 0 && neg_rel >= 0.0 && !(th < -neg_rel * (1.0 + fabs(th_max)))) break;
       if (i > 0) tridiag_evec(k, al.data(), be.data(), th, sv);
       MDSDP_HIP(hipMemcpyAsync(h, sv.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
       CHK(launch_gemv(n, k, V, h, evec + (size_t)i * n, s));
@@ -619,9 +651,10 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->gtol0 = 1e-2;
   o->gtol_min = 1e-10;
   o->gtol_decay = 1.0;
-  o->gtol_ratio = 0.0;
-  o->gtol_stall = 0.1;
-  o->sigma_hold = 1;
+  o->gtol_ratio = 0.1;
+  o->gtol_stall = 0.0;
+  o->sigma_hold = 0;
+  o->escape_when_solved = 1;
   o->rtr_maxiter = 50;
   o->tcg_maxinner = 200;
   o->hvp_prec = MDSDP_FP64;
@@ -634,19 +667,25 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->seed = 1;
 }
 
-mdsdp_status mdsdp_min_eigpair(mdsdp_problem P, double tol, int32_t maxit, uint64_t seed, double* lambda_min,
-                               double* lambda_max, double* evec, int32_t* iters, void* stream) {
-  if (!P || !lambda_min || !lambda_max) {
+mdsdp_status mdsdp_min_eigpair(mdsdp_problem P, int32_t k, double tol, int32_t maxit, uint64_t seed,
+                               double* evals, double* lambda_max, double* evecs, int32_t* iters, void* stream) {
+  if (!P || !evals || !lambda_max) {
     set_error("NULL argument");
     return MDSDP_EINVAL;
   }
-  if (maxit < 2 || !(tol > 0.0)) {
-    set_error("maxit must be >= 2 and tol > 0");
+  if (k < 1 || maxit < 2 || !(tol > 0.0)) {
+    set_error("need k >= 1, maxit >= 2 and tol > 0");
+    return MDSDP_EINVAL;
+  }
+  if (k > P->n || k + 2 > maxit) {
+    set_error("need k <= n and k + 2 <= maxit");
     return MDSDP_EINVAL;
   }
   bool conv = false;
   int it = 0;
-  mdsdp_status st = lanczos(P, tol, maxit, seed, lambda_min, lambda_max, evec, &it, &conv, (hipStream_t)stream);
+  double lmin = 0.0;
+  mdsdp_status st = lanczos(P, tol, maxit, seed, &lmin, lambda_max, evecs, &it, &conv, (hipStream_t)stream, k,
+                            -1.0, nullptr, nullptr, nullptr, false, k, evals);
   if (iters) *iters = it;
   if (st != MDSDP_OK) return st;
   if (!conv) {
@@ -656,9 +695,62 @@ mdsdp_status mdsdp_min_eigpair(mdsdp_problem P, double tol, int32_t maxit, uint6
   return MDSDP_OK;
 }
 
+mdsdp_status mdsdp_certificate_estimate(mdsdp_problem P, double tol, int32_t maxit, uint64_t seed,
+                                       const double* warm, double* out, double* evec, int32_t* iters,
+                                       void* stream) {
+  if (!P || !out) {
+    set_error("NULL argument");
+    return MDSDP_EINVAL;
+  }
+  if (maxit < 3 || !(tol > 0.0)) {
+    set_error("need maxit >= 3 and tol > 0");
+    return MDSDP_EINVAL;
+  }
+  bool conv = false;
+  int it = 0;
+  double err = 0.0;
+  mdsdp_status st = lanczos(P, tol, maxit, seed, out, out + 1, evec, &it, &conv, (hipStream_t)stream, 1, 0.0,
+                            nullptr, warm, &err, true);
+  if (iters) *iters = it;
+  out[2] = err;
+  out[3] = conv ? 1.0 : 0.0;
+  return st;
+}
+
 mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, double* Ybuf, mdsdp_result* res,
                          double* hist, int32_t hist_cap, void* stream) {
-  if (!P || !opt || !Ybuf || !res) {
+  if (!opt) {
+    set_error("NULL options");
+    return MDSDP_EINVAL;
+  }
+  // options first, so that a bad option is reported whatever else is wrong
+  if (!(opt->tol > 0.0) || opt->max_outer < 1) {
+    set_error("need tol > 0 and max_outer >= 1");
+    return MDSDP_EINVAL;
+  }
+  if (!(opt->sigma_min > 0.0 && opt->sigma_min <= opt->sigma_max && std::isfinite(opt->sigma_max))) {
+    set_error("need 0 < sigma_min <= sigma_max < inf");
+    return MDSDP_EINVAL;
+  }
+  if (!(opt->sigma0 >= opt->sigma_min && opt->sigma0 <= opt->sigma_max)) {
+    set_error("need sigma_min <= sigma0 <= sigma_max");
+    return MDSDP_EINVAL;
+  }
+  if (!(opt->gamma > 1.0 && opt->kappa1 > 0.0 && opt->kappa1 <= opt->kappa2 && std::isfinite(opt->kappa2))) {
+    set_error("need gamma > 1 and 0 < kappa1 <= kappa2 (eq. sec5:eq1)");
+    return MDSDP_EINVAL;
+  }
+  if (!(opt->time_limit_s >= 0.0) || opt->rtr_maxiter < 1 || opt->tcg_maxinner < 1 || opt->eig_maxit < 2 ||
+      !(opt->eig_tol > 0.0) || !(opt->gtol0 > 0.0) || !(opt->gtol_min >= 0.0)) {
+    set_error("need time_limit_s >= 0, rtr_maxiter >= 1, tcg_maxinner >= 1, eig_maxit >= 2, eig_tol > 0, "
+              "gtol0 > 0, gtol_min >= 0");
+    return MDSDP_EINVAL;
+  }
+  if (opt->hvp_prec != MDSDP_FP64 && opt->hvp_prec != MDSDP_FP32) {
+    set_error("hvp_prec must be MDSDP_FP64 or MDSDP_FP32");
+    return MDSDP_EINVAL;
+  }
+  if (!P || !Ybuf || !res) {
     set_error("NULL argument");
     return MDSDP_EINVAL;
   }
@@ -687,10 +779,12 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   double* Y = Ybuf;
   // normalise rows of the start point
   CHK(launch_retract(n, p, Y, Y, 0.0, Y, s));
-  if (opt->resume)
+  if (opt->resume) {
     CHK(mdsdp_set_sigma(P, opt->sigma0));
-  else
+    CHK(vec_fill(1, 0.0, P->scal + SC_NONFIN, s));
+  } else {
     CHK(mdsdp_set_multiplier(P, nullptr, opt->sigma0, s));
+  }
   double sigma = opt->sigma0;
   double eta_max = 1.0;
   bool carry = false;
@@ -725,13 +819,22 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
       }
     }
     {
-      double g = std::min(std::min(opt->gtol0, 0.1 * eta_max), opt->gtol_decay * gtol);
-      if (opt->gtol_ratio > 0.0 && std::isfinite(prim_ratio)) g = std::min(g, opt->gtol_ratio * prim_ratio);
+      double g;
+      if (opt->gtol_ratio > 0.0)
+        g = std::isfinite(prim_ratio) ? std::min(opt->gtol0, opt->gtol_ratio * prim_ratio) : opt->gtol0;
+      else
+        g = std::min(std::min(opt->gtol0, 0.1 * eta_max), opt->gtol_decay * gtol);
       g = std::min(g, stall_cap);
       gtol = std::max(opt->gtol_min, g);
     }
     RTRState rs;
-    CHK(rtr(P, p, Y, gtol, opt->rtr_maxiter, opt->tcg_maxinner, prec, W, C, rs, s, opt->verbose));
+    mdsdp_status rst = rtr(P, p, Y, gtol, opt->rtr_maxiter, opt->tcg_maxinner, prec, W, C, rs, s, opt->verbose);
+    if (rst == MDSDP_ENONFINITE) {
+      final_status = MDSDP_ENONFINITE;
+      ++k;
+      break;
+    }
+    CHK(rst);
     if (opt->gtol_stall > 0.0 && rs.iters == 0 && rs.gn > 0.0) stall_cap = std::min(stall_cap, opt->gtol_stall * rs.gn);
     // multiplier update (Algorithm alg1 steps 5-8)
     auto tu = clk::now();
@@ -739,6 +842,12 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     double kk[4];
     CHK(read_dev(P, P->scal + SC_KKT, 4, kk, s));
     C.t_update += secs(tu, clk::now());
+    if (!(std::isfinite(kk[0]) && std::isfinite(kk[1]) && std::isfinite(kk[2]) && std::isfinite(kk[3]))) {
+      set_error("non-finite value in the multiplier update (||Q(Z)||, b^T y or sum z)");
+      final_status = MDSDP_ENONFINITE;
+      ++k;
+      break;
+    }
     // certificate spectrum
     auto te = clk::now();
     double lmin = 0, lmax = 0;
@@ -805,10 +914,11 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     for (int i = 0; i < p; ++i)
       if (sqrt(std::max(0.0, wv[idx[i]])) > opt->tau_rank * s1) ++r;
     r = std::max(1, r);
+    const bool unsolved = rs.gn > gtol;  // RTR stopped at its iteration cap
     const bool neg = lmin < -1e-12 * (1.0 + fabs(lmax));
     // negative-curvature directions: Ritz vectors of the negative Ritz values
     int nneg = 0;
-    if (neg && opt->n_neg > 0) nneg = std::min(nfound, opt->n_neg);
+    if (neg && opt->n_neg > 0 && !(opt->escape_when_solved && unsolved)) nneg = std::min(nfound, opt->n_neg);
     const int dadd = std::max(0, std::min(nneg, opt->p_max - r));
     const int pnew = r + dadd;
     // M = [V_r, 0] (p x pnew)
@@ -830,7 +940,6 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     // sigma rule, eq. sec5:eq1
     const double ratio = normR / (1.0 + P->normb);
     prim_ratio = ratio;
-    const bool unsolved = rs.gn > gtol;  // RTR stopped at its iteration cap
     if (ratio < opt->kappa1 * rs.gn && !(opt->sigma_hold && unsolved))
       sigma = std::max(sigma / opt->gamma, opt->sigma_min);
     else if (ratio > opt->kappa2 * rs.gn)
@@ -856,6 +965,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   res->t_hvp = C.t_hvp;
   res->t_eig = C.t_eig;
   res->t_update = C.t_update;
+  if (final_status == MDSDP_ENONFINITE) return MDSDP_ENONFINITE;
   return final_status == MDSDP_OK ? MDSDP_OK : MDSDP_ENOCONV;
 }
 

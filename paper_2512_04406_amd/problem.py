@@ -213,16 +213,41 @@ class Problem:
         call("mdsdp_certificate_matvec", self._h, V.shape[1], _ptr(V), _ptr(XV), _stream())
         return XV
 
-    def min_eigpair(self, tol: float = 1e-10, maxit: int = 300, seed: int = 0):
-        lmin = C.c_double()
+    def min_eigpairs(self, k: int = 1, tol: float = 1e-10, maxit: int = 300, seed: int = 0):
+        """The k smallest eigenpairs of the certificate and its largest
+        eigenvalue: (evals (k,), lambda_max, evecs (k, n) device, iters,
+        converged)."""
+        ev = np.empty(k, dtype=np.float64)
         lmax = C.c_double()
         it = C.c_int32()
-        v = torch.empty(self.n, dtype=torch.float64, device="cuda")
-        code = lib().mdsdp_min_eigpair(self._h, tol, maxit, seed, C.byref(lmin), C.byref(lmax), _ptr(v),
+        V = torch.empty(k, self.n, dtype=torch.float64, device="cuda")
+        code = lib().mdsdp_min_eigpair(self._h, k, tol, maxit, seed, _ptr(ev), C.byref(lmax), _ptr(V),
                                         C.byref(it), _stream())
         if code not in (0, -7):
             _lib.check(code, "mdsdp_min_eigpair")
-        return lmin.value, lmax.value, v, it.value, code == 0
+        return ev, lmax.value, V, it.value, code == 0
+
+    def min_eigpair(self, tol: float = 1e-10, maxit: int = 300, seed: int = 0):
+        ev, lmax, V, it, conv = self.min_eigpairs(1, tol, maxit, seed)
+        return float(ev[0]), lmax, V[0], it, conv
+
+    def certificate_estimate(self, tol: float = 1e-10, maxit: int = 300, seed: int = 0, warm=None) -> dict:
+        """The solver's estimate of the certificate's extreme eigenvalues (see
+        mdsdp_certificate_estimate)."""
+        out = np.zeros(4, dtype=np.float64)
+        v = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        it = C.c_int32()
+        if warm is not None:
+            warm = _dev_f64(warm.contiguous(), "warm")
+        call("mdsdp_certificate_estimate", self._h, tol, maxit, seed, _ptr(warm), _ptr(out), _ptr(v),
+             C.byref(it), _stream())
+        return {"theta_min": float(out[0]), "theta_max": float(out[1]), "err": float(out[2]),
+                "converged": bool(out[3]), "evec": v, "iters": it.value}
+
+    def sync_status(self) -> None:
+        """Raise MdsdpError(MDSDP_ENONFINITE) if a kernel met a non-finite value
+        since the last set_multiplier (synchronises the stream)."""
+        call("mdsdp_sync_status", self._h, _stream())
 
     def adjoint_C(self) -> torch.Tensor:
         X = torch.empty(self.n, self.n, dtype=torch.float64, device="cuda")

@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["bqp_instance", "gaussian", "gaussian_vector", "sparse_bqp_instance"]
+__all__ = ["bqp_instance", "gaussian", "gaussian_vector", "sparse_bqp_instance", "ucqp_instance"]
 
 
 def bqp_instance(q: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
@@ -46,6 +46,24 @@ def sparse_bqp_instance(q: int, density: float, seed: int) -> tuple[np.ndarray, 
     Q[iu] = vals
     Q = Q + Q.T
     return Q, c
+
+
+def ucqp_instance(q: int, seed: int) -> np.ndarray:
+    """Hermitian q x q complex128 Q: real N(0,1) diagonal, strictly-upper
+    entries iid complex Gaussian CN(0,1) (real and imaginary parts iid
+    N(0, 1/2)), lower triangle the conjugate.  Draw order: the q diagonal
+    values, then (re, im) of each strictly-upper entry in row-major order."""
+    if q < 1:
+        raise ValueError("q must be >= 1")
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal(q)
+    iu = np.triu_indices(q, k=1)
+    ri = rng.standard_normal((iu[0].size, 2)) / np.sqrt(2.0)
+    Q = np.zeros((q, q), dtype=np.complex128)
+    Q[iu] = ri[:, 0] + 1j * ri[:, 1]
+    Q = Q + Q.conj().T
+    Q[np.diag_indices(q)] = d
+    return Q
 
 
 def gaussian(rows: int, cols: int, seed: int) -> np.ndarray:

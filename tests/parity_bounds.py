@@ -14,7 +14,8 @@ With W = Y U^T + U Y^T and |.| taken entry-wise:
   rgrad    : B_g + rowsum(B_g o |Y|) o |Y|
   ehess[U] : B_e = 2 |G| |U| + 2 sigma (|W| + P|W|) |Y|
   rhess[U] : B_e + rowsum(B_e o |Y|) o |Y| + 2 |z| o |U|
-where P replaces an entry by its class average (here of absolute values).
+where P replaces an entry by its class average (here of absolute values, with
+|w_e| for signed class coefficients).
 """
 
 from __future__ import annotations
@@ -24,13 +25,20 @@ import numpy as np
 from oracle.operators import D_matrix, P_op
 
 
+def _aw(sub):
+    """|w| of signed class coefficients (None for 0/1 indicators)."""
+    w = getattr(sub, "w", None)
+    return None if w is None else np.abs(w)
+
+
 def _abs_G(sub, Y):
     Z = Y @ Y.T
     if sub.C is not None:
         Z = Z + sub.C
     aZ = np.abs(Z)
-    return (np.abs(sub.Xt) + np.abs(D_matrix(sub.b, sub.cls, sub.counts))
-            + sub.sigma * (aZ + P_op(aZ, sub.cls, sub.counts)))
+    aw = _aw(sub)
+    return (np.abs(sub.Xt) + np.abs(D_matrix(sub.b, sub.cls, sub.counts, aw))
+            + sub.sigma * (aZ + P_op(aZ, sub.cls, sub.counts, aw)))
 
 
 def _project_bound(B, Y):
@@ -50,7 +58,7 @@ def bound_ehess(sub, Y, U):
     aY, aU = np.abs(Y), np.abs(U)
     aW = aY @ aU.T + aU @ aY.T
     return (2.0 * _abs_G(sub, Y) @ aU
-            + 2.0 * sub.sigma * (aW + P_op(aW, sub.cls, sub.counts)) @ aY)
+            + 2.0 * sub.sigma * (aW + P_op(aW, sub.cls, sub.counts, _aw(sub))) @ aY)
 
 
 def bound_rhess(sub, Y, U):

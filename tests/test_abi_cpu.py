@@ -89,20 +89,104 @@ def _coo(n, cls_full, skip=None, dup=None, val=1.0):
     return k.astype(np.int32), r.astype(np.int32), c.astype(np.int32), v
 
 
-@pytest.mark.parametrize("case,code", [("overlap", -4), ("uncovered", -6), ("signed", -6)])
+@pytest.mark.parametrize("case,code", [("overlap", -4), ("weighted", -6), ("nan", -5), ("emptyclass", -1)])
 def test_sparse_A_validation(case, code):
-    """Sparse 0/1 A: overlapping supports (AA* not diagonal) -> MDSDP_ENOTORTH;
-    uncovered entries or non-unit values -> MDSDP_EUNSUPPORTED; both found on
-    the host before any device work."""
+    """Sparse signed A: overlapping supports (AA* not diagonal) ->
+    MDSDP_ENOTORTH; coefficients other than +-1 -> MDSDP_EUNSUPPORTED;
+    non-finite -> MDSDP_ENONFINITE; a class left with no entry -> EINVAL; all
+    found on the host before any device work."""
     from paper_2512_04406_amd import _lib
 
     q = 4
     Q, c = bqp_instance(q, 0)
     rel = bqp.build_relaxation(Q, c, "colex")
-    kw = {"overlap": dict(dup=3), "uncovered": dict(skip=5), "signed": dict(val=-1.0)}[case]
+    kw = {"overlap": dict(dup=3), "weighted": dict(val=2.0), "nan": dict(val=np.nan), "emptyclass": {}}[case]
     k, r, cc, v = _coo(rel.n, rel.cls, **kw)
+    if case == "emptyclass":  # drop every triplet of class 0 (the diagonal)
+        keep = k != 0
+        k, r, cc, v = k[keep], r[keep], cc[keep], v[keep]
     L = _lib.lib()
     h = C.c_void_p()
     p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
     got = L.mdsdp_create_sparse_A(rel.n, rel.m, k.size, p(k), p(r), p(cc), p(v), p(rel.b), None, C.byref(h))
     assert got == code, L.mdsdp_last_error()
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+@pytest.mark.parametrize("where", ["Q", "c"])
+def test_nonfinite_bqp_data_rejected_on_host(where):
+    """NaN or Inf in the BQP data: MDSDP_ENONFINITE, found on the host before
+    any device work (so no GPU is needed to see it)."""
+    from paper_2512_04406_amd import _lib
+
+    Q, c = bqp_instance(6, 0)
+    if where == "Q":
+        Q = Q.copy()
+        Q[1, 2] = np.nan
+    else:
+        c = c.copy()
+        c[3] = np.inf
+    h = C.c_void_p()
+    L = _lib.lib()
+    assert L.mdsdp_create_bqp(6, 1, _p(np.ascontiguousarray(Q)), _p(c), C.byref(h)) == -5
+    assert where.encode() in L.mdsdp_last_error()
+    assert not h.value
+
+
+@pytest.mark.parametrize("where", ["b", "C"])
+def test_nonfinite_classmap_data_rejected_on_host(where):
+    from paper_2512_04406_amd import _lib
+
+    Q, c = bqp_instance(4, 1)
+    rel = bqp.build_relaxation(Q, c, "lex")
+    iu = np.triu_indices(rel.n)
+    cls = np.ascontiguousarray(rel.cls[iu].astype(np.int32))
+    b = rel.b.copy()
+    Cm = None
+    if where == "b":
+        b[2] = np.nan
+    else:
+        Cm = np.zeros((rel.n, rel.n))
+        Cm[0, 1] = Cm[1, 0] = -np.inf
+    h = C.c_void_p()
+    L = _lib.lib()
+    got = L.mdsdp_create_classmap(rel.n, rel.m, _p(cls), _p(b), None if Cm is None else _p(Cm), C.byref(h))
+    assert got == -5, L.mdsdp_last_error()
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("sigma0", 2e6, b"sigma0"),            # sigma above sigma_max
+    ("sigma_min", 0.0, b"sigma_min"),
+    ("max_outer", 0, b"max_outer"),
+    ("tol", 0.0, b"tol"),
+    ("time_limit_s", -1.0, b"time_limit_s"),
+    ("kappa1", 20.0, b"kappa1"),           # kappa1 > kappa2
+    ("gamma", 1.0, b"gamma"),
+    ("hvp_prec", 7, b"hvp_prec"),
+])
+def test_solver_options_validated_first(field, value, msg):
+    """Invalid options of Algorithm alg1 / eq. sec5:eq1 are rejected with
+    MDSDP_EINVAL before anything else is looked at."""
+    from paper_2512_04406_amd import _lib
+
+    L = _lib.lib()
+    o = _lib.Options()
+    L.mdsdp_default_options(C.byref(o))
+    assert o.sigma_hold == 0 and o.escape_when_solved == 1 and o.gtol_ratio > 0
+    setattr(o, field, value)
+    res = _lib.Result()
+    assert L.mdsdp_solve(None, C.byref(o), 2, None, C.byref(res), None, 0, None) == -1
+    assert msg in L.mdsdp_last_error()
+
+
+def test_status_and_eigpair_validation():
+    from paper_2512_04406_amd import _lib
+
+    L = _lib.lib()
+    assert L.mdsdp_sync_status(None, None) == -1
+    ev = np.zeros(2)
+    lmax = C.c_double()
+    assert L.mdsdp_min_eigpair(None, 2, 1e-8, 10, 0, _p(ev), C.byref(lmax), None, None, None) == -1
