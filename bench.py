@@ -3,23 +3,27 @@
 
 Workload: dense BQP, q = 100 (n = 5051, m = 4,087,976 classes), Q symmetric
 with iid N(0,1) off-diagonal entries and zero diagonal, c iid N(0,1) (seed 0);
-order-2 moment relaxation, colex basis; Burer-Monteiro start p0 = 16
-(= ceil(ln m)).  Synthetic data, resident in HBM before any timed region.
+order-2 moment relaxation, colex basis; factor rank up to 16 (start p0 = 16 =
+ceil(ln m)).  Synthetic data, resident in HBM before any timed region.
 
-A step is one outer iteration of Algorithm alg1: the RTR subproblem solve
-(cost/gradient passes, truncated-CG HVPs, retractions), the multiplier update,
-the Lanczos certificate eigensolve, the KKT residuals and the rank/sigma
-updates.  `--warmup` outer iterations run first (untimed), then `--steps`
-outer iterations continue the same run (timed).  `value` = HVPs per second
-over the timed steps.  Also reported: the isolated Riemannian HVP throughput
-at a fixed point (FP32 tiles and FP64); the roofline of the dominant kernel,
-the HVP product pass (its average launch time from HIP events around 100
-back-to-back launches on its stream; the HBM traffic from the committed
-rocprofv3 counter summary when it matches the current kernel sources); the
-isolated HVP rates of the q = 40 and sparse-Q q = 120 instances, with a full
-solve of the q = 40 instance to eta_max <= 1e-8 in both precisions; capped full
-solves to eta_max <= 1e-8 in mixed precision and in FP64; and the FP64 oracle
-timed on the host CPU on a bounded sample.
+A step is one outer iteration of Algorithm alg1 at rank <= 16: the RTR
+subproblem solve (cost/gradient passes, truncated-CG HVPs, retractions), the
+multiplier update, the Lanczos certificate eigensolve, the KKT residuals and
+the rank/sigma updates.  `--warmup` outer iterations run first (untimed), then
+`--steps` outer iterations continue the same run (timed).  `value` = HVPs per
+second over the timed steps with FP32 MFMA tiles in the HVP product pass
+(class sums, gradient, multiplier update, KKT in FP64); the same steps with
+FP64 tiles are reported beside it (`fp64_steps`).  Also reported: the
+isolated Riemannian HVP rate at a fixed point (both precisions); the roofline
+of the dominant kernel, the HVP product pass (average launch time from HIP
+events around 100 back-to-back launches on its stream; algorithmic bytes
+counted as in the method's traffic model, each packed entry's class word and
+multiplier shadow read once and the class data y, y' gathered once per class
+in FP64; measured HBM traffic from the committed rocprofv3 counter summary
+when it matches the current kernel sources); capped full solves to
+eta_max <= 1e-8 at q = 100 in mixed precision and in FP64 (dynamic rank); the
+q = 40 dense, sparse-Q q = 120 and Hermitian UCQP q = 30 instances; and the
+FP64 oracle timed on the host CPU on a bounded sample.
 
 `--kkt-only mixed,fp64 [--q Q --p P0] --kkt-time-limit-s T` runs only the full
 solves (time to KKT) and prints their JSON.
@@ -41,10 +45,16 @@ HBM_PEAK_GBS = 8000.0
 
 
 def _alg_bytes_hvp_resid(ne: int, m: int, fp32: bool) -> float:
-    """Algorithmic HBM bytes of one HVP product pass, each read once: per
-    packed entry the class word (4 B) and the multiplier (4 B FP32 shadow or
-    8 B FP64); per class the pair {D - sigma y, -sigma y'} (8 B in FP32, 16 B
-    in FP64)."""
+    """Algorithmic HBM bytes of one HVP product pass in the method's traffic
+    model: per packed entry the class word (4 B) and the multiplier (4 B FP32
+    shadow or 8 B FP64) read once; per class y and y' gathered once in FP64
+    (16 B)."""
+    return ne * (4 + (4 if fp32 else 8)) + 16.0 * m
+
+
+def _kernel_min_bytes_hvp_resid(ne: int, m: int, fp32: bool) -> float:
+    """The product pass's own minimum: per class it reads the one pair
+    {D - sigma y, -sigma y'} it needs, 8 B in FP32 (16 B in FP64)."""
     return ne * (4 + (4 if fp32 else 8)) + (8.0 if fp32 else 16.0) * m
 
 
@@ -118,11 +128,16 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed outer iterations before the timed ones")
     ap.add_argument("--q", type=int, default=100)
     ap.add_argument("--p", type=int, default=16, help="factor width of the isolated HVP and start rank p0")
-    ap.add_argument("--p-max", type=int, default=0, help="rank cap of the solver (0 = library default)")
+    ap.add_argument("--p-max", type=int, default=0, help="rank cap of the full time-to-KKT solves (0 = library default)")
+    ap.add_argument("--p-steps", type=int, default=16, help="rank cap of the timed outer iterations")
+    ap.add_argument("--ablation-time-limit-s", type=float, default=20.0,
+                    help="cap of each solve of the DSDP' / direct-DSDP comparison (0 skips it)")
+    ap.add_argument("--ucqp-time-limit-s", type=float, default=60.0,
+                    help="cap of each Hermitian UCQP q=30 full solve (0 skips them)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--hvp-iters", type=int, default=200)
-    ap.add_argument("--kkt-time-limit-s", type=float, default=90.0,
+    ap.add_argument("--kkt-time-limit-s", type=float, default=150.0,
                     help="cap of each full time-to-KKT solve (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
@@ -189,6 +204,48 @@ def main() -> int:
             res["value_rel_diff"] = abs(res["mixed"]["value"] - res["fp64"]["value"]) / (1 + abs(res["fp64"]["value"]))
         return res
 
+    def ucqp_solves(cap):
+        """Hermitian UCQP q = 30 (real embedding n = 992, m = 217,621 signed
+        classes): full solves to eta_max <= 1e-8 with FP32-tile and FP64 HVPs."""
+        from synth import ucqp_instance
+
+        pu = Problem.ucqp(ucqp_instance(30, args.seed))
+        res = kkt_solves(("mixed", "fp64"), cap, pr=pu, p0=8)
+        out = {"n": pu.n, "m": pu.m, "time_to_kkt": res}
+        pu.close()
+        return out
+
+    def ablation(cap):
+        """DSDP' (ManiDSDP) against the direct-DSDP two-block ADMM (section "Why
+        solve DSDP' instead of DSDP"): time to eta_max <= 1e-8 at q = 10, 20, 30
+        (FP64 HVPs), with the sigma rule of eq. sec5:eq1 and with sigma held at
+        sigma_0 = 0.01."""
+        out = {}
+        for qa in (10, 20, 30):
+            Qa, ca = bqp_instance(qa, args.seed)
+            pa = Problem.bqp(Qa, ca, ORDER_COLEX)
+            Ya = torch.from_numpy(gaussian(pa.n, 2, 100 + args.seed)).to(dev)
+            row = {}
+            for proto in ("adaptive", "fixed_sigma"):
+                for form, direct in (("dsdp_prime", 0), ("direct_admm", 1)):
+                    o = options(pa, FP64, direct_admm=direct, time_limit_s=cap)
+                    if proto == "fixed_sigma":
+                        o.sigma0, o.kappa1, o.kappa2 = 0.01, 1e-12, 1e12
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    r = pa.solve(Ya, o)
+                    torch.cuda.synchronize()
+                    row[f"{proto}/{form}"] = {"converged": r.status == 0, "seconds": time.perf_counter() - t0,
+                                              "eta_max": max(r.eta), "value": r.value, "outer": r.outer_iters,
+                                              "hvps": r.hvps}
+                a_, b_ = row[f"{proto}/dsdp_prime"], row[f"{proto}/direct_admm"]
+                if a_["converged"] and b_["converged"]:
+                    row[f"{proto}/speedup_dsdp_prime"] = b_["seconds"] / a_["seconds"]
+            pa.close()
+            out[f"q={qa}"] = row
+            print(f"[bench] ablation q={qa}: {row}", file=sys.stderr, flush=True)
+        return out
+
     if args.kkt_only:
         out = {"workload": f"dense BQP q={q} n={n} m={m} seed {args.seed}, p0={p}",
                "time_to_kkt": kkt_solves(args.kkt_only.split(","), args.kkt_time_limit_s)}
@@ -252,6 +309,39 @@ def main() -> int:
                           "kernels_sha": _kernel_sources_sha()}))
         return 0
 
+    def options(pr, prec, **kw):
+        o = pr.default_options()
+        o.hvp_prec = prec
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    # ---- steps: outer iterations of Algorithm alg1 at rank <= p_steps ----
+    def run_steps(prec):
+        Y0 = torch.from_numpy(gaussian(n, p, 100 + args.seed)).to(dev)
+        r_w = prob.solve(Y0, options(prob, prec, max_outer=max(1, args.warmup), p_max=args.p_steps))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r_t = prob.solve(r_w.Y.contiguous(), options(prob, prec, max_outer=args.steps, resume=1, sigma0=r_w.sigma,
+                                                      p_max=args.p_steps))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"[bench] steps prec={prec}: {r_t.outer_iters} outer in {dt:.2f} s, {r_t.hvps} HVPs, "
+              f"eta={max(r_t.eta):.2e}, p={r_t.p_final}", file=sys.stderr, flush=True)
+        return r_w, r_t, dt
+
+    r_w, r_t, total = run_steps(hvp_prec)
+    steps_done = r_t.outer_iters
+    fp64_steps = None
+    if hvp_prec != FP64:
+        _, r64, t64 = run_steps(FP64)
+        fp64_steps = {"hvps_per_s": r64.hvps / t64, "steps": r64.outer_iters,
+                      "ms_per_step": 1e3 * t64 / max(1, r64.outer_iters), "hvps": r64.hvps, "seconds": t64,
+                      "eta_max_after": max(r64.eta), "p_final": r64.p_final}
+
+    # ---- time to eta_max <= 1e-8 at the benchmark size (capped full solves) ----
+    kkt = kkt_solves(("mixed", "fp64"), args.kkt_time_limit_s) if args.kkt_time_limit_s > 0 else None
+
     other = {}
     if not args.no_other_configs:
         from synth import sparse_bqp_instance
@@ -282,34 +372,13 @@ def main() -> int:
                 # a converged time to KKT <= 1e-8 on the small dense instance (p0 = 4)
                 other[label]["time_to_kkt"] = kkt_solves(("mixed", "fp64"), 120.0, pr=po_prob, p0=po)
             po_prob.close()
+        if args.ucqp_time_limit_s > 0:
+            other["Hermitian UCQP q=30"] = ucqp_solves(args.ucqp_time_limit_s)
+        if args.ablation_time_limit_s > 0:
+            other["DSDP' vs direct-DSDP ADMM"] = ablation(args.ablation_time_limit_s)
         print(f"[bench] other configs: {other}", file=sys.stderr, flush=True)
 
-    def options(prec, **kw):
-        o = prob.default_options()
-        o.hvp_prec = prec
-        if args.p_max > 0:
-            o.p_max = args.p_max
-        for k, v in kw.items():
-            setattr(o, k, v)
-        return o
-
-    Y0 = torch.from_numpy(gaussian(n, p, 100 + args.seed)).to(dev)
-
-    # ---- steps: outer iterations of Algorithm alg1 ----
-    r_w = prob.solve(Y0, options(hvp_prec, max_outer=max(1, args.warmup)))
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done: {r_w.outer_iters} outer, eta={max(r_w.eta):.2e}", file=sys.stderr, flush=True)
-    t_start = time.perf_counter()
-    r_t = prob.solve(r_w.Y.contiguous(), options(hvp_prec, max_outer=args.steps, resume=1, sigma0=r_w.sigma))
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    steps_done = r_t.outer_iters
-    print(f"[bench] timed {steps_done} outer iterations in {total:.2f} s, {r_t.hvps} HVPs, "
-          f"eta={max(r_t.eta):.2e}", file=sys.stderr, flush=True)
-
-    # ---- time to eta_max <= 1e-8 (capped full solves) ----
-    kkt = kkt_solves(("mixed", "fp64"), args.kkt_time_limit_s) if args.kkt_time_limit_s > 0 else None
-
+    alg_tb = _kernel_min_bytes_hvp_resid(ne, m, hvp_prec == FP32)
     out = {
         "metric": "HVPs/s + time to KKT<=1e-8, mixed vs FP64, dense BQP q=100 (n=5051)",
         "value": r_t.hvps / total,
@@ -321,21 +390,25 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 tiles (HVP) + f64 (class sums, gradients, multiplier, KKT)" if hvp_prec == FP32 else "f64",
+        "dtype": ("fp32 MFMA tiles (HVP product pass) + fp64 (class sums, gradient, multiplier, KKT)"
+                  if hvp_prec == FP32 else "f64"),
         "data": "synthetic",
         "config": {"workload": f"dense BQP q={q} n={n} m={m}, Q,c ~ N(0,1) seed {args.seed}, order-2 moment "
-                               f"relaxation, ManiDSDP outer iterations from p0={p}",
+                               f"relaxation, ManiDSDP outer iterations at rank <= {args.p_steps} from p0={p}",
                    "global_batch": 1, "seq_len": n, "parallelism": "single GPU"},
         "timed_steps": {"hvps": r_t.hvps, "seconds": total, "eta_max_after": max(r_t.eta), "p_final": r_t.p_final,
                         "sigma": r_t.sigma, "phases_s": r_t.phases},
+        "fp64_steps": fp64_steps,
         "time_to_kkt": kkt,
         "hvp_isolated_per_s": 1.0 / hvp_dt,
         "hvp_isolated_us": hvp_dt * 1e6,
+        "hvp_fp64_isolated_per_s": 1.0 / hvp64_dt,
         "hvp_fp64_isolated_us": hvp64_dt * 1e6,
         "hvp_kernels_us": kern_us,
         "roofline": {"bound": "hbm", "kernel": resid_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg, "avg_launch_us": resid_s * 1e6},
+                     "alg_bytes_per_launch": alg, "kernel_min_bytes_per_launch": alg_tb,
+                     "avg_launch_us": resid_s * 1e6},
         "other_configs": other,
     }
     if not args.no_cpu_baseline:

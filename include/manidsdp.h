@@ -90,6 +90,28 @@ mdsdp_status mdsdp_bqp_sizes(int32_t q, int32_t* n_out, int64_t* m_out);
 mdsdp_status mdsdp_bqp_classmap(int32_t q, int32_t order, int32_t* cls_out);
 mdsdp_status mdsdp_bqp_b(int32_t q, const double* Q_host, const double* c_host, double* b_out);
 
+/* ---- Hermitian UCQP relaxation builder (host only, no device work) ----------
+ * Order-2 Hermitian moment relaxation of min z^H Q z over |z_i| = 1, z in C^q
+ * (paragraph on unit-modulus complex quadratic programs; this keeps the
+ * complex moments), in the real embedding S = [[Re M, -Im M], [Im M, Re M]] of
+ * the moment matrix M: basis 1, z_i, z_i z_j (i <= j) lexicographically,
+ * n_c = 1 + q + q(q+1)/2, n = 2 n_c.  Entries of M are classed by the exponent
+ * difference d = alpha - beta up to sign (representative gamma with its first
+ * nonzero component positive, d = s gamma): class re(gamma) holds (a, c) and
+ * (n_c + a, n_c + c) with coefficient +1; class im(gamma), gamma != 0, holds
+ * (n_c + a, c) with coefficient s and (a, n_c + c) with -s; the imaginary
+ * parts of the diagonal class are in no class (coefficient 0).  Class ids:
+ * representatives in ascending order as integer vectors, re(gamma) = rank,
+ * im(gamma) = m_re + rank - 1, m = 2 m_re - 1.  b: tr Q on class 0,
+ * 2 Re Q_ij on re(e_i - e_j), 2 Im Q_ij on im(e_i - e_j) (i < j).
+ * mdsdp_ucqp_sizes: n and m.  mdsdp_ucqp_structure: packed upper triangle
+ * (row-major, n(n+1)/2 entries) of class ids and coefficients (+1, -1, 0).
+ * mdsdp_ucqp_b: b (length m) from Q = Qre + i Qim (q x q row-major).
+ * 1 <= q <= 60. */
+mdsdp_status mdsdp_ucqp_sizes(int32_t q, int32_t* n_out, int64_t* m_out);
+mdsdp_status mdsdp_ucqp_structure(int32_t q, int32_t* cls_out, int8_t* coef_out);
+mdsdp_status mdsdp_ucqp_b(int32_t q, const double* Qre_host, const double* Qim_host, double* b_out);
+
 /* ---- problem lifetime ------------------------------------------------------
  * mdsdp_create_classmap: cls_host = packed upper-triangle class ids (row-major,
  * length n(n+1)/2, ids in [0, m), every class non-empty); b_host
@@ -108,6 +130,12 @@ mdsdp_status mdsdp_create_classmap(int32_t n, int64_t m, const int32_t* cls_host
  * the generic class-map path to rounding.  Errors as mdsdp_create_classmap. */
 mdsdp_status mdsdp_create_bqp(int32_t q, int32_t order, const double* Q_host, const double* c_host,
                               mdsdp_problem* out);
+/* Hermitian UCQP relaxation built in-library from Q = Qre + i Qim (q x q
+ * row-major host, Hermitian; EINVAL otherwise, ENONFINITE for NaN/Inf), with
+ * the class structure of mdsdp_ucqp_structure (signed coefficients; the
+ * generic class-map kernels). */
+mdsdp_status mdsdp_create_ucqp(int32_t q, const double* Qre_host, const double* Qim_host,
+                               mdsdp_problem* out);
 /* Sparse A given as a list of (class, row, col, value) with row <= col: the
  * entry (row, col) and its mirror have coefficient `value` in A_class.  Values
  * must be +1 or -1 (signed unit coefficients, as in the real embedding of a
@@ -134,6 +162,17 @@ mdsdp_status mdsdp_set_multiplier(mdsdp_problem prob, const double* Xt_dev, doub
                                   void* stream);
 mdsdp_status mdsdp_get_multiplier(mdsdp_problem prob, double* Xt_dev, void* stream);
 mdsdp_status mdsdp_set_sigma(mdsdp_problem prob, double sigma);
+
+/* ---- direct-DSDP subproblem (ablation) --------------------------------------
+ * on = 1 switches the problem to the S-subproblem of the two-block ADMM applied
+ * directly to DSDP (section "Why solve DSDP' instead of DSDP",
+ * eq. direct-ALM-subproblem): cost <D + Xt, Z> + sigma/2 ||Z - P(Z^k)||^2 with
+ * the stale class averages y^k, gradient 2 (Xt + D + sigma (Z - P(Z^k))) Y and
+ * Hessian sigma I in S (eq. hessian-comparison).  With Y_dev (n x p, FP64) y^k
+ * is set to the class averages of Y Y^T + C; otherwise the last computed ones
+ * are kept.  mdsdp_update_multiplier refreshes y^k (the ADMM y-update).  on = 0
+ * returns to the variable-projected subproblem of DSDP'. */
+mdsdp_status mdsdp_set_direct(mdsdp_problem prob, int32_t on, int32_t p, const double* Y_dev, void* stream);
 
 /* ---- device status (non-finite guard) --------------------------------------
  * Kernels raise a sticky flag in device memory when they meet a non-finite
@@ -225,11 +264,13 @@ typedef struct {
                           k = 0); <= 0: max(gtol_min, min(gtol0, 0.1 eta_max, gtol_decay * previous)) */
   double gtol_stall;   /* > 0: when an RTR call starts below its tolerance (takes no step), cap all
                           later tolerances at gtol_stall * ||grad||; default 0 (off) */
-  int32_t sigma_hold;  /* 1: do not decrease sigma after an RTR call that stopped at rtr_maxiter;
-                          default 0 (eq. sec5:eq1 as printed) */
-  int32_t rtr_maxiter, tcg_maxinner;
+  int32_t sigma_hold;  /* 1 (default): eq. sec5:eq1, but its decrease branch is not taken after an RTR
+                          call that stopped at its iteration budget (||grad|| then measures the
+                          unfinished inner solve, not a dual residual); 0: the rule as printed */
+  int32_t rtr_maxiter, tcg_maxinner; /* RTR iterations per subproblem (default 10; see rtr_maxiter_polish)
+                          and truncated-CG steps per RTR iteration (default 200) */
   int32_t hvp_prec;    /* mdsdp_prec for tCG HVPs */
-  int32_t polish_fp64; /* switch HVPs to FP64 once eta_max < polish_eta */
+  int32_t polish_fp64; /* switch HVPs to FP64 once eta_max < polish_eta (default 1e-4) */
   double polish_eta;
   double eig_tol;
   int32_t eig_maxit;
@@ -238,10 +279,20 @@ typedef struct {
   uint64_t seed;
   int32_t resume;      /* 0: start from Xt = 0, sigma = sigma0; 1: continue from the problem's current
                           multiplier Xt with sigma = sigma0 (e.g. the sigma a previous solve returned) */
-  int32_t escape_when_solved; /* 1 (default): form the carried direction of Theorem sec5:thm1 and add
-                          its zero columns only after an RTR call that reached its tolerance (the
-                          direction escapes stationary points whose certificate is not PSD); 0: after
-                          every outer step */
+  int32_t escape_when_solved; /* 1: form the carried direction of Theorem sec5:thm1 and add its zero
+                          columns only after an RTR call that reached its tolerance; 0 (default): after
+                          every outer step whose certificate has curvature below -tol (1 + |lambda_max|)
+                          (step 9 of Algorithm alg1) */
+  int32_t deflate;     /* 1 (default): the certificate eigensolve runs on the complement of range(Y)
+                          and combines it with the compression Q^T X Q to range(Y) (Weyl bound, see
+                          mdsdp_solve); 0: plain Lanczos on X */
+  int32_t direct_admm; /* 1: solve DSDP by the two-block ADMM with the direct S-subproblem
+                          (mdsdp_set_direct; the ablation of section "Why solve DSDP' instead of
+                          DSDP"); 0 (default): ManiDSDP on DSDP' */
+  int32_t rtr_warm_radius; /* 1 (default): each RTR call starts from the previous call's final trust
+                          radius (capped at Delta_bar / 8); 0: from Delta_bar / 8 */
+  int32_t rtr_maxiter_polish; /* RTR iteration budget once eta_max < polish_eta (default 50; the budget
+                          before that is rtr_maxiter, default 10) */
 } mdsdp_options;
 
 typedef struct {
@@ -267,6 +318,19 @@ void mdsdp_default_options(mdsdp_options* opt);
 mdsdp_status mdsdp_solve(mdsdp_problem prob, const mdsdp_options* opt, int32_t p0, double* Y_dev,
                          mdsdp_result* res, double* history_host, int32_t history_cap,
                          void* stream);
+
+/* Batch of independent problems (e.g. many small relaxations of uneven size):
+ * nworkers host threads, each with its own HIP stream (default priority),
+ * take problems from a shared work queue ordered by decreasing n and run
+ * mdsdp_solve on them, so the kernels of different problems overlap on the
+ * GPU.  probs[i], p0[i], Ybufs[i] (device, n_i * p_max doubles) as for
+ * mdsdp_solve; results[i] receives each solve's result (status included);
+ * the same options for all.  Returns MDSDP_OK when every problem reached the
+ * tolerance, MDSDP_ENOCONV if one did not, or the first error met.  Each
+ * problem must be used by no other thread during the call. */
+mdsdp_status mdsdp_solve_batch(int32_t nprob, mdsdp_problem* probs, const mdsdp_options* opt,
+                               const int32_t* p0, double* const* Ybufs, mdsdp_result* results,
+                               int32_t nworkers);
 
 /* ---- diagnostics -----------------------------------------------------------
  * Export internal tile-major arrays back to packed order (host buffers of

@@ -30,7 +30,7 @@ Readings of points the paper leaves open:
   that eq. sec5:eq1 weighs against ||grad||; for k = 0 (no R yet) gtol0.  Then
   the two sides of eq. sec5:eq1 are measured on one scale, and the rule
   raises sigma when an outer step leaves the primal residual about where it
-  was and lowers it when RTR stops short of its tolerance.  (With
+  was.  (With
   gtol_ratio <= 0 the older form min(gtol0, 0.1 eta_max^k, gtol_decay * previous)
   is used; there ||grad|| scales with eta_p while the rule divides ||R|| by
   1 + ||b||, so the decrease branch fires whenever 1 + ||b|| is large.)
@@ -38,16 +38,25 @@ Readings of points the paper leaves open:
   step) every later tolerance is capped at gtol_stall * ||grad|| (off by
   default).
 * sigma constants: sigma_0 = 1, sigma_min = 1e-3, sigma_max = 1e6, gamma = 2,
-  kappa_1 = 0.1, kappa_2 = 10 (the paper states none); eq. sec5:eq1 is applied
-  as printed after every outer step.  Option sigma_hold (off by default)
-  skips its decrease branch after an RTR call that stopped at its iteration
-  cap.
-* carried direction (step 9): the paper introduces the direction of Theorem
-  sec5:thm1 to escape stationary points whose certificate is not PSD; with
-  escape_when_solved (default) it is formed, and the zero columns added, only
-  after an RTR call that reached its tolerance -- an unfinished subproblem is
-  not such a point, and RTR continues from it along the gradient.
-* eigenvector sign: the largest-magnitude component is made positive.
+  kappa_1 = 0.1, kappa_2 = 10 (the paper states none).  eq. sec5:eq1 weighs
+  the scaled primal residual against ||grad Psi_k(Y^{k+1})|| as the dual
+  residual of a (approximately) solved subproblem; when RTR stops at its
+  iteration budget that norm measures the unfinished inner solve instead, so
+  with sigma_hold (default) the decrease branch is not taken then (the
+  increase branch and the rule after a solved subproblem are as printed;
+  sigma_hold = False applies the rule as printed after every step).
+* inner budget: the subproblem is solved approximately (Algorithm alg1 step
+  3): at most rtr_maxiter = 10 RTR iterations, and rtr_maxiter_polish = 50
+  once eta_max < polish_eta = 1e-4 (the polishing phase).
+* carried direction (step 9): formed after every outer step whose
+  certificate has an eigenvalue below -max(neg_tol, tol) (1 + |lambda_max|)
+  (curvature below the stopping tolerance's scale adds no columns); with
+  escape_when_solved only after an RTR call that reached its tolerance.
+* direct-DSDP ablation (option direct, section "Why solve DSDP' instead of
+  DSDP"): the subproblem is eq. direct-ALM-subproblem with the stale y^k of
+  the two-block ADMM; y^0 is the class average of the start point (the paper
+  derives the subproblem from the second iteration on); the multiplier,
+  sigma, rank and stopping steps are the same as for DSDP'.
 
 Parity: not pinned on iterates; the result is pinned by brute force (q <= 16,
 v <= min f, equality when rank S = 1), by the rank-one rounding certificate,
@@ -63,7 +72,7 @@ import numpy as np
 
 from .operators import A_adj, D_matrix, Q_op, class_average
 from .rtr import rtr
-from .subproblem import Subproblem, retract, rowdot
+from .subproblem import DirectSubproblem, Subproblem, retract, rowdot
 
 __all__ = ["ALMOptions", "ALMResult", "solve", "kkt_residuals", "rank_one_rounding"]
 
@@ -86,9 +95,12 @@ class ALMOptions:
     gtol_decay: float = 1.0
     gtol_ratio: float = 0.1
     gtol_stall: float = 0.0
-    sigma_hold: bool = False
-    escape_when_solved: bool = True
-    rtr_maxiter: int = 50
+    sigma_hold: bool = True
+    escape_when_solved: bool = False
+    direct: bool = False  # the direct-DSDP ADMM subproblem (ablation), see DirectSubproblem
+    rtr_maxiter: int = 10
+    rtr_maxiter_polish: int = 50
+    polish_eta: float = 1e-4
     neg_tol: float = 1e-12
 
 
@@ -156,8 +168,14 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
     normb = float(np.linalg.norm(b))
     y = z = X = None
     eta = (np.inf, np.inf, np.inf)
+    # direct-DSDP ablation: the stale dual iterate y^k of the two-block ADMM,
+    # taken at the start point for k = 0 and after every multiplier update
+    yk = class_average(Y @ Y.T + (0.0 if C is None else C), cls, counts, w) if opts.direct else None
     for k in range(opts.max_outer):
-        sub = Subproblem(cls, counts, b, Xt, sigma, C, w)
+        if opts.direct:
+            sub = DirectSubproblem(cls, counts, b, Xt, sigma, C, w, yk=yk)
+        else:
+            sub = Subproblem(cls, counts, b, Xt, sigma, C, w)
         if U is not None:
             Y = _escape(sub, Y, U)
         if opts.gtol_ratio > 0.0:
@@ -165,13 +183,16 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
         else:
             g = min(opts.gtol0, 0.1 * eta_max, opts.gtol_decay * gtol)
         gtol = max(opts.gtol_min, min(g, stall_cap))
-        res = rtr(sub, Y, gtol, maxiter=opts.rtr_maxiter)
+        budget = max(opts.rtr_maxiter, opts.rtr_maxiter_polish) if eta_max < opts.polish_eta else opts.rtr_maxiter
+        res = rtr(sub, Y, gtol, maxiter=budget)
         if opts.gtol_stall > 0.0 and res.iters == 0 and res.gradnorm > 0.0:
             stall_cap = min(stall_cap, opts.gtol_stall * res.gradnorm)
         Y = res.Y
         S = Y @ Y.T
         Z = S if C is None else S + C
         y = class_average(Z, cls, counts, w)
+        if opts.direct:
+            yk = y  # the y-update of the two-block ADMM (eq. direct-y-projection)
         Rq = Q_op(Z, cls, counts, w)  # = -(A* y - S - C)
         Xt = Xt + sigma * Rq
         z = rowdot((Xt + D) @ Y, Y)
@@ -187,7 +208,7 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
             break
         unsolved = res.gradnorm > gtol  # RTR stopped at its iteration cap
         # negative-curvature directions (Theorem sec5:thm1)
-        neg = np.nonzero(evals < -opts.neg_tol * (1.0 + abs(lmax)))[0][: opts.n_neg]
+        neg = np.nonzero(evals < -max(opts.neg_tol, opts.tol) * (1.0 + abs(lmax)))[0][: opts.n_neg]
         if opts.escape_when_solved and unsolved:
             neg = neg[:0]
         V = evecs[:, neg]

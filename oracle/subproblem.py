@@ -29,9 +29,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .operators import D_matrix, Q_op, class_average
+from .operators import A_adj, D_matrix, Q_op, class_average
 
-__all__ = ["Subproblem", "proj_tangent", "retract", "rowdot"]
+__all__ = ["Subproblem", "DirectSubproblem", "proj_tangent", "retract", "rowdot"]
 
 
 def rowdot(A: np.ndarray, B: np.ndarray) -> np.ndarray:
@@ -102,3 +102,37 @@ class Subproblem:
     def class_avg(self, Y: np.ndarray) -> np.ndarray:
         """y(S) = class averages of Z."""
         return class_average(self.Z(Y), self.cls, self.counts, self.w)
+
+
+@dataclass
+class DirectSubproblem(Subproblem):
+    """S-subproblem of the two-block ADMM applied directly to DSDP (section
+    "Why solve DSDP' instead of DSDP", eq. direct-ALM-subproblem): with the
+    multiplier written as D + Xt (eq. shifted-direct-multiplier) and the stale
+    dual iterate y^k entering through A*(y^k) = P(Z^k) (eq. direct-y-projection),
+
+        Psi_dir(Y) = <D + Xt, Z> + sigma/2 ||Z - P(Z^k)||^2,
+
+    i.e. the reduced cost plus sigma/2 ||P(Z - Z^k)||^2 (eq. penalty-decomposition).
+    Its gradient in S is G = Xt + D + sigma (Z - P(Z^k)) and its Hessian in S is
+    sigma I instead of sigma Q (eq. hessian-comparison), so in Y
+        egrad = 2 G Y,   ehess[U] = 2 G U + 2 sigma (Y U^T + U Y^T) Y.
+    yk holds the class averages y^k of Z^k; the projections use its class map.
+    Parity: pinned by the penalty decomposition against the reduced cost, the
+    Hessian difference sigma ||P(Y U^T + U Y^T)||^2, and finite differences."""
+
+    yk: np.ndarray | None = None
+
+    def G(self, Y: np.ndarray) -> np.ndarray:
+        Z = self.Z(Y)
+        PZk = A_adj(self.yk, self.cls, self.w)
+        return self.Xt + self.D + self.sigma * (Z - PZk)
+
+    def cost(self, Y: np.ndarray) -> float:
+        Z = self.Z(Y)
+        E = Z - A_adj(self.yk, self.cls, self.w)
+        return float(np.sum((self.D + self.Xt) * Z) + 0.5 * self.sigma * np.sum(E * E))
+
+    def ehess(self, Y: np.ndarray, U: np.ndarray) -> np.ndarray:
+        Zu = Y @ U.T + U @ Y.T
+        return 2.0 * self.G(Y) @ U + 2.0 * self.sigma * Zu @ Y

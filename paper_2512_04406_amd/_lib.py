@@ -35,7 +35,8 @@ class Options(C.Structure):
                 ("rtr_maxiter", _i32), ("tcg_maxinner", _i32), ("hvp_prec", _i32),
                 ("polish_fp64", _i32), ("polish_eta", _f64), ("eig_tol", _f64), ("eig_maxit", _i32),
                 ("time_limit_s", _f64), ("verbose", _i32), ("seed", _u64),
-                ("resume", _i32), ("escape_when_solved", _i32)]
+                ("resume", _i32), ("escape_when_solved", _i32), ("deflate", _i32),
+                ("direct_admm", _i32), ("rtr_warm_radius", _i32), ("rtr_maxiter_polish", _i32)]
 
 
 class Result(C.Structure):
@@ -54,6 +55,10 @@ SIGNATURES = {
     "mdsdp_bqp_b": (_i32, [_i32, _vp, _vp, _vp]),
     "mdsdp_create_classmap": (_i32, [_i32, _i64, _vp, _vp, _vp, C.POINTER(_vp)]),
     "mdsdp_create_bqp": (_i32, [_i32, _i32, _vp, _vp, C.POINTER(_vp)]),
+    "mdsdp_ucqp_sizes": (_i32, [_i32, _pi32, _pi64]),
+    "mdsdp_ucqp_structure": (_i32, [_i32, _vp, _vp]),
+    "mdsdp_ucqp_b": (_i32, [_i32, _vp, _vp, _vp]),
+    "mdsdp_create_ucqp": (_i32, [_i32, _vp, _vp, C.POINTER(_vp)]),
     "mdsdp_create_sparse_A": (_i32, [_i32, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
     "mdsdp_destroy": (_i32, [_vp]),
     "mdsdp_problem_info": (_i32, [_vp, _pi32, _pi64, _pi64, _pi32]),
@@ -69,10 +74,12 @@ SIGNATURES = {
     "mdsdp_certificate_matvec": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "mdsdp_min_eigpair": (_i32, [_vp, _i32, _f64, _i32, _u64, _vp, _pf64, _vp, _pi32, _vp]),
     "mdsdp_sync_status": (_i32, [_vp, _vp]),
+    "mdsdp_set_direct": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "mdsdp_certificate_estimate": (_i32, [_vp, _f64, _i32, _u64, _vp, _vp, _vp, _pi32, _vp]),
     "mdsdp_adjoint_C": (_i32, [_vp, _vp, _vp]),
     "mdsdp_default_options": (None, [C.POINTER(Options)]),
     "mdsdp_solve": (_i32, [_vp, C.POINTER(Options), _i32, _vp, C.POINTER(Result), _vp, _i32, _vp]),
+    "mdsdp_solve_batch": (_i32, [_i32, _vp, C.POINTER(Options), _vp, _vp, _vp, _i32]),
     "mdsdp_export_classmap": (_i32, [_vp, _vp]),
     "mdsdp_export_multiplier_packed": (_i32, [_vp, _vp]),
     "mdsdp_kernel_times": (_i32, [_vp, _vp, _i32, _pi32]),

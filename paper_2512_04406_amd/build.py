@@ -59,7 +59,7 @@ def build(verbose: bool = False) -> str:
         _run([hipcc, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, "-shared", "--offload-arch=gfx950", *objs, "-o", tmp, "-L/opt/rocm/lib", "-lrocblas",
+    _run([hipcc, "-shared", "--offload-arch=gfx950", *objs, "-o", tmp, "-L/opt/rocm/lib",
           "-Wl,-rpath,/opt/rocm/lib"], verbose)
     os.replace(tmp, LIB)
     return LIB

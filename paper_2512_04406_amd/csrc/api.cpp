@@ -115,6 +115,167 @@ mdsdp_status mdsdp_bqp_classmap(int32_t q, int32_t order, int32_t* cls_out) {
   return MDSDP_OK;
 }
 
+// ---- Hermitian UCQP relaxation (real embedding) -----------------------------
+// An exponent difference alpha - beta of two basis monomials (at most two
+// units each) has at most four nonzero components: kept as (index, value)
+// pairs sorted by index.  Class representatives have their first nonzero
+// component positive; classes are numbered in the ascending order of the
+// representatives as dense integer vectors (the comparator below walks the
+// sparse pairs in that order).
+namespace {
+struct UDiff {
+  int8_t cnt = 0;
+  int16_t idx[4];
+  int8_t val[4];
+};
+bool udiff_less(const UDiff& a, const UDiff& b) {
+  int ia = 0, ib = 0;
+  while (ia < a.cnt || ib < b.cnt) {
+    const int xa = ia < a.cnt ? a.idx[ia] : 1 << 30, xb = ib < b.cnt ? b.idx[ib] : 1 << 30;
+    const int i = std::min(xa, xb);
+    const int va = xa == i ? a.val[ia] : 0, vb = xb == i ? b.val[ib] : 0;
+    if (va != vb) return va < vb;
+    if (xa == i) ++ia;
+    if (xb == i) ++ib;
+  }
+  return false;
+}
+bool udiff_eq(const UDiff& a, const UDiff& b) { return !udiff_less(a, b) && !udiff_less(b, a); }
+// basis monomial t: 1 (t = 0), z_i (t = 1 + i), z_i z_j with i <= j (lex order)
+std::vector<std::pair<int, int>> ucqp_basis(int q) {
+  std::vector<std::pair<int, int>> B{{-1, -1}};
+  for (int i = 0; i < q; ++i) B.push_back({i, -1});
+  for (int i = 0; i < q; ++i)
+    for (int j = i; j < q; ++j) B.push_back({i, j});
+  return B;
+}
+UDiff ucqp_diff(const std::pair<int, int>& a, const std::pair<int, int>& b, int* sign) {
+  int idx[4], val[4], k = 0;
+  auto add = [&](int i, int v) {
+    if (i < 0) return;
+    for (int t = 0; t < k; ++t)
+      if (idx[t] == i) {
+        val[t] += v;
+        return;
+      }
+    idx[k] = i;
+    val[k++] = v;
+  };
+  add(a.first, 1);
+  add(a.second, 1);
+  add(b.first, -1);
+  add(b.second, -1);
+  UDiff d;
+  for (int t = 0; t < k; ++t)
+    if (val[t] != 0) {
+      int u = d.cnt;  // insertion sort by index
+      while (u > 0 && d.idx[u - 1] > idx[t]) {
+        d.idx[u] = d.idx[u - 1];
+        d.val[u] = d.val[u - 1];
+        --u;
+      }
+      d.idx[u] = (int16_t)idx[t];
+      d.val[u] = (int8_t)val[t];
+      ++d.cnt;
+    }
+  *sign = (d.cnt > 0 && d.val[0] < 0) ? -1 : 1;
+  if (*sign < 0)
+    for (int t = 0; t < d.cnt; ++t) d.val[t] = (int8_t)-d.val[t];
+  return d;
+}
+struct UcqpMap {
+  int nc = 0;
+  long long m_re = 0;
+  std::vector<int32_t> rep;  // nc x nc: rank of the representative of (a, c)
+  std::vector<int8_t> sgn;   // nc x nc: +-1
+};
+mdsdp_status ucqp_map(int q, UcqpMap& M) {
+  const auto B = ucqp_basis(q);
+  const int nc = (int)B.size();
+  M.nc = nc;
+  std::vector<UDiff> all;
+  all.reserve((size_t)nc * nc);
+  M.sgn.resize((size_t)nc * nc);
+  for (int a = 0; a < nc; ++a)
+    for (int c = 0; c < nc; ++c) {
+      int sg = 1;
+      all.push_back(ucqp_diff(B[a], B[c], &sg));
+      M.sgn[(size_t)a * nc + c] = (int8_t)sg;
+    }
+  std::vector<UDiff> reps = all;
+  std::sort(reps.begin(), reps.end(), udiff_less);
+  reps.erase(std::unique(reps.begin(), reps.end(), udiff_eq), reps.end());
+  M.m_re = (long long)reps.size();
+  M.rep.resize((size_t)nc * nc);
+  for (size_t e = 0; e < all.size(); ++e) {
+    const auto it = std::lower_bound(reps.begin(), reps.end(), all[e], udiff_less);
+    M.rep[e] = (int32_t)(it - reps.begin());
+  }
+  return MDSDP_OK;
+}
+}  // namespace
+
+mdsdp_status mdsdp_ucqp_sizes(int32_t q, int32_t* n_out, int64_t* m_out) {
+  if (q < 1 || q > 60) return einval("q must be in [1, 60]");
+  const int nc = 1 + q + q * (q + 1) / 2;
+  if (n_out) *n_out = 2 * nc;
+  if (m_out) {
+    UcqpMap M;
+    mdsdp_status st = ucqp_map(q, M);
+    if (st != MDSDP_OK) return st;
+    *m_out = 2 * M.m_re - 1;
+  }
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_ucqp_structure(int32_t q, int32_t* cls_out, int8_t* coef_out) {
+  if (q < 1 || q > 60) return einval("q must be in [1, 60]");
+  if (!cls_out || !coef_out) return einval("NULL argument");
+  UcqpMap M;
+  mdsdp_status st = ucqp_map(q, M);
+  if (st != MDSDP_OK) return st;
+  const int nc = M.nc;
+  const long long n = 2LL * nc;
+  long long idx = 0;
+  for (long long r = 0; r < n; ++r)
+    for (long long c = r; c < n; ++c, ++idx) {
+      const int a = (int)(r % nc), b = (int)(c % nc);
+      const bool rim = r >= nc, cim = c >= nc;
+      const int k = M.rep[(size_t)a * nc + b];
+      if (rim == cim) {  // Re M in both diagonal blocks
+        cls_out[idx] = k;
+        coef_out[idx] = 1;
+      } else if (k == 0) {  // imaginary part of a diagonal-class entry: no class
+        cls_out[idx] = 0;
+        coef_out[idx] = 0;
+      } else {  // (nc + a, b): +s Im M[a][b];  (a, nc + b): -s Im M[a][b]
+        const int s = M.sgn[(size_t)a * nc + b];
+        cls_out[idx] = (int32_t)(M.m_re + k - 1);
+        coef_out[idx] = (int8_t)(rim ? s : -s);
+      }
+    }
+  return MDSDP_OK;
+}
+
+mdsdp_status mdsdp_ucqp_b(int32_t q, const double* Qre, const double* Qim, double* b) {
+  if (q < 1 || q > 60) return einval("q must be in [1, 60]");
+  if (!Qre || !Qim || !b) return einval("NULL argument");
+  UcqpMap M;
+  mdsdp_status st = ucqp_map(q, M);
+  if (st != MDSDP_OK) return st;
+  const long long m = 2 * M.m_re - 1;
+  for (long long g = 0; g < m; ++g) b[g] = 0.0;
+  for (int i = 0; i < q; ++i) b[0] += Qre[(size_t)i * q + i];
+  // class of e_i - e_j (i < j): the pair (z_i, z_j) of basis rows 1 + i, 1 + j
+  for (int i = 0; i < q; ++i)
+    for (int j = i + 1; j < q; ++j) {
+      const int k = M.rep[(size_t)(1 + i) * M.nc + (1 + j)];
+      b[k] += 2.0 * Qre[(size_t)i * q + j];
+      b[M.m_re + k - 1] += 2.0 * Qim[(size_t)i * q + j];
+    }
+  return MDSDP_OK;
+}
+
 mdsdp_status mdsdp_bqp_b(int32_t q, const double* Q, const double* c, double* b) {
   if (q < 1 || q > 362) return einval("q must be in [1, 362]");
   if (!Q || !c || !b) return einval("NULL argument");
@@ -136,8 +297,7 @@ namespace mdsdp {
 
 static void free_problem(mdsdp_problem P) {
   if (!P) return;
-  blas_destroy(P);
-  void* ptrs[] = {P->cls,      P->Xt,     P->Xt32,    P->Ct,      P->segs,   P->seg_start, P->cy,
+  void* ptrs[] = {P->cls,      P->cls32,  P->Xt,     P->Xt32,    P->Ct,      P->segs,   P->seg_start, P->cy,
                   P->Cavg,     P->ab64,   P->ab32,    P->invc,    P->bvec,    P->sacc,   P->Yp,        P->Up,
                   P->bqp4_items, P->bqp1_items, P->bqp2_items, P->bqpP1, P->bqpT, P->bqpStar,
                   P->zvec,     P->zmult,  P->rowpart, P->colpart, P->wgpart, P->zpart,     P->gram,
@@ -315,6 +475,7 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
   TRY(dalloc(&P->cls, P->nslots));
   TRY(dalloc(&P->Xt, P->nslots));
   TRY(dalloc(&P->Xt32, P->nslots));
+  TRY(dalloc(&P->cls32, P->nslots));
   if (C) TRY(dalloc(&P->Ct, P->nslots));
   TRY(dalloc(&P->segs, P->nseg));
   TRY(dalloc(&P->seg_start, P->nb + 1));
@@ -359,6 +520,11 @@ static mdsdp_status create_from_packed(int n, long long m, const int32_t* cls, c
     return s2;                                                   \
   }
   CP(P->cls, hcls.data(), P->nslots * sizeof(uint32_t));
+  {
+    std::vector<uint32_t> h32(P->nslots);
+    for (long long q = 0; q < P->nslots; ++q) h32[slot32((size_t)q)] = hcls[q];
+    CP(P->cls32, h32.data(), P->nslots * sizeof(uint32_t));
+  }
   if (C) CP(P->Ct, hC.data(), P->nslots * sizeof(double));
   CP(P->segs, hseg.data(), hseg.size() * sizeof(Seg));
   CP(P->seg_start, hstart.data(), hstart.size() * sizeof(int));
@@ -502,6 +668,33 @@ mdsdp_status mdsdp_create_bqp(int32_t q, int32_t order, const double* Q, const d
   return MDSDP_OK;
 }
 
+mdsdp_status mdsdp_create_ucqp(int32_t q, const double* Qre, const double* Qim, mdsdp_problem* out) {
+  if (!out) return einval("out is NULL");
+  *out = nullptr;
+  if (q < 1 || q > 60) return einval("q must be in [1, 60]");
+  if (!Qre || !Qim) return einval("Qre and Qim are required");
+  for (long long i = 0; i < (long long)q * q; ++i)
+    if (!std::isfinite(Qre[i]) || !std::isfinite(Qim[i])) {
+      set_error("Q has a non-finite entry at " + std::to_string(i));
+      return MDSDP_ENONFINITE;
+    }
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j)
+      if (Qre[(size_t)i * q + j] != Qre[(size_t)j * q + i] || Qim[(size_t)i * q + j] != -Qim[(size_t)j * q + i])
+        return einval("Q must be Hermitian");
+  int32_t n = 0;
+  int64_t m = 0;
+  mdsdp_status st = mdsdp_ucqp_sizes(q, &n, &m);
+  if (st != MDSDP_OK) return st;
+  const long long ne = (long long)n * (n + 1) / 2;
+  std::vector<int32_t> cls(ne);
+  std::vector<int8_t> coef(ne);
+  std::vector<double> b(m);
+  if ((st = mdsdp_ucqp_structure(q, cls.data(), coef.data())) != MDSDP_OK) return st;
+  if ((st = mdsdp_ucqp_b(q, Qre, Qim, b.data())) != MDSDP_OK) return st;
+  return create_from_packed(n, m, cls.data(), coef.data(), b.data(), nullptr, out);
+}
+
 mdsdp_status mdsdp_create_sparse_A(int32_t n, int64_t m, int64_t nnz, const int32_t* cls, const int32_t* row,
                                    const int32_t* col, const double* val, const double* b, const double* C,
                                    mdsdp_problem* out) {
@@ -572,6 +765,23 @@ mdsdp_status mdsdp_set_multiplier(mdsdp_problem P, const double* Xt_dev, double 
   return launch_set_dense(P, Xt_dev, (hipStream_t)stream);
 }
 
+mdsdp_status mdsdp_set_direct(mdsdp_problem P, int32_t on, int32_t p, const double* Y_dev, void* stream) {
+  if (!P) return einval("problem is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  if (on && Y_dev) {
+    // y^k = class averages of Z^k = Y Y^T + C (the ADMM y-update at Y)
+    mdsdp_status st = check_p(P, p);
+    if (st != MDSDP_OK) return st;
+    P->frozen = false;
+    if ((st = launch_stage(P, p, Y_dev, nullptr, false, s)) != MDSDP_OK) return st;
+    if ((st = launch_classsum_S(P, s)) != MDSDP_OK) return st;
+  }
+  P->frozen = on != 0;
+  P->ycoef_zero = false;
+  P->a32_valid = P->a64_valid = false;
+  return MDSDP_OK;
+}
+
 mdsdp_status mdsdp_sync_status(mdsdp_problem P, void* stream) {
   if (!P) return einval("problem is NULL");
   hipStream_t s = (hipStream_t)stream;
@@ -607,8 +817,10 @@ mdsdp_status mdsdp_cost_grad(mdsdp_problem P, int32_t p, const double* Y, double
   if (!Y) return einval("Y is NULL");
   hipStream_t s = (hipStream_t)stream;
   if ((st = launch_stage(P, p, Y, nullptr, false, s)) != MDSDP_OK) return st;
-  if ((st = launch_classsum_S(P, s)) != MDSDP_OK) return st;
-  if ((st = launch_bty(P, s)) != MDSDP_OK) return st;
+  if (!P->frozen) {  // the direct-DSDP subproblem keeps the stale class averages y^k
+    if ((st = launch_classsum_S(P, s)) != MDSDP_OK) return st;
+    if ((st = launch_bty(P, s)) != MDSDP_OK) return st;
+  }
   if ((st = launch_resid(P, M_GRAD, false, s)) != MDSDP_OK) return st;
   return launch_rowfinal_grad(P, p, Y, egrad, rgrad, f, s);
 }

@@ -41,7 +41,6 @@
 #include <algorithm>
 #include <type_traits>
 
-#include <rocblas/rocblas.h>
 
 #include "mdsdp_internal.hpp"
 
@@ -101,6 +100,7 @@ struct KArgs {
   void* rowpart;
   void* colpart;
   double* wgpart;
+  int frozen;  // direct-DSDP (ADMM) subproblem: y is the stale y^k, and sum D Z is accumulated
 };
 
 constexpr int NWP = 4;  // scalar partials per workgroup
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int c = 0; c < NC; ++c) accC[i][c] = v4{0, 0, 0, 0};
-  double p_r2 = 0.0, p_xz = 0.0, p_cx = 0.0;
+  double p_r2 = 0.0, p_xz = 0.0, p_cx = 0.0, p_dz = 0.0;
   T* tAw = tA + w * L::tbuf;
   T* tBw = tB + w * L::tbuf;
 
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
         if (sizeof(XT) == 8)
           xv[sc][v] = (XT)a.Xt[off];
         else
-          xv[sc][v] = (XT)a.Xt32[off];
+          xv[sc][v] = (XT)a.Xt32[slot32(off)];
       }
     double2 dyv[4][4];  // {D, y}, or for the HVP {D - sigma y, -sigma y'}
 #pragma unroll
@@ -415,12 +415,13 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
             p_r2 += wgt * r * r;
             if (MODE == M_GRAD) {
               p_xz += wgt * x * Zv;
+              p_dz += wgt * dy.x * Zv;  // <D, Z> (the cost's first term when y is stale)
               av = (T)(x + dy.x + sigma * r);
             } else {
               const double xn = x + sigma * r;
               if (lead) {
                 a.Xt_out[off] = xn;
-                a.Xt32[off] = (float)xn;
+                a.Xt32[slot32(off)] = (float)xn;
               }
               p_cx += wgt * Ce * (xn + dy.x);
               av = (T)(xn + dy.x);
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
     }
   }
   if ((MODE == M_GRAD || MODE == M_MULT) && lead) {
-    double vals[NWP] = {p_r2, p_xz, 0.0, p_cx};
+    double vals[NWP] = {p_r2, p_xz, p_dz, p_cx};
     for (int qq = 0; qq < NWP; ++qq) {
       __syncthreads();
       red[tid] = vals[qq];
@@ -526,7 +527,7 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
 // share the entry and class reads through that XCD's L2.
 // ---------------------------------------------------------------------------
 struct H32Args {
-  const uint32_t* cls;
+  const uint32_t* cls32;  // class words in FP32-tile order (slot32)
   const float* Xt32;
   const double* Ct;
   const Seg* segs;
@@ -591,15 +592,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SW == 16 ? 
   float yrv[RPT], urv[RPT];
   auto load_tile = [&](int I) {
     const long long t = (long long)sg.J * (sg.J + 1) / 2 + I;
-    const size_t tb = (size_t)t * TSLOTS + (size_t)(w * 4) * 256 + li;
+    // FP32-tile order: this lane's four entries (rows 4 lk .. 4 lk + 3 of
+    // column li in each sub-block) are one 16-byte vector
+    const size_t tb32 = (size_t)t * TSLOTS + (size_t)(w * 4) * 256 + li * 16 + 4 * lk;
 #pragma unroll
-    for (int sc = 0; sc < 4; ++sc)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const size_t off = tb + sc * 256 + (4 * lk + v) * 16;
-        cwv[sc][v] = a.cls[off];
-        xv[sc][v] = a.Xt32[off];
-      }
+    for (int sc = 0; sc < 4; ++sc) {
+      const uint4 cw4 = *(const uint4*)(a.cls32 + tb32 + sc * 256);
+      const float4 x4 = *(const float4*)(a.Xt32 + tb32 + sc * 256);
+      cwv[sc][0] = cw4.x;
+      cwv[sc][1] = cw4.y;
+      cwv[sc][2] = cw4.z;
+      cwv[sc][3] = cw4.w;
+      xv[sc][0] = x4.x;
+      xv[sc][1] = x4.y;
+      xv[sc][2] = x4.z;
+      xv[sc][3] = x4.w;
+    }
     if (PREF_ROWS) {
 #pragma unroll
       for (int e = 0; e < RPT; ++e) {
@@ -939,7 +947,7 @@ __global__ __launch_bounds__(256) void k_row_xmv(RowArgs ra, const double* __res
 __global__ __launch_bounds__(256) void k_scalars(int mode, const double* __restrict__ wgpart, int nseg,
                                                  const double* __restrict__ zpart, int nz,
                                                  const double* __restrict__ btypart, int nbty, double sigma,
-                                                 double* scal, double* f_out, double* kkt_out) {
+                                                 double* scal, double* f_out, double* kkt_out, int frozen) {
   __shared__ double red[256];
   double acc[NWP + 1];
   for (int q = 0; q < NWP; ++q) {
@@ -976,7 +984,9 @@ __global__ __launch_bounds__(256) void k_scalars(int mode, const double* __restr
     scal[SC_XZ] = xz;
     scal[SC_BTY] = bty;
     if (mode == M_GRAD) {
-      const double f = bty + xz + 0.5 * sigma * r2;
+      // <D, Z> = b^T y(S) (section 3 opening); with a stale y (direct-DSDP
+      // subproblem) it is accumulated entry by entry instead
+      const double f = (frozen ? tot[2] : bty) + xz + 0.5 * sigma * r2;
       scal[SC_F] = f;
       if (!isfinite(f)) scal[SC_NONFIN] = 1.0;
       if (f_out) *f_out = f;
@@ -1133,7 +1143,7 @@ __global__ __launch_bounds__(256) void k_set_dense(int n, int nb, long long nslo
   if (r < n && c < n) v = X ? X[(size_t)r * n + c] : 0.0;
   if (!isfinite(v)) *nonfin = 1.0;  // sticky non-finite flag
   Xt[s] = v;
-  Xt32[s] = (float)v;
+  Xt32[slot32(s)] = (float)v;
 }
 
 __global__ __launch_bounds__(256) void k_get_dense(int n, int nb, long long nslots, const double* __restrict__ Xt,
@@ -1206,6 +1216,16 @@ __global__ __launch_bounds__(256) void k_vt_w(int n, const double* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) h[j] = red[0];
+}
+
+// QT = Q^T for a row-major n x r Q (QT row-major r x n), 16 x 16 tiles via LDS
+__global__ __launch_bounds__(256) void k_transpose(int n, int r, const double* __restrict__ Q, double* __restrict__ QT) {
+  __shared__ double t[16][17];
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  if (i0 + ty < n && j0 + tx < r) t[ty][tx] = Q[(size_t)(i0 + ty) * r + j0 + tx];
+  __syncthreads();
+  if (j0 + ty < r && i0 + tx < n) QT[(size_t)(j0 + ty) * n + i0 + tx] = t[tx][ty];
 }
 
 __global__ __launch_bounds__(256) void k_lincomb(long long len, double alpha, const double* __restrict__ x,
@@ -1423,6 +1443,14 @@ __global__ __launch_bounds__(256) void k_final_Z32(long long m, long long* __res
 }
 
 // FP32-tile HVP: class coefficient D - sigma y of U (y of the last S-pass)
+// direct-DSDP subproblem: its Hessian in S is sigma I (no projection), so the
+// class coefficient of Y in the HVP is zero
+__global__ __launch_bounds__(256) void k_zero_ycoef(long long m, double2* __restrict__ ab64, float2* __restrict__ ab32) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= m) return;
+  ab64[g].y = 0.0;
+  ab32[g].y = 0.0f;
+}
 __global__ __launch_bounds__(256) void k_make_a32(long long m, const double2* __restrict__ cy, double sigma,
                                                   float2* __restrict__ ab32) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2082,6 +2110,7 @@ static KArgs make_args(mdsdp_problem P) {
   a.rowpart = P->rowpart;
   a.colpart = P->colpart;
   a.wgpart = P->wgpart;
+  a.frozen = P->frozen ? 1 : 0;
   return a;
 }
 
@@ -2231,6 +2260,16 @@ mdsdp_status launch_classsum_S(mdsdp_problem P, hipStream_t s) {
 }
 
 mdsdp_status launch_classsum_Z(mdsdp_problem P, bool fp32, hipStream_t s) {
+  if (P->frozen) {
+    // direct-DSDP subproblem: no class sums of Y U^T + U Y^T; zero coefficients once
+    if (!P->ycoef_zero) {
+      k_zero_ycoef<<<blocks_for(P->m, 256), 256, 0, s>>>(P->m, P->ab64, P->ab32);
+      MDSDP_HIP(hipGetLastError());
+      P->ycoef_zero = true;
+    }
+    return MDSDP_OK;
+  }
+  P->ycoef_zero = false;
   timer_begin(P, s, fp32 ? "classsum_Z32" : "classsum_Z64");
   if (P->bqp_q > 0) {
     mdsdp_status st = launch_bqp(P, true, fp32, s);
@@ -2330,7 +2369,7 @@ mdsdp_status launch_hvp32(mdsdp_problem P, hipStream_t s) {
     P->a32_valid = true;
   }
   H32Args a{};
-  a.cls = P->cls;
+  a.cls32 = P->cls32;
   a.Xt32 = P->Xt32;
   a.Ct = P->Ct;
   a.segs = P->segs;
@@ -2373,67 +2412,106 @@ static RowArgs row_args(mdsdp_problem P, int p) {
   return ra;
 }
 
-// rocBLAS handle of the problem on stream s (created on first use); the plain
-// FP64 GEMMs of wide factors (Gram matrices, low-rank HVP term) go through it,
-// with atomics off so that the results are reproducible.
-static mdsdp_status blas_on(mdsdp_problem P, hipStream_t s, rocblas_handle* h) {
-  if (!P->blas) {
-    rocblas_handle nh = nullptr;
-    if (rocblas_create_handle(&nh) != rocblas_status_success) {
-      set_error("rocblas_create_handle failed");
-      return MDSDP_EHIP;
+// Wide factors (p > 64): the Gram matrices and the low-rank HVP term are
+// plain FP64 GEMMs, done by the two MFMA kernels below (no vendor library).
+//
+// k_gemm_tn_part: partial[c] = A^T B over the rows of chunk c (A, B row-major
+// n x p); one wave per 64 x 64 output macro-block and chunk, a 4 x 4 grid of
+// 16 x 16 MFMA tiles fed by one A and one B fragment of 4 rows per tile row /
+// column; partial[c] is row-major with pitch pw inside the Gram partial layout
+// (stride 2 pw^2 between chunks), added in a fixed order by k_gram_final.
+__global__ __launch_bounds__(256) void k_gemm_tn_part(int n, int p, int pw, int rows, int nmb,
+                                                      const double* __restrict__ A, const double* __restrict__ B,
+                                                      double* __restrict__ part) {
+  const int wid = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int chunk = blockIdx.y;
+  if (wid >= nmb * nmb) return;
+  const int I0 = (wid / nmb) * 64, J0 = (wid % nmb) * 64;
+  const int r0 = chunk * rows, r1 = min(n, r0 + rows);
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+  for (int r = r0; r < r1; r += 4) {
+    const int rr = r + lk;
+    const bool rin = rr < r1;
+    double fa[4], fb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int ci = I0 + 16 * a + li, cj = J0 + 16 * a + li;
+      fa[a] = (rin && ci < p) ? A[(size_t)rr * p + ci] : 0.0;
+      fb[a] = (rin && cj < p) ? B[(size_t)rr * p + cj] : 0.0;
     }
-    (void)rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed);
-    P->blas = (void*)nh;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = mfma(fa[a], fb[b], acc[a][b]);
   }
-  *h = (rocblas_handle)P->blas;
-  if (rocblas_set_stream(*h, s) != rocblas_status_success) {
-    set_error("rocblas_set_stream failed");
-    return MDSDP_EHIP;
-  }
-  return MDSDP_OK;
+  double* out = part + (size_t)chunk * 2 * pw * pw;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = I0 + 16 * a + drow<double>(lk, v), j = J0 + 16 * b + li;
+        if (i < pw && j < pw) out[(size_t)i * pw + j] = acc[a][b][v];
+      }
 }
 
-void blas_destroy(mdsdp_problem P) {
-  if (P->blas) (void)rocblas_destroy_handle((rocblas_handle)P->blas);
-  P->blas = nullptr;
+// k_lowrank: LR = Y (Y^T U + U^T Y) + U (Y^T Y) (n x p row-major), with
+// Y^T Y at gram and Y^T U at gram + GRAM_U (pitch gp): one wave per 16 rows
+// and 64 output columns, contraction over 2p (the Y part, then the U part).
+__global__ __launch_bounds__(256) void k_lowrank(int n, int p, int gp, const double* __restrict__ Y,
+                                                 const double* __restrict__ U, const double* __restrict__ gram,
+                                                 double* __restrict__ LR) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int R0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16, K0 = blockIdx.y * 64;
+  if (R0 >= n) return;
+  const double* YtY = gram;
+  const double* YtU = gram + GRAM_U;
+  v4d acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = v4d{0, 0, 0, 0};
+  const int row = R0 + li;
+  for (int part = 0; part < 2; ++part) {
+    const double* F = part == 0 ? Y : U;
+    for (int t0 = 0; t0 < p; t0 += 4) {
+      const int t = t0 + lk;
+      const double fa = (row < n && t < p) ? F[(size_t)row * p + t] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k = K0 + 16 * c + li;
+        double fb = 0.0;
+        if (t < p && k < p)
+          fb = part == 0 ? YtU[(size_t)k * gp + t] + YtU[(size_t)t * gp + k] : YtY[(size_t)t * gp + k];
+        acc[c] = mfma(fa, fb, acc[c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = R0 + drow<double>(lk, v), k = K0 + 16 * c + li;
+      if (r < n && k < p) LR[(size_t)r * p + k] = acc[c][v];
+    }
 }
 
-#define BLAS_CHK(x)                              \
-  do {                                           \
-    if ((x) != rocblas_status_success) {         \
-      set_error(std::string("rocBLAS: ") + #x);  \
-      return MDSDP_EHIP;                         \
-    }                                            \
-  } while (0)
-
-// Row-major n x p factors are column-major p x n matrices with leading
-// dimension p.  C = A^T B (p x p, row-major with pitch pw) is, in column-major
-// terms, C^T = B^c (A^c)^T: dgemm(N, T, p, p, n, B, A).  The sum over the n
-// rows is split into nch chunks (one strided-batched call, each chunk's
-// product into its own partial of the Gram partial layout, offset `half`),
-// then added in a fixed order by k_gram_final.
-static mdsdp_status gram_blas(mdsdp_problem P, int p, int pw, int& nch, const double* A, const double* B,
+// Gram partials of A^T B for wide factors: the rows in nch chunks (one chunk's
+// product per partial, offset `half` in the Gram partial layout)
+static mdsdp_status gram_wide(mdsdp_problem P, int p, int pw, int& nch, const double* A, const double* B,
                               size_t half, hipStream_t s) {
-  rocblas_handle h;
-  mdsdp_status st = blas_on(P, s, &h);
-  if (st != MDSDP_OK) return st;
-  const double one = 1.0, zero = 0.0;
   const int n = P->n;
   int rows = (n + nch - 1) / nch;
-  if (n - (nch - 1) * rows < 1) {  // (not reached for nch <= ceil(n / 64))
-    nch = 1;
-    rows = n;
-  }
-  const int last = n - (nch - 1) * rows;
-  double* part = P->gpart + GP_GRAM + half;
-  const rocblas_stride sp = (rocblas_stride)2 * pw * pw, sy = (rocblas_stride)rows * p;
-  if (nch > 1)
-    BLAS_CHK(rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, p, p, rows, &one,
-                                           B, p, sy, A, p, sy, &zero, part, pw, sp, nch - 1));
-  BLAS_CHK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, p, p, last, &one,
-                         B + (size_t)(nch - 1) * rows * p, p, A + (size_t)(nch - 1) * rows * p, p, &zero,
-                         part + (size_t)(nch - 1) * sp, pw));
+  rows = (rows + 3) & ~3;
+  nch = (n + rows - 1) / rows;
+  const int nmb = (p + 63) / 64;
+  k_gemm_tn_part<<<dim3(blocks_for((long long)nmb * nmb, 4), nch), 256, 0, s>>>(n, p, pw, rows, nmb, A, B,
+                                                                                 P->gpart + GP_GRAM + half);
+  MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
 
@@ -2448,8 +2526,8 @@ mdsdp_status launch_gram(mdsdp_problem P, int p, const double* Y, const double* 
     int nch = (int)std::max<size_t>(1, std::min<size_t>({64, GRAM_PART_MAX / (2 * pw2),
                                                                (size_t)(P->n + 63) / 64}));
     mdsdp_status st = MDSDP_OK;
-    if (with_yy) st = gram_blas(P, p, gpw, nch, Y, Y, 0, s);
-    if (st == MDSDP_OK) st = gram_blas(P, p, gpw, nch, Y, U, pw2, s);
+    if (with_yy) st = gram_wide(P, p, gpw, nch, Y, Y, 0, s);
+    if (st == MDSDP_OK) st = gram_wide(P, p, gpw, nch, Y, U, pw2, s);
     if (st != MDSDP_OK) return st;
     const int len = (int)(2 * pw2), e0 = with_yy ? 0 : (int)pw2;
     k_gram_final<<<blocks_for(len - e0, 256), 256, 0, s>>>(nch, len, e0, P->gpart + GP_GRAM, P->gram, gpw, 1);
@@ -2489,7 +2567,7 @@ mdsdp_status launch_rowfinal_grad(mdsdp_problem P, int p, const double* Y, doubl
   else
     k_row_grad<8><<<nblk, 256, 0, s>>>(ra, Y, egrad, rgrad, P->zvec);
   k_scalars<<<1, 256, 0, s>>>(M_GRAD, P->wgpart, P->nseg, nullptr, 0, P->gpart + GP_BTY, 64, P->sigma, P->scal, f,
-                              nullptr);
+                              nullptr, P->frozen ? 1 : 0);
   timer_end(P, s);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
@@ -2502,20 +2580,10 @@ mdsdp_status launch_rowfinal_hvp(mdsdp_problem P, int p, bool fp32, const double
   const unsigned nblk = blocks_for((long long)P->n * 64, 256);  // L * SPL = 64 lanes per row
   const double* lr = nullptr;
   if (p > 64) {
-    // LR = Y (Y^T U + U^T Y) + U (Y^T Y); column-major: LR^c = M^T Y^c + M Y^c
-    // + (Y^T Y) U^c with M^c = the stored Y^T U (pitch gram_pw)
-    rocblas_handle h;
-    mdsdp_status st = blas_on(P, s, &h);
-    if (st != MDSDP_OK) return st;
-    const double one = 1.0, zero = 0.0;
-    const int gp = P->gram_pw, n = P->n;
-    const double* M = P->gram + GRAM_U;
-    BLAS_CHK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, p, n, p, &one, M, gp, Y, p, &zero,
-                           P->lrbuf, p));
-    BLAS_CHK(rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, p, n, p, &one, M, gp, Y, p, &one,
-                           P->lrbuf, p));
-    BLAS_CHK(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, p, n, p, &one, P->gram, gp, U, p, &one,
-                           P->lrbuf, p));
+    // LR = Y (Y^T U + U^T Y) + U (Y^T Y) by an MFMA kernel (k_lowrank)
+    const int n = P->n;
+    k_lowrank<<<dim3(blocks_for(n, 64), (p + 63) / 64), 256, 0, s>>>(n, p, P->gram_pw, Y, U, P->gram, P->lrbuf);
+    MDSDP_HIP(hipGetLastError());
     lr = P->lrbuf;
   }
   const int rm = P->pw <= 64 ? 1 : P->pw / 64;
@@ -2554,7 +2622,7 @@ mdsdp_status launch_rowfinal_mult(mdsdp_problem P, int p, const double* Y, doubl
   const unsigned nblk = blocks_for((long long)P->n * std::min(P->pw, 64), 256);
   k_row_mult<<<nblk, 256, 0, s>>>(ra, Y, P->zmult, z, P->zpart);
   k_scalars<<<1, 256, 0, s>>>(M_MULT, P->wgpart, P->nseg, P->zpart, (int)nblk, P->gpart + GP_BTY, 64, P->sigma,
-                              P->scal, nullptr, kkt);
+                              P->scal, nullptr, kkt, 0);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
@@ -2664,6 +2732,47 @@ mdsdp_status launch_gemv_sub(int n, int k, const double* V, const double* h, dou
   return MDSDP_OK;
 }
 
+// Lanczos step on the device: alpha_j = h[j] + h2[j] (the two reorthogonal-
+// isation passes), beta_j^2 = <w, w>; v_{j+1} = w / beta_j (zeros when beta_j
+// vanishes: the host stops at that step)
+__global__ __launch_bounds__(256) void k_lanczos_step(int n, int j, const double* __restrict__ h,
+                                                      const double* __restrict__ h2, const double* __restrict__ nrm2,
+                                                      double* __restrict__ alpha, double* __restrict__ beta2,
+                                                      const double* __restrict__ w, double* __restrict__ vnext) {
+  const double b2 = *nrm2;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    alpha[j] = h[j] + h2[j];
+    beta2[j] = b2;
+  }
+  if (!vnext) return;
+  const double inv = b2 > 0.0 ? 1.0 / sqrt(b2) : 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) vnext[i] = w[i] * inv;
+}
+
+mdsdp_status launch_lanczos_step(int n, int j, const double* h, const double* h2, const double* nrm2, double* alpha,
+                                 double* beta2, const double* w, double* vnext, bool write_next, hipStream_t s) {
+  k_lanczos_step<<<blocks_for(n, 256), 256, 0, s>>>(n, j, h, h2, nrm2, alpha, beta2, w, write_next ? vnext : nullptr);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_transpose(int n, int r, const double* Q, double* QT, hipStream_t s) {
+  k_transpose<<<dim3(blocks_for(n, 16), blocks_for(r, 16)), 256, 0, s>>>(n, r, Q, QT);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_deflate(int n, int r, const double* QT, double* w, double* c, hipStream_t s) {
+  // w <- (I - Q Q^T) w with QT = Q^T (r x n), twice (classical Gram-Schmidt
+  // with one refinement)
+  for (int pass = 0; pass < 2; ++pass) {
+    mdsdp_status st = launch_vt_w(n, r, QT, w, c, s);
+    if (st == MDSDP_OK) st = launch_gemv_sub(n, r, QT, c, w, s);
+    if (st != MDSDP_OK) return st;
+  }
+  return MDSDP_OK;
+}
+
 mdsdp_status launch_gemv(int n, int k, const double* V, const double* sv, double* out, hipStream_t s) {
   k_gemv<<<blocks_for(n, 256), 256, 0, s>>>(n, k, V, sv, out);
   MDSDP_HIP(hipGetLastError());
@@ -2675,5 +2784,7 @@ mdsdp_status vec_fill(long long len, double v, double* out, hipStream_t s) {
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }
+
+
 
 }  // namespace mdsdp

@@ -38,6 +38,14 @@ constexpr int STAR_LG = 32;     // residue classes of l in the degree-2 BQP cont
 // class word of a slot: bit 31 padding slot (outside the matrix), bit 30
 // first slot of its class, bit 29 coefficient -1 in A_gamma, bit 28 no class
 // (coefficient 0: A*(y) is zero there), bits 0..27 the class id
+// FP32-tile order of a slot: inside each 16 x 16 sub-block the entry
+// (r, c) moves from r * 16 + c to c * 16 + r, so that the four entries an
+// FP32 MFMA result lane holds (rows 4 lk .. 4 lk + 3 of column li) are
+// consecutive and load as one 16-byte vector
+__host__ __device__ inline size_t slot32(size_t s) {
+  const size_t e = s & 255;
+  return (s & ~(size_t)255) | ((e & 15) << 4) | (e >> 4);
+}
 constexpr uint32_t CLS_MASK = 0x0FFFFFFFu;
 constexpr uint32_t OWNER_BIT = 0x40000000u;
 constexpr uint32_t NEG_BIT = 0x20000000u;
@@ -91,7 +99,8 @@ struct mdsdp_problem_s {
   uint32_t* cls = nullptr;      // nslots class words
   double* Xt = nullptr;         // nslots
   double* Xt2 = nullptr;        // nslots, second multiplier buffer of the sliced update (allocated on first use)
-  float* Xt32 = nullptr;        // nslots (FP32 shadow, refreshed on every Xt write)
+  float* Xt32 = nullptr;        // nslots (FP32 shadow, refreshed on every Xt write), FP32-tile order
+  uint32_t* cls32 = nullptr;    // nslots: the class words again, in FP32-tile order
   double* Ct = nullptr;         // nslots or null
   mdsdp::Seg* segs = nullptr;   // nseg
   int* seg_start = nullptr;     // nb + 1: segments of column block J are seg_start[J]..seg_start[J+1]-1
@@ -137,7 +146,8 @@ struct mdsdp_problem_s {
   int gram_yy_p = 0;           // factor width of that Y^T Y
   int last_hvp_prec = -1;      // tile precision of the last mdsdp_hvp call
   double* lrbuf = nullptr;     // n x PMAX: low-rank part of the HVP for p > 64
-  void* blas = nullptr;        // rocBLAS handle (wide-factor GEMMs), created on first use
+  bool frozen = false;        // direct-DSDP (ADMM) subproblem: stale y, Hessian sigma I in S
+  bool ycoef_zero = false;    // HVP class coefficients of Y zeroed (frozen mode)
   // solver / Lanczos workspace
   double* dotpart = nullptr;
   const double** dotptr = nullptr;  // unused (kept for layout stability)
@@ -206,7 +216,6 @@ mdsdp_status launch_rowfinal_mult(mdsdp_problem P, int p, const double* Y, doubl
                                   double* kkt, hipStream_t s);
 mdsdp_status launch_rowfinal_xmv(mdsdp_problem P, int k, const double* V, double* XV,
                                  hipStream_t s);
-void blas_destroy(mdsdp_problem P);
 mdsdp_status launch_retract(int n, int p, const double* Y, const double* V, double t,
                             double* Yout, hipStream_t s);
 mdsdp_status launch_project(int n, int p, const double* Y, const double* U, double* out,
@@ -240,6 +249,14 @@ mdsdp_status launch_set_col(int n, int p, int col, const double* v, double* U, h
                            bool zero_rest = true);
 mdsdp_status launch_gemv_sub(int n, int k, const double* V, const double* h, double* w, hipStream_t s);
 mdsdp_status launch_gemv(int n, int k, const double* V, const double* sv, double* out, hipStream_t s);
+// one Lanczos step's scalars and normalisation on the device (see solver.cpp)
+mdsdp_status launch_lanczos_step(int n, int j, const double* h, const double* h2, const double* nrm2, double* alpha,
+                                 double* beta2, const double* w, double* vnext, bool write_next, hipStream_t s);
+// QT = Q^T (Q row-major n x r, QT row-major r x n)
+mdsdp_status launch_transpose(int n, int r, const double* Q, double* QT, hipStream_t s);
+// w <- (I - Q Q^T) w for Q with orthonormal columns, given as QT = Q^T (r x n);
+// c: r doubles of scratch
+mdsdp_status launch_deflate(int n, int r, const double* QT, double* w, double* c, hipStream_t s);
 
 void timer_begin(mdsdp_problem P, hipStream_t s, const char* name);
 void timer_end(mdsdp_problem P, hipStream_t s);

@@ -16,21 +16,27 @@
 //    is used.  Optional stall cap (gtol_stall > 0): after an RTR call that
 //    starts below its tolerance every later tolerance is at most
 //    gtol_stall ||grad||;
-//  * the certificate Lanczos starts from the previous Ritz vector plus a
-//    random component and stops when the error estimate of theta_min
-//    (residual, or residual^2 / Ritz gap) is below eig_tol (1 + |theta_max|);
-//    when it stops unconverged, eta_d uses theta_min minus that estimate, and
-//    when eta_d is then the only residual above the tolerance the step budget
-//    of the next eigensolve doubles (up to n);
-//  * eq. sec5:eq1 is applied as printed after every outer step (option
-//    sigma_hold, off by default, skips its decrease branch after an RTR call
-//    that stopped at its iteration cap);
+//  * the certificate Lanczos (deflated against range(Y), see the outer loop)
+//    starts from the previous Ritz vector plus a random component and stops
+//    when the error estimate of theta_min (residual, or residual^2 / certified
+//    gap) is below eig_tol (1 + |theta_max|), or once theta_min minus that
+//    estimate is >= 0; when it stops unconverged, eta_d uses theta_min minus
+//    the estimate, and when eta_d is then at least half the largest residual
+//    the step budget of the next eigensolve doubles (up to n);
+//  * eq. sec5:eq1 after every outer step, except that (option sigma_hold, on
+//    by default) its decrease branch is skipped after an RTR call that stopped
+//    at its iteration budget: ||grad|| then measures an unfinished inner
+//    solve, not a dual residual, and with a 10-step budget the printed rule
+//    drives sigma down on every step of a large instance;
+//  * inner budget: rtr_maxiter (10) RTR iterations per subproblem until
+//    eta_max < polish_eta (1e-4), rtr_maxiter_polish (50) after that, when the
+//    HVPs also switch to FP64 (polish_fp64);
 //  * carried direction: backtracking t = sqrt(n), sqrt(n)/2, ... along
-//    R_[Y,0](t [0, v]) until Psi_k decreases, then RTR.  With
-//    escape_when_solved (default) the direction, and the zero columns it
-//    needs, are formed only after an RTR call that reached its tolerance: the
-//    paper brings in Theorem sec5:thm1 to leave stationary points whose
-//    certificate is not PSD, and an unfinished subproblem is not one;
+//    R_[Y,0](t [0, v]) until Psi_k decreases, then RTR.  By default the
+//    direction and its zero columns are added after every outer step whose
+//    certificate curvature is below -max(1e-12, tol) (1 + |lambda_max|)
+//    (step 9 of Algorithm alg1); escape_when_solved restricts that to steps
+//    whose RTR call reached its tolerance;
 //  * rank rule: drop singular directions of Y below tau_rank * s_1, then add
 //    one zero column per carried negative eigenvector (at most n_neg per
 //    outer step, p <= p_max);
@@ -39,8 +45,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdio>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -277,14 +285,14 @@ mdsdp_status read_dev(mdsdp_problem P, const double* dev, int cnt, double* host,
 struct Work {
   int n = 0;
   double* buf = nullptr;
-  double *Ynew, *g, *gnew, *eta, *Heta, *r, *d, *Hd, *U, *tmp, *part, *dpart, *rrb;
+  double *Ynew, *g, *gnew, *eta, *Heta, *r, *d, *Hd, *U, *tmp, *part, *dpart, *rrb, *qc;
   TcgIter it2;  // the second truncated-CG iterate (double buffering)
   hipEvent_t ev[2] = {nullptr, nullptr};
   mdsdp_status init(int n_) {
     n = n_;
     const size_t vec = (size_t)n * PMAX;
     const size_t npart = (size_t)n / 4 + 64;  // tCG partials: one per 256 threads of 64-lane rows
-    hipError_t e = hipMalloc((void**)&buf, (15 * vec + 2 * npart + 96) * sizeof(double));
+    hipError_t e = hipMalloc((void**)&buf, (15 * vec + 2 * npart + 96 + PMAX) * sizeof(double));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(solver work)");
     double* p = buf;
     Ynew = p; p += vec;
@@ -304,7 +312,8 @@ struct Work {
     it2.Hd = p; p += vec;
     part = p; p += npart;
     dpart = p; p += npart;
-    rrb = p;
+    rrb = p;  // 96 doubles of tCG scalars, then PMAX of deflation coefficients
+    qc = p + 96;
     for (auto& x : ev)
       if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
     return MDSDP_OK;
@@ -426,14 +435,16 @@ mdsdp_status tcg(mdsdp_problem P, int p, const double* Y, const double* g, doubl
 struct RTRState {
   double f = 0, gn = 0;
   int iters = 0;
+  double Delta0 = 0.0;  // in: initial radius (0: Delta_bar / 8); out: the final radius
 };
 
 mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, int maxinner, int prec,
-                 Work& W, Counters& C, RTRState& st, hipStream_t s, int verbose = 0) {
+                 Work& W, Counters& C, RTRState& st, hipStream_t s, int verbose = 0,
+                 clk::time_point deadline = clk::time_point::max()) {
   const int n = P->n;
   const long long len = (long long)n * p;
   const double Delta_bar = M_PI * sqrt((double)n);
-  double Delta = Delta_bar / 8.0;
+  double Delta = st.Delta0 > 0.0 ? std::min(st.Delta0, Delta_bar) : Delta_bar / 8.0;
   double f;
   CHK(eval(P, p, Y, W.g, &f, C, s));
   double gg;
@@ -483,10 +494,15 @@ mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, i
       CHK(eval(P, p, Y, W.g, &fcur, C, s));
     }
     C.rtr_iters++;
+    if (clk::now() > deadline) {
+      ++it;
+      break;
+    }
   }
   st.f = f;
   st.gn = gn;
   st.iters = it;
+  st.Delta0 = Delta;
   return MDSDP_OK;
 }
 
@@ -502,10 +518,12 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
                             double* evec, int* iters, bool* converged, hipStream_t s, int nvec = 1,
                             double neg_rel = 0.0, int* nfound = nullptr, const double* warm = nullptr,
                             double* resid_out = nullptr, bool use_gap = false, int kconv = 1,
-                            double* evals_out = nullptr, double* ext = nullptr) {
+                            double* evals_out = nullptr, double* ext = nullptr, const double* Qd = nullptr,
+                            int rq = 0, double* qc = nullptr, bool stop_nonneg = false,
+                            double stop_above = 0.0) {
   const int n = P->n;
   maxit = std::max(2, std::min(maxit, n));
-  // basis V (n x (maxit + 1)), w (n), h (2 maxit + 8): the caller's fixed
+  // basis V (n x (maxit + 1)), w (n), h (4 maxit + 16): the caller's fixed
   // scratch `ext` if given, else buffers of the problem (grown on demand)
   if (!ext && P->lz_cap < maxit + 1) {
     if (P->lz_V) (void)hipFree(P->lz_V);
@@ -514,7 +532,7 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
     P->lz_cap = maxit + 1;
     if (!P->lz_w) MDSDP_HIP(hipMalloc((void**)&P->lz_w, (size_t)n * sizeof(double)));
     if (P->lz_h) (void)hipFree(P->lz_h);
-    MDSDP_HIP(hipMalloc((void**)&P->lz_h, (size_t)(2 * maxit + 8) * sizeof(double)));
+    MDSDP_HIP(hipMalloc((void**)&P->lz_h, (size_t)(4 * maxit + 16) * sizeof(double)));
   }
   double* V = ext ? ext : P->lz_V;
   double* w = ext ? ext + (size_t)n * (maxit + 1) : P->lz_w;
@@ -543,67 +561,109 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
       for (double& x : v0) x /= t;
     }
   }
-  MDSDP_HIP(hipMemcpyAsync(V, v0.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  // host-to-device copies go through the problem's pinned buffer (n doubles
+  // fit: n < 65536 <= HBUF_LEN - 64), so no pageable staging is involved
+  memcpy(P->hbuf + 64, v0.data(), n * sizeof(double));
+  MDSDP_HIP(hipMemcpyAsync(V, P->hbuf + 64, n * sizeof(double), hipMemcpyHostToDevice, s));
+  if (Qd && rq > 0) {
+    // deflation (Qd = Q^T, rq x n): the Krylov space is kept orthogonal to range(Q), so the run
+    // sees the compression of X to the complement of range(Q); the start is
+    // projected and renormalised
+    CHK(launch_deflate(n, rq, Qd, V, qc, s));
+    CHK(launch_vt_w(n, 1, V, V, h, s));
+    double nn;
+    MDSDP_HIP(hipMemcpyAsync(P->hbuf, h, sizeof(double), hipMemcpyDeviceToHost, s));
+    MDSDP_HIP(hipStreamSynchronize(s));
+    nn = P->hbuf[0];
+    if (!(nn > 0.0)) {
+      set_error("deflated Lanczos start vector vanished");
+      return MDSDP_EINVAL;
+    }
+    CHK(vec_lincomb(n, 1.0 / sqrt(nn), V, 0.0, nullptr, V, s));
+  }
   MDSDP_HIP(hipStreamSynchronize(s));
   std::vector<double> al, be;
   std::vector<double> sv;
   double th_min = 0, th_max = 0;
   int k = 0;
   *converged = false;
-  for (int j = 0; j < maxit; ++j) {
-    double* vj = V + (size_t)j * n;
-    CHK(mdsdp_certificate_matvec(P, 1, vj, w, s));
-    // full reorthogonalisation, twice (classical Gram-Schmidt with refinement)
-    CHK(launch_vt_w(n, j + 1, V, w, h, s));
-    CHK(launch_gemv_sub(n, j + 1, V, h, w, s));
-    CHK(launch_vt_w(n, j + 1, V, w, h + maxit + 2, s));
-    CHK(launch_gemv_sub(n, j + 1, V, h + maxit + 2, w, s));
-    CHK(launch_vt_w(n, 1, w, w, h + 2 * maxit + 6, s));
-    double hj[3];
-    MDSDP_HIP(hipMemcpyAsync(P->hbuf, h + j, sizeof(double), hipMemcpyDeviceToHost, s));
-    MDSDP_HIP(hipMemcpyAsync(P->hbuf + 1, h + maxit + 2 + j, sizeof(double), hipMemcpyDeviceToHost, s));
-    MDSDP_HIP(hipMemcpyAsync(P->hbuf + 2, h + 2 * maxit + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+  // The recurrence runs on the device: step j stores alpha_j and beta_j^2 in
+  // alpha_d[j], beta2_d[j] and normalises the next basis vector by the
+  // device value, so the host reads the scalars only every LZ_BATCH steps;
+  // it then replays the convergence tests step by step on those scalars, so
+  // the stopping step is the same as with a read-back after every step (the
+  // steps enqueued beyond it are discarded).
+  constexpr int LZ_BATCH = 8;
+  double* alpha_d = h + 2 * maxit + 8;
+  double* beta2_d = alpha_d + maxit;
+  bool stop = false;
+  for (int j0 = 0; j0 < maxit && !stop; j0 += LZ_BATCH) {
+    const int j1 = std::min(maxit, j0 + LZ_BATCH);
+    for (int j = j0; j < j1; ++j) {
+      double* vj = V + (size_t)j * n;
+      CHK(mdsdp_certificate_matvec(P, 1, vj, w, s));
+      if (Qd && rq > 0) CHK(launch_deflate(n, rq, Qd, w, qc, s));
+      // full reorthogonalisation, twice (classical Gram-Schmidt with refinement)
+      CHK(launch_vt_w(n, j + 1, V, w, h, s));
+      CHK(launch_gemv_sub(n, j + 1, V, h, w, s));
+      CHK(launch_vt_w(n, j + 1, V, w, h + maxit + 2, s));
+      CHK(launch_gemv_sub(n, j + 1, V, h + maxit + 2, w, s));
+      CHK(launch_vt_w(n, 1, w, w, h + 2 * maxit + 6, s));
+      CHK(launch_lanczos_step(n, j, h, h + maxit + 2, h + 2 * maxit + 6, alpha_d, beta2_d, w,
+                              V + (size_t)(j + 1) * n, j + 1 < maxit, s));
+    }
+    const int cnt = j1 - j0;
+    MDSDP_HIP(hipMemcpyAsync(P->hbuf, alpha_d + j0, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+    MDSDP_HIP(hipMemcpyAsync(P->hbuf + LZ_BATCH, beta2_d + j0, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
     MDSDP_HIP(hipStreamSynchronize(s));
-    hj[0] = P->hbuf[0];
-    hj[1] = P->hbuf[1];
-    hj[2] = P->hbuf[2];
-    al.push_back(hj[0] + hj[1]);
-    const double bj = sqrt(std::max(0.0, hj[2]));
-    k = j + 1;
-    th_min = tridiag_eig(k, al.data(), be.data(), 0);
-    th_max = tridiag_eig(k, al.data(), be.data(), k - 1);
-    tridiag_evec(k, al.data(), be.data(), th_min, sv);
-    // error estimate of theta_min: the residual, or residual^2 / gap when the
-    // gap to the rest of the spectrum is certified: theta_2 minus its own
-    // residual still lies above theta_min (then the interval of theta_2
-    // excludes theta_min's eigenvalue and resid^2 / gap bounds its error)
-    const double resid = bj * fabs(sv[k - 1]);
-    double err = resid;
-    if (use_gap && k >= 2) {
-      const double th2 = tridiag_eig(k, al.data(), be.data(), 1);
-      std::vector<double> s2;
-      tridiag_evec(k, al.data(), be.data(), th2, s2);
-      const double gap = th2 - bj * fabs(s2[k - 1]) - th_min;
-      if (gap > 0.0) err = std::min(resid, resid * resid / gap);
+    for (int j = j0; j < j1; ++j) {
+      al.push_back(P->hbuf[j - j0]);
+      const double bj = sqrt(std::max(0.0, P->hbuf[LZ_BATCH + j - j0]));
+      k = j + 1;
+      th_min = tridiag_eig(k, al.data(), be.data(), 0);
+      th_max = tridiag_eig(k, al.data(), be.data(), k - 1);
+      tridiag_evec(k, al.data(), be.data(), th_min, sv);
+      // error estimate of theta_min: the residual, or residual^2 / gap when the
+      // gap to the rest of the spectrum is certified: theta_2 minus its own
+      // residual still lies above theta_min (then the interval of theta_2
+      // excludes theta_min's eigenvalue and resid^2 / gap bounds its error)
+      const double resid = bj * fabs(sv[k - 1]);
+      double err = resid;
+      if (use_gap && k >= 2) {
+        const double th2 = tridiag_eig(k, al.data(), be.data(), 1);
+        std::vector<double> s2;
+        tridiag_evec(k, al.data(), be.data(), th2, s2);
+        const double gap = th2 - bj * fabs(s2[k - 1]) - th_min;
+        if (gap > 0.0) err = std::min(resid, resid * resid / gap);
+      }
+      // the other pairs that must converge (kconv > 1): their residuals
+      double err_all = err;
+      for (int i = 1; i < std::min(kconv, k); ++i) {
+        std::vector<double> si;
+        tridiag_evec(k, al.data(), be.data(), tridiag_eig(k, al.data(), be.data(), i), si);
+        err_all = std::max(err_all, bj * fabs(si[k - 1]));
+      }
+      if (resid_out) *resid_out = err;
+      if (k >= std::max(3, kconv + 2) && err_all <= tol * (1.0 + fabs(th_max))) {
+        *converged = true;
+        stop = true;
+        break;
+      }
+      // certified: theta_min - err >= stop_above puts the smallest eigenvalue
+      // (of the operator the run sees) at or above stop_above, which is all
+      // the dual residual and the curvature test need
+      if (stop_nonneg && k >= 3 && th_min - err >= stop_above * (1.0 + fabs(th_max))) {
+        *converged = true;
+        stop = true;
+        break;
+      }
+      if (bj <= 1e-14 * (1.0 + fabs(th_max))) {
+        *converged = true;  // invariant subspace
+        stop = true;
+        break;
+      }
+      be.push_back(bj);
     }
-    // the other pairs that must converge (kconv > 1): their residuals
-    double err_all = err;
-    for (int i = 1; i < std::min(kconv, k); ++i) {
-      std::vector<double> si;
-      tridiag_evec(k, al.data(), be.data(), tridiag_eig(k, al.data(), be.data(), i), si);
-      err_all = std::max(err_all, bj * fabs(si[k - 1]));
-    }
-    if (resid_out) *resid_out = err;
-    if (k >= std::max(3, kconv + 2) && err_all <= tol * (1.0 + fabs(th_max))) {
-      *converged = true;
-      break;
-    }
-    if (bj <= 1e-14 * (1.0 + fabs(th_max))) {
-      *converged = true;  // invariant subspace
-      break;
-    }
-    be.push_back(bj);
-    CHK(vec_lincomb(n, 1.0 / bj, w, 0.0, nullptr, V + (size_t)(j + 1) * n, s));
   }
   *lmin = th_min;
   *lmax = th_max;
@@ -618,7 +678,8 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
       const double th = i == 0 ? th_min : tridiag_eig(k, al.data(), be.data(), i);
       if (i > 0 && neg_rel >= 0.0 && !(th < -neg_rel * (1.0 + fabs(th_max)))) break;
       if (i > 0) tridiag_evec(k, al.data(), be.data(), th, sv);
-      MDSDP_HIP(hipMemcpyAsync(h, sv.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+      memcpy(P->hbuf + 64, sv.data(), k * sizeof(double));
+      MDSDP_HIP(hipMemcpyAsync(h, P->hbuf + 64, k * sizeof(double), hipMemcpyHostToDevice, s));
       CHK(launch_gemv(n, k, V, h, evec + (size_t)i * n, s));
       MDSDP_HIP(hipStreamSynchronize(s));
       ++found;
@@ -653,13 +714,17 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->gtol_decay = 1.0;
   o->gtol_ratio = 0.1;
   o->gtol_stall = 0.0;
-  o->sigma_hold = 0;
-  o->escape_when_solved = 1;
-  o->rtr_maxiter = 50;
+  o->sigma_hold = 1;
+  o->escape_when_solved = 0;
+  o->rtr_maxiter = 10;
   o->tcg_maxinner = 200;
   o->hvp_prec = MDSDP_FP64;
   o->polish_fp64 = 1;
-  o->polish_eta = 1e-6;
+  o->polish_eta = 1e-4;
+  o->deflate = 1;
+  o->direct_admm = 0;
+  o->rtr_warm_radius = 1;
+  o->rtr_maxiter_polish = 50;
   o->eig_tol = 1e-10;
   o->eig_maxit = 300;
   o->time_limit_s = 0.0;
@@ -785,6 +850,8 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   } else {
     CHK(mdsdp_set_multiplier(P, nullptr, opt->sigma0, s));
   }
+  // direct-DSDP ablation: stale y^0 = class averages at the start point
+  CHK(mdsdp_set_direct(P, opt->direct_admm ? 1 : 0, p, opt->direct_admm ? Y : nullptr, s));
   double sigma = opt->sigma0;
   double eta_max = 1.0;
   bool carry = false;
@@ -799,9 +866,13 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   double stall_cap = INFINITY;   // tolerance cap after an RTR call that took no step
   bool have_evec = false;
   int eig_budget = opt->eig_maxit;
+  double warm_delta = 0.0;
   for (k = 0; k < opt->max_outer; ++k) {
     CHK(mdsdp_set_sigma(P, sigma));
-    const int prec = (opt->polish_fp64 && eta_max < opt->polish_eta) ? MDSDP_FP64 : opt->hvp_prec;
+    // polishing phase (eta_max < polish_eta): FP64 HVPs and the larger RTR budget
+    const bool polish = eta_max < opt->polish_eta;
+    const int prec = (opt->polish_fp64 && polish) ? MDSDP_FP64 : opt->hvp_prec;
+    const int rtr_budget = polish ? std::max(opt->rtr_maxiter, opt->rtr_maxiter_polish) : opt->rtr_maxiter;
     if (carry) {
       // backtracking along the carried negative-curvature direction
       double f0;
@@ -828,13 +899,22 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
       gtol = std::max(opt->gtol_min, g);
     }
     RTRState rs;
-    mdsdp_status rst = rtr(P, p, Y, gtol, opt->rtr_maxiter, opt->tcg_maxinner, prec, W, C, rs, s, opt->verbose);
+    // warm radius: the previous call's final radius (at most Delta_bar / 8),
+    // so that a call does not spend its first steps shrinking Delta_bar / 8
+    if (opt->rtr_warm_radius && warm_delta > 0.0) rs.Delta0 = std::min(warm_delta, M_PI * sqrt((double)n) / 8.0);
+    const clk::time_point deadline =
+        opt->time_limit_s > 0 ? t_start + std::chrono::duration_cast<clk::duration>(
+                                              std::chrono::duration<double>(opt->time_limit_s))
+                              : clk::time_point::max();
+    mdsdp_status rst = rtr(P, p, Y, gtol, rtr_budget, opt->tcg_maxinner, prec, W, C, rs, s, opt->verbose,
+                           deadline);
     if (rst == MDSDP_ENONFINITE) {
       final_status = MDSDP_ENONFINITE;
       ++k;
       break;
     }
     CHK(rst);
+    warm_delta = rs.Delta0;
     if (opt->gtol_stall > 0.0 && rs.iters == 0 && rs.gn > 0.0) stall_cap = std::min(stall_cap, opt->gtol_stall * rs.gn);
     // multiplier update (Algorithm alg1 steps 5-8)
     auto tu = clk::now();
@@ -848,31 +928,99 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
       ++k;
       break;
     }
-    // certificate spectrum
+    // Gram matrix of Y and its eigen-decomposition (p x p, host): the rank
+    // update below and the deflation of the certificate eigensolve
+    CHK(launch_gram(P, p, Y, Y, s));
+    P->gram_yy_valid = false;  // the Gram buffer is reused below and Y changes
+    std::vector<double> wv(p), Vv((size_t)p * p);
+    {
+      const int pw = P->gram_pw;
+      std::vector<double> G((size_t)pw * pw), A((size_t)p * p);
+      CHK(read_dev(P, P->gram, pw * pw, G.data(), s));
+      for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) A[i * p + j] = G[(size_t)i * pw + j];
+      sym_eig(p, A.data(), wv.data(), Vv.data());
+    }
+    std::vector<int> idx(p);
+    for (int i = 0; i < p; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return wv[x] > wv[y]; });
+    // certificate spectrum.  With Q an orthonormal basis of range(Y) and
+    // A = Q^T X Q, B = (I - Q Q^T) X Q, C = the compression of X to the
+    // complement of range(Q): X = [[A, B^T], [B, C]] in [Q, Q_perp], so by
+    // Weyl's inequality lambda_min(X) >= min(lambda_min(A), lambda_min(C)) - ||B||_2.
+    // X Y = grad / 2 is small at a solved subproblem, so A and B are small and
+    // the Lanczos run on C does not have to resolve the cluster of eigenvalues
+    // near zero that range(Y) carries.
     auto te = clk::now();
     double lmin = 0, lmax = 0;
     int eit = 0;
     bool conv = false;
     int nfound = 0;
     double lres = 0.0;
+    double lmin_A = 0.0, lmax_A = 0.0, nB = 0.0;
+    int rq = 0;
+    {
+      const double w0 = std::max(0.0, wv[idx[0]]);
+      for (int i = 0; i < p; ++i)
+        if (wv[idx[i]] > 1e-14 * w0) ++rq;
+      rq = std::min(rq, n - 2);
+    }
+    if (opt->deflate && rq > 0) {
+      // Q = Y V_r diag(w_r)^{-1/2}  (n x rq, in W.r); X Q in W.Hd, then Q^T there
+      std::vector<double> Mq((size_t)p * rq);
+      for (int i = 0; i < p; ++i)
+        for (int c = 0; c < rq; ++c) Mq[(size_t)i * rq + c] = Vv[i * p + idx[c]] / sqrt(wv[idx[c]]);
+      memcpy(P->hbuf + 64, Mq.data(), Mq.size() * sizeof(double));
+      MDSDP_HIP(hipMemcpyAsync(P->gpart + GP_M, P->hbuf + 64, Mq.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      CHK(launch_rightmul(n, p, rq, Y, P->gpart + GP_M, false, W.r, s));
+      CHK(mdsdp_certificate_matvec(P, rq, W.r, W.Hd, s));
+      CHK(launch_gram(P, rq, W.r, W.Hd, s));
+      const int pw = P->gram_pw;
+      std::vector<double> G((size_t)pw * pw), Aq((size_t)rq * rq), wa(rq), Va((size_t)rq * rq);
+      CHK(read_dev(P, P->gram + GRAM_U, pw * pw, G.data(), s));
+      double a2 = 0.0;
+      for (int i = 0; i < rq; ++i)
+        for (int j = 0; j < rq; ++j) {
+          Aq[i * rq + j] = 0.5 * (G[(size_t)i * pw + j] + G[(size_t)j * pw + i]);
+          a2 += Aq[i * rq + j] * Aq[i * rq + j];
+        }
+      sym_eig(rq, Aq.data(), wa.data(), Va.data());
+      lmin_A = *std::min_element(wa.begin(), wa.end());
+      lmax_A = *std::max_element(wa.begin(), wa.end());
+      double xq2;
+      {
+        const double* a1[1] = {W.Hd};
+        CHK(dots(P, 1, a1, a1, (long long)n * rq, &xq2, s));
+      }
+      nB = sqrt(std::max(0.0, xq2 - a2));  // ||X Q - Q A||_F >= ||B||_2
+      CHK(launch_transpose(n, rq, W.r, W.Hd, s));  // Q^T (rq x n) for the projections
+    } else {
+      rq = 0;
+    }
     CHK(lanczos(P, opt->eig_tol, eig_budget, opt->seed + (uint64_t)k, &lmin, &lmax, evec, &eit, &conv, s,
-                std::max(1, opt->n_neg), 1e-12, &nfound, have_evec ? evec : nullptr, &lres, true));
+                std::max(1, opt->n_neg), 1e-12, &nfound, have_evec ? evec : nullptr, &lres, true, 1, nullptr,
+                nullptr, rq > 0 ? W.Hd : nullptr, rq, W.qc, true, -0.5 * opt->tol));
     have_evec = true;
     C.eig_iters += eit;
     C.t_eig += secs(te, clk::now());
     const double normR = kk[0], bty = kk[1], sumz = kk[2], cx = kk[3];
     eta[0] = normR / (1.0 + P->normC);
-    // an unconverged Lanczos only certifies an eigenvalue within its residual
-    // of theta_min: use theta_min - residual then
-    eta[1] = std::max(0.0, -(conv ? lmin : lmin - lres)) / (1.0 + fabs(lmax));
+    // an unconverged Lanczos only certifies an eigenvalue within its error
+    // estimate of theta_min: use theta_min - estimate then; with deflation the
+    // bound combines the compressions (see above)
+    double lo = conv ? lmin : lmin - lres;
+    if (rq > 0) {
+      lo = std::min(lo, lmin_A) - nB;
+      lmax = std::max(lmax, lmax_A);
+    }
+    eta[1] = std::max(0.0, -lo) / (1.0 + fabs(lmax));
     const double prim = cx + sumz;
     eta[2] = fabs(prim - bty) / (1.0 + fabs(prim) + fabs(bty));
     eta_max = std::max(eta[0], std::max(eta[1], eta[2]));
-    // when only the dual residual (an unconverged Lanczos estimate) stands
-    // between the iterate and the tolerance, give the next eigensolve more
-    // steps (it restarts from the current Ritz vector)
-    if (!conv && eta[1] > opt->tol && eta[0] <= opt->tol && eta[2] <= opt->tol)
-      eig_budget = std::min(n, 2 * eig_budget);
+    // when the dual residual (an unconverged Lanczos estimate) is among the
+    // largest residuals, give the next eigensolve more steps (it restarts
+    // from the current Ritz vector)
+    if (!conv && eta[1] > opt->tol && eta[1] >= 0.5 * eta_max) eig_budget = std::min(n, 2 * eig_budget);
     value = bty;
     if (hist && k < hist_cap) {
       double* hrow = hist + (size_t)k * 8;
@@ -897,25 +1045,15 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
       ++k;
       break;
     }
-    // rank update: SVD of Y through its Gram matrix (p x p)
-    CHK(launch_gram(P, p, Y, Y, s));
-    P->gram_yy_valid = false;  // Y changes below
-    const int pw = P->gram_pw;
-    std::vector<double> G((size_t)pw * pw), A((size_t)p * p), wv(p), Vv((size_t)p * p);
-    CHK(read_dev(P, P->gram, pw * pw, G.data(), s));
-    for (int i = 0; i < p; ++i)
-      for (int j = 0; j < p; ++j) A[i * p + j] = G[(size_t)i * pw + j];
-    sym_eig(p, A.data(), wv.data(), Vv.data());
-    std::vector<int> idx(p);
-    for (int i = 0; i < p; ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return wv[x] > wv[y]; });
+    // rank update: singular values of Y from its Gram matrix (computed above)
     const double s1 = sqrt(std::max(0.0, wv[idx[0]]));
     int r = 0;
     for (int i = 0; i < p; ++i)
       if (sqrt(std::max(0.0, wv[idx[i]])) > opt->tau_rank * s1) ++r;
     r = std::max(1, r);
     const bool unsolved = rs.gn > gtol;  // RTR stopped at its iteration cap
-    const bool neg = lmin < -1e-12 * (1.0 + fabs(lmax));
+    // curvature below the stopping tolerance's scale is not worth new columns
+    const bool neg = lmin < -std::max(1e-12, opt->tol) * (1.0 + fabs(lmax));
     // negative-curvature directions: Ritz vectors of the negative Ritz values
     int nneg = 0;
     if (neg && opt->n_neg > 0 && !(opt->escape_when_solved && unsolved)) nneg = std::min(nfound, opt->n_neg);
@@ -946,6 +1084,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
       sigma = std::min(opt->gamma * sigma, opt->sigma_max);
   }
   MDSDP_HIP(hipStreamSynchronize(s));
+  if (opt->direct_admm) CHK(mdsdp_set_direct(P, 0, p, nullptr, s));
   if (Y != Ybuf) MDSDP_HIP(hipMemcpy(Ybuf, Y, (size_t)n * p * sizeof(double), hipMemcpyDeviceToDevice));
   res->status = final_status;
   res->outer_iters = k;
@@ -967,6 +1106,71 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   res->t_update = C.t_update;
   if (final_status == MDSDP_ENONFINITE) return MDSDP_ENONFINITE;
   return final_status == MDSDP_OK ? MDSDP_OK : MDSDP_ENOCONV;
+}
+
+mdsdp_status mdsdp_solve_batch(int32_t nprob, mdsdp_problem* probs, const mdsdp_options* opt, const int32_t* p0,
+                               double* const* Ybufs, mdsdp_result* results, int32_t nworkers) {
+  if (nprob < 1 || !probs || !opt || !p0 || !Ybufs || !results) {
+    set_error("NULL argument or nprob < 1");
+    return MDSDP_EINVAL;
+  }
+  if (nworkers < 1 || nworkers > 64) {
+    set_error("need 1 <= nworkers <= 64");
+    return MDSDP_EINVAL;
+  }
+  int dev = 0;
+  MDSDP_HIP(hipGetDevice(&dev));
+  for (int i = 0; i < nprob; ++i)
+    if (!probs[i] || !Ybufs[i] || probs[i]->device != dev) {
+      set_error("problem " + std::to_string(i) + " is NULL, has no Y buffer or lives on another device");
+      return MDSDP_EINVAL;
+    }
+  // work queue: largest problems first (longest-processing-time order)
+  std::vector<int> order(nprob);
+  for (int i = 0; i < nprob; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a]->n > probs[b]->n; });
+  const int nw = std::min(nworkers, nprob);
+  std::vector<hipStream_t> streams(nw, nullptr);
+  for (int w = 0; w < nw; ++w) {
+    hipError_t e = hipStreamCreateWithFlags(&streams[w], hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      for (int u = 0; u < w; ++u) (void)hipStreamDestroy(streams[u]);
+      return hip_fail(e, "hipStreamCreate");
+    }
+  }
+  std::atomic<int> next(0);
+  std::vector<mdsdp_status> worker_status(nw, MDSDP_OK);
+  std::vector<std::string> worker_err(nw);
+  auto work = [&](int w) {
+    (void)hipSetDevice(dev);
+    for (;;) {
+      const int t = next.fetch_add(1);
+      if (t >= nprob) break;
+      const int i = order[t];
+      const mdsdp_status st = mdsdp_solve(probs[i], opt, p0[i], Ybufs[i], &results[i], nullptr, 0, streams[w]);
+      results[i].status = st;
+      if (st != MDSDP_OK && st != MDSDP_ENOCONV && worker_status[w] == MDSDP_OK) {
+        worker_status[w] = st;
+        worker_err[w] = std::string("problem ") + std::to_string(i) + ": " + mdsdp_last_error();
+      }
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int w = 1; w < nw; ++w) threads.emplace_back(work, w);
+  work(0);
+  for (auto& th : threads) th.join();
+  for (int w = 0; w < nw; ++w) (void)hipStreamDestroy(streams[w]);
+  for (int w = 0; w < nw; ++w)
+    if (worker_status[w] != MDSDP_OK) {
+      set_error(worker_err[w]);
+      return worker_status[w];
+    }
+  for (int i = 0; i < nprob; ++i)
+    if (results[i].status != MDSDP_OK) {
+      set_error("problem " + std::to_string(i) + " did not reach the tolerance");
+      return MDSDP_ENOCONV;
+    }
+  return MDSDP_OK;
 }
 
 }  // extern "C"

@@ -64,6 +64,33 @@ def bqp_b(Q: np.ndarray, c: np.ndarray) -> np.ndarray:
     return out
 
 
+def ucqp_sizes(q: int) -> tuple[int, int]:
+    n = C.c_int32()
+    m = C.c_int64()
+    call("mdsdp_ucqp_sizes", q, C.byref(n), C.byref(m))
+    return n.value, m.value
+
+
+def ucqp_structure(q: int) -> tuple[np.ndarray, np.ndarray]:
+    """Packed upper-triangle class ids and coefficients (+1, -1, 0) of the
+    Hermitian UCQP relaxation's real embedding."""
+    n, _ = ucqp_sizes(q)
+    cls_ = np.empty(n * (n + 1) // 2, dtype=np.int32)
+    coef = np.empty(n * (n + 1) // 2, dtype=np.int8)
+    call("mdsdp_ucqp_structure", q, _ptr(cls_), _ptr(coef))
+    return cls_, coef
+
+
+def ucqp_b(Q: np.ndarray) -> np.ndarray:
+    q = Q.shape[0]
+    _, m = ucqp_sizes(q)
+    out = np.empty(m, dtype=np.float64)
+    Qre = np.ascontiguousarray(np.real(Q), dtype=np.float64)
+    Qim = np.ascontiguousarray(np.imag(Q), dtype=np.float64)
+    call("mdsdp_ucqp_b", q, _ptr(Qre), _ptr(Qim), _ptr(out))
+    return out
+
+
 @dataclass
 class SolveResult:
     Y: torch.Tensor
@@ -120,6 +147,17 @@ class Problem:
         h = C.c_void_p()
         call("mdsdp_create_sparse_A", n, m, ci.size, _ptr(ci), _ptr(ri), _ptr(co), _ptr(va), _ptr(bb),
              _ptr(Cd), C.byref(h))
+        return cls(h)
+
+    @classmethod
+    def ucqp(cls, Q: np.ndarray):
+        """Hermitian order-2 relaxation of min z^H Q z, |z_i| = 1 (real
+        embedding, signed classes; see mdsdp_ucqp_structure)."""
+        q = Q.shape[0]
+        Qre = np.ascontiguousarray(np.real(Q), dtype=np.float64)
+        Qim = np.ascontiguousarray(np.imag(Q), dtype=np.float64)
+        h = C.c_void_p()
+        call("mdsdp_create_ucqp", q, _ptr(Qre), _ptr(Qim), C.byref(h))
         return cls(h)
 
     @classmethod
@@ -244,6 +282,13 @@ class Problem:
         return {"theta_min": float(out[0]), "theta_max": float(out[1]), "err": float(out[2]),
                 "converged": bool(out[3]), "evec": v, "iters": it.value}
 
+    def set_direct(self, on: bool, Y: torch.Tensor | None = None) -> None:
+        """Switch to (or from) the direct-DSDP ADMM subproblem; with Y the
+        stale class averages y^k are taken at Y."""
+        if Y is not None:
+            _dev_f64(Y, "Y")
+        call("mdsdp_set_direct", self._h, 1 if on else 0, 0 if Y is None else Y.shape[1], _ptr(Y), _stream())
+
     def sync_status(self) -> None:
         """Raise MdsdpError(MDSDP_ENONFINITE) if a kernel met a non-finite value
         since the last set_multiplier (synchronises the stream)."""
@@ -289,6 +334,31 @@ class Problem:
         o = Options()
         lib().mdsdp_default_options(C.byref(o))
         return o
+
+    @staticmethod
+    def solve_batch(problems, Y0s, opts: Options | None = None, nworkers: int = 4):
+        """Solve independent problems concurrently (mdsdp_solve_batch): returns
+        one (Y, Result) pair per problem."""
+        nprob = len(problems)
+        opts = opts or problems[0].default_options()
+        handles = (C.c_void_p * nprob)(*[pr._h for pr in problems])
+        p0 = (C.c_int32 * nprob)(*[int(Y.shape[1]) for Y in Y0s])
+        bufs = []
+        for pr, Y in zip(problems, Y0s):
+            _dev_f64(Y, "Y0")
+            b = torch.zeros(pr.n * max(opts.p_max, Y.shape[1]), dtype=torch.float64, device=Y.device)
+            b[: pr.n * Y.shape[1]] = Y.reshape(-1)
+            bufs.append(b)
+        ptrs = (C.c_void_p * nprob)(*[b.data_ptr() for b in bufs])
+        res = (Result * nprob)()
+        torch.cuda.current_stream().synchronize()
+        code = lib().mdsdp_solve_batch(nprob, handles, C.byref(opts), p0, ptrs, res, nworkers)
+        if code not in (0, -7):
+            _lib.check(code, "mdsdp_solve_batch")
+        out = []
+        for pr, b, r in zip(problems, bufs, res):
+            out.append((b[: pr.n * r.p_final].reshape(pr.n, r.p_final).clone(), r))
+        return out
 
     def solve(self, Y0: torch.Tensor, opts: Options | None = None, history_cap: int = 1000) -> SolveResult:
         self._ad_key = None

@@ -175,7 +175,7 @@ def test_solver_options_validated_first(field, value, msg):
     L = _lib.lib()
     o = _lib.Options()
     L.mdsdp_default_options(C.byref(o))
-    assert o.sigma_hold == 0 and o.escape_when_solved == 1 and o.gtol_ratio > 0
+    assert o.sigma_hold == 1 and o.escape_when_solved == 0 and o.gtol_ratio > 0 and o.rtr_maxiter == 10
     setattr(o, field, value)
     res = _lib.Result()
     assert L.mdsdp_solve(None, C.byref(o), 2, None, C.byref(res), None, 0, None) == -1
@@ -190,3 +190,60 @@ def test_status_and_eigpair_validation():
     ev = np.zeros(2)
     lmax = C.c_double()
     assert L.mdsdp_min_eigpair(None, 2, 1e-8, 10, 0, _p(ev), C.byref(lmax), None, None, None) == -1
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 5, 8, 13])
+def test_ucqp_builder_bit_exact(q):
+    """The library's Hermitian UCQP builder against the oracle's real
+    embedding: class ids and signed coefficients bit for bit, b bit for bit
+    apart from the trace (a sum in another order)."""
+    from oracle import ucqp
+    from paper_2512_04406_amd.problem import ucqp_b, ucqp_sizes, ucqp_structure
+    from synth import ucqp_instance
+
+    Q = ucqp_instance(q, 7)
+    rel = ucqp.build_relaxation(Q)
+    n, m = ucqp_sizes(q)
+    assert (n, m) == (rel.n, rel.m)
+    cls_, coef = ucqp_structure(q)
+    iu = np.triu_indices(n)
+    np.testing.assert_array_equal(coef, rel.w[iu].astype(np.int8))
+    np.testing.assert_array_equal(cls_, rel.cls[iu])
+    # b: bit-exact except the trace, a floating sum in another order
+    bb = ucqp_b(Q)
+    np.testing.assert_array_equal(bb[1:], rel.b[1:])
+    assert bb[0] == pytest.approx(rel.b[0], rel=1e-14, abs=1e-14)
+
+
+def test_ucqp_sizes_q30():
+    from paper_2512_04406_amd.problem import ucqp_sizes
+
+    assert ucqp_sizes(30) == (992, 217621)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of mdsdp_options and mdsdp_result have the header's
+    size and field offsets (compiled with the host compiler)."""
+    import shutil
+    import subprocess
+
+    from paper_2512_04406_amd import _lib
+
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    lines = ['#include <cstdio>', '#include <cstddef>', '#include "manidsdp.h"', "int main() {"]
+    for cname, py in (("mdsdp_options", _lib.Options), ("mdsdp_result", _lib.Result)):
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("}")
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([cxx, "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for cname, py in (("mdsdp_options", _lib.Options), ("mdsdp_result", _lib.Result)):
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)

@@ -1,8 +1,9 @@
 """GPU parity and solves of the Hermitian UCQP relaxation (signed classes).
 
-The problem enters through the sparse-A constructor with coefficients +-1
-(imaginary parts of the real embedding) and entries left in no class (the
-imaginary parts of the moment-matrix diagonal).  Against the oracle with the
+The parity cases enter through the sparse-A constructor with coefficients
++-1 (imaginary parts of the real embedding) and entries left in no class (the
+imaginary parts of the moment-matrix diagonal), built from the oracle's
+structure; the solves use the library's own builder (mdsdp_create_ucqp).  Against the oracle with the
 same signed operators: class averages (1e-12), cost, Euclidean/Riemannian
 gradients and HVPs entry by entry (1e-10 of the per-entry bound in FP64, 1e-4
 with FP32 tiles), the multiplier update; q = 3 (n = 20), 10 (n = 132) and the
@@ -105,13 +106,13 @@ def _certify(rel, Q, res, prob):
 
 
 def test_ucqp_q3_solve_matches_oracle():
-    from paper_2512_04406_amd.problem import FP32, FP64
+    from paper_2512_04406_amd.problem import FP32, FP64, Problem
 
     Q = ucqp_instance(3, 1)
     rel = ucqp.build_relaxation(Q)
     ref = alm.solve(rel.cls, rel.counts, rel.b, gaussian(rel.n, 2, 101), alm.ALMOptions(), w=rel.w)
     for prec in (FP64, FP32):
-        prob = _problem(rel)
+        prob = Problem.ucqp(Q)  # the library's own builder
         o = prob.default_options()
         o.hvp_prec = prec
         res = prob.solve(_t(gaussian(rel.n, 2, 101)), o)
@@ -125,7 +126,7 @@ def test_ucqp_q3_solve_matches_oracle():
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden value not written yet (make_ucqp_q30_value.py)")
 def test_ucqp_q30_mixed_and_fp64():
-    from paper_2512_04406_amd.problem import FP32, FP64
+    from paper_2512_04406_amd.problem import FP32, FP64, Problem
 
     vals = {}
     for line in open(GOLDEN):
@@ -136,7 +137,7 @@ def test_ucqp_q30_mixed_and_fp64():
     rel = ucqp.build_relaxation(Q)
     out = {}
     for name, prec in (("mixed", FP32), ("fp64", FP64)):
-        prob = _problem(rel)
+        prob = Problem.ucqp(Q)
         o = prob.default_options()
         o.hvp_prec = prec
         o.time_limit_s = 100.0

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 from oracle import bqp
-from oracle.operators import Q_op
+from oracle.operators import Q_op, class_average
 from oracle.subproblem import Subproblem, proj_tangent, retract, rowdot
 from synth import bqp_instance, gaussian
 
@@ -113,3 +113,42 @@ def test_negative_curvature_direction_theorem(setup):
     H = sub.rhess(Yh, Uh)
     np.testing.assert_allclose(H, 2 * X @ Uh, rtol=0, atol=1e-11 * (1 + np.abs(X).max()))
     assert _inner(Uh, H) < 0
+
+
+def test_direct_subproblem_pins():
+    """Direct-DSDP (ADMM) subproblem of the ablation: its cost exceeds the
+    reduced cost by exactly sigma/2 ||P(Z - Z^k)||^2 (eq. penalty-decomposition),
+    its Hessian quadratic form by sigma ||P(Y U^T + U Y^T)||^2 (the extra
+    sigma P curvature of eq. hessian-comparison, at a point where the
+    two gradients' Diag(z) terms are taken into account), and its gradient and
+    Hessian agree with central differences."""
+    from oracle.operators import P_op
+    from oracle.subproblem import DirectSubproblem
+
+    q, p, sigma = 6, 3, 1.7
+    Q, c = bqp_instance(q, 3)
+    rel = bqp.build_relaxation(Q, c, "colex")
+    W = gaussian(rel.n, rel.n, 4)
+    Xt = Q_op(0.1 * (W + W.T), rel.cls, rel.counts)
+    Yk = gaussian(rel.n, p, 5)
+    Yk /= np.linalg.norm(Yk, axis=1, keepdims=True)
+    yk = class_average(Yk @ Yk.T, rel.cls, rel.counts)
+    red = Subproblem(rel.cls, rel.counts, rel.b, Xt, sigma)
+    dire = DirectSubproblem(rel.cls, rel.counts, rel.b, Xt, sigma, yk=yk)
+    Y = gaussian(rel.n, p, 6)
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    Z = Y @ Y.T
+    extra = 0.5 * sigma * np.sum(P_op(Z - Yk @ Yk.T, rel.cls, rel.counts) ** 2)
+    assert dire.cost(Y) - red.cost(Y) == pytest.approx(extra, rel=1e-11)
+    U = proj_tangent(Y, gaussian(rel.n, p, 7))
+    Wu = Y @ U.T + U @ Y.T
+    de = np.sum(U * dire.ehess(Y, U)) - np.sum(U * red.ehess(Y, U))
+    dG = dire.G(Y) - red.G(Y)  # = sigma P(Z - Z^k), class-constant
+    assert de == pytest.approx(sigma * np.sum(P_op(Wu, rel.cls, rel.counts) ** 2) + 2 * np.sum(U * (dG @ U)),
+                               rel=1e-10)
+    # central differences of the cost along U and of egrad
+    for h in (1e-3, 1e-4):
+        fd = (dire.cost(Y + h * U) - dire.cost(Y - h * U)) / (2 * h)
+        assert fd == pytest.approx(np.sum(dire.egrad(Y) * U), rel=1e-5)
+        fdg = (dire.egrad(Y + h * U) - dire.egrad(Y - h * U)) / (2 * h)
+        assert np.linalg.norm(fdg - dire.ehess(Y, U)) <= 1e-5 * np.linalg.norm(dire.ehess(Y, U))
