@@ -231,6 +231,20 @@ mdsdp_status mdsdp_certificate_matvec(mdsdp_problem prob, int32_t k, const doubl
 mdsdp_status mdsdp_min_eigpair(mdsdp_problem prob, int32_t k, double tol, int32_t maxit, uint64_t seed,
                                double* evals_host, double* lambda_max_host, double* evecs_dev,
                                int32_t* iters, void* stream);
+/* Allocation-free variant of mdsdp_min_eigpair, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): same arguments and results, but the
+ * Lanczos basis and coefficients live in a fixed device scratch of 4 Mi
+ * doubles (32 MiB) per GPU, held until the process ends, instead of buffers
+ * the problem allocates on demand.  Needs n (maxit' + 1) + n + 4 maxit' + 16
+ * <= 4194304 doubles with maxit' = min(maxit, n), else MDSDP_EINVAL before any
+ * work; the current device must be the problem's.  Every call on a GPU uses
+ * that GPU's one scratch: calls that overlap on one GPU (other threads or
+ * streams) race and must be serialised by the caller.  Makes no hipMalloc,
+ * hipFree or allocating library call. */
+mdsdp_status mdsdp_min_eigpair_noalloc(mdsdp_problem prob, int32_t k, double tol, int32_t maxit,
+                                       uint64_t seed, double* evals_host, double* lambda_max_host,
+                                       double* evecs_dev, int32_t* iters, void* stream);
 /* The certificate spectrum estimate the solver uses for eta_d (eq. res):
  * Lanczos from `warm_dev` (n doubles, nullable: a random start) plus a small
  * random component, stopping when the error estimate of theta_min -- its

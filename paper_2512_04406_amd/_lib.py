@@ -74,6 +74,7 @@ SIGNATURES = {
     "mdsdp_certificate_matvec": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "mdsdp_min_eigpair": (_i32, [_vp, _i32, _f64, _i32, _u64, _vp, _pf64, _vp, _pi32, _vp]),
     "mdsdp_sync_status": (_i32, [_vp, _vp]),
+    "mdsdp_min_eigpair_noalloc": (_i32, [_vp, _i32, _f64, _i32, _u64, _vp, _pf64, _vp, _pi32, _vp]),
     "mdsdp_set_direct": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "mdsdp_certificate_estimate": (_i32, [_vp, _f64, _i32, _u64, _vp, _vp, _vp, _pi32, _vp]),
     "mdsdp_adjoint_C": (_i32, [_vp, _vp, _vp]),

@@ -39,6 +39,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 
@@ -2782,6 +2783,33 @@ mdsdp_status launch_gemv(int n, int k, const double* V, const double* sv, double
 mdsdp_status vec_fill(long long len, double v, double* out, hipStream_t s) {
   k_fill<<<blocks_for(len, 256), 256, 0, s>>>(len, v, out);
   MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+// Fixed device scratch of the entry points that allocate nothing: one copy
+// per GPU, held until the process ends.  Host code must not pass `scratch`
+// itself to a kernel (in host code the name is a host-side stand-in): the
+// device address comes from hipGetSymbolAddress, fetched once per device with
+// that device current, and is cached here.
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+mdsdp_status scratch_buffer(double** out) {
+  static std::mutex mu;
+  static double* ptrs[MAX_DEVICES] = {};
+  int dev = 0;
+  MDSDP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    set_error("device index out of range for the fixed scratch");
+    return MDSDP_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    ptrs[dev] = (double*)ptr;
+  }
+  *out = ptrs[dev];
   return MDSDP_OK;
 }
 

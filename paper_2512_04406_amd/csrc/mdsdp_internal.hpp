@@ -249,6 +249,11 @@ mdsdp_status launch_set_col(int n, int p, int col, const double* v, double* U, h
                            bool zero_rest = true);
 mdsdp_status launch_gemv_sub(int n, int k, const double* V, const double* h, double* w, hipStream_t s);
 mdsdp_status launch_gemv(int n, int k, const double* V, const double* sv, double* out, hipStream_t s);
+// device address of this GPU's fixed scratch (SCRATCH_DOUBLES doubles), for
+// the entry points that allocate nothing; fetched once per device
+constexpr long long SCRATCH_DOUBLES = 4ll << 20;  // 32 MiB
+constexpr int MAX_DEVICES = 64;
+mdsdp_status scratch_buffer(double** out);
 // one Lanczos step's scalars and normalisation on the device (see solver.cpp)
 mdsdp_status launch_lanczos_step(int n, int j, const double* h, const double* h2, const double* nrm2, double* alpha,
                                  double* beta2, const double* w, double* vnext, bool write_next, hipStream_t s);

@@ -760,6 +760,47 @@ mdsdp_status mdsdp_min_eigpair(mdsdp_problem P, int32_t k, double tol, int32_t m
   return MDSDP_OK;
 }
 
+mdsdp_status mdsdp_min_eigpair_noalloc(mdsdp_problem P, int32_t k, double tol, int32_t maxit, uint64_t seed,
+                                       double* evals, double* lambda_max, double* evecs, int32_t* iters,
+                                       void* stream) {
+  if (!P || !evals || !lambda_max) {
+    set_error("NULL argument");
+    return MDSDP_EINVAL;
+  }
+  if (k < 1 || maxit < 2 || !(tol > 0.0) || k > P->n || k + 2 > maxit) {
+    set_error("need 1 <= k <= n, maxit >= k + 2 and tol > 0");
+    return MDSDP_EINVAL;
+  }
+  const int n = P->n;
+  const int mx = std::min(maxit, n);
+  const long long need = (long long)n * (mx + 1) + n + 4LL * mx + 16;
+  if (need > SCRATCH_DOUBLES) {
+    set_error("n * (maxit + 1) + n + 4 maxit + 16 = " + std::to_string(need) + " doubles exceeds the fixed scratch of " +
+              std::to_string(SCRATCH_DOUBLES) + " doubles; lower maxit or use mdsdp_min_eigpair");
+    return MDSDP_EINVAL;
+  }
+  int dev = -1;
+  MDSDP_HIP(hipGetDevice(&dev));
+  if (dev != P->device) {
+    set_error("the current device is not the problem's device");
+    return MDSDP_EINVAL;
+  }
+  double* ext = nullptr;
+  CHK(scratch_buffer(&ext));
+  bool conv = false;
+  int it = 0;
+  double lmin = 0.0;
+  mdsdp_status st = lanczos(P, tol, maxit, seed, &lmin, lambda_max, evecs, &it, &conv, (hipStream_t)stream, k,
+                            -1.0, nullptr, nullptr, nullptr, false, k, evals, ext);
+  if (iters) *iters = it;
+  if (st != MDSDP_OK) return st;
+  if (!conv) {
+    set_error("Lanczos reached maxit before the residual tolerance");
+    return MDSDP_ENOCONV;
+  }
+  return MDSDP_OK;
+}
+
 mdsdp_status mdsdp_certificate_estimate(mdsdp_problem P, double tol, int32_t maxit, uint64_t seed,
                                        const double* warm, double* out, double* evec, int32_t* iters,
                                        void* stream) {
