@@ -307,6 +307,14 @@ typedef struct {
                           radius (capped at Delta_bar / 8); 0: from Delta_bar / 8 */
   int32_t rtr_maxiter_polish; /* RTR iteration budget once eta_max < polish_eta (default 50; the budget
                           before that is rtr_maxiter, default 10) */
+  int32_t round_rank_one; /* 1 (default): rank-one compression test of Theorem thm:finite-locking and
+                          Remark rem:inexact-near-locking: after an outer step with eta_max < round_eta
+                          whose Y has s_2 <= round_gap s_1, eq. res is evaluated at Y1 = sign(Y v_1)
+                          (n x 1) with the current multiplier and no multiplier step; the solve stops
+                          there (p_final = 1, rank_one_round = 1) when that point meets tol, and the
+                          iteration is unchanged otherwise.  0: off */
+  double round_eta;    /* default 1e-3 */
+  double round_gap;    /* in [0, 1], default 0.1 */
 } mdsdp_options;
 
 typedef struct {
@@ -321,6 +329,7 @@ typedef struct {
   double sigma;
   double seconds;
   double t_eval, t_hvp, t_eig, t_update; /* seconds per phase */
+  int32_t rank_one_round; /* 1: the final point is the rank-one compression (see round_rank_one) */
 } mdsdp_result;
 
 void mdsdp_default_options(mdsdp_options* opt);

@@ -102,6 +102,9 @@ class ALMOptions:
     rtr_maxiter_polish: int = 50
     polish_eta: float = 1e-4
     neg_tol: float = 1e-12
+    round_rank_one: bool = True  # rank-one compression test (Remark rem:inexact-near-locking)
+    round_eta: float = 1e-3      # ... tried once eta_max is below this
+    round_gap: float = 0.1       # ... and s_2 <= round_gap s_1 (singular values of Y)
 
 
 @dataclass
@@ -140,6 +143,34 @@ def _escape(sub: Subproblem, Y: np.ndarray, U: np.ndarray) -> np.ndarray:
             return Yt
         t *= 0.5
     return Y
+
+
+def _rank_one_candidate(Y, Xt, D, cls, counts, b, C, w, gap):
+    """Rank-one compression of the current iterate, checked as a KKT point.
+
+    Theorem thm:finite-locking: once the multiplier Xt is close enough to its
+    limit, the rank-one solution S* is the unique minimiser of every later
+    subproblem, its residual R is zero (so the multiplier stops moving) and
+    (S*, y*, C_{S*}(Xt + D), z) satisfies the KKT system of DSDP.  Remark
+    rem:inexact-near-locking: an inexact subproblem only brings S near S*, and
+    a rank-one compression step can then land on S* exactly.  Reading: when
+    Y's second singular value is at most gap times its first, take the
+    leading left singular vector u of Y, the oblique-manifold point
+    Y1 = sign(u) (rows of width 1; zeros to +1), and evaluate eq. res at
+    S1 = Y1 Y1^T with the current multiplier Xt and no multiplier step:
+    y1 = (A A^*)^{-1} A (S1 + C), z1 = diag((Xt + D) S1), X1 = Xt + D - Diag(z1).
+    The caller accepts it only when that point meets the stopping tolerance,
+    so a wrong guess costs one evaluation and never changes the iteration.
+    Returns (Y1, y1, z1, X1, S1, eta1) or None when the gap test fails."""
+    U, s, Vt = np.linalg.svd(Y, full_matrices=False)
+    if s.size > 1 and s[1] > gap * s[0]:
+        return None
+    Y1 = np.where(U[:, 0] >= 0.0, 1.0, -1.0)[:, None]
+    S1 = Y1 @ Y1.T
+    y1 = class_average(S1 if C is None else S1 + C, cls, counts, w)
+    z1 = rowdot((Xt + D) @ Y1, Y1)
+    X1 = Xt + D - np.diag(z1)
+    return Y1, y1, z1, X1, S1, kkt_residuals(S1, y1, X1, z1, b, cls, C, w)
 
 
 def rank_one_rounding(Y: np.ndarray, Q: np.ndarray, c: np.ndarray, order_basis: np.ndarray):
@@ -206,6 +237,15 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
                          lmin=lmin, lmax=lmax))
         if eta_max <= opts.tol:
             break
+        if opts.round_rank_one and not opts.direct and eta_max < opts.round_eta:
+            cand = _rank_one_candidate(Y, Xt, D, cls, counts, b, C, w, opts.round_gap)
+            if cand is not None:
+                hist[-1]["round_eta"] = cand[5]
+                if max(cand[5]) <= opts.tol:
+                    Y, y, z, X, S, eta = cand
+                    hist.append(dict(k=k, p=1, sigma=sigma, eta=eta, value=float(b @ y), gradnorm=0.0,
+                                     rtr_iters=0, n_hvp=0, rounded=True))
+                    break
         unsolved = res.gradnorm > gtol  # RTR stopped at its iteration cap
         # negative-curvature directions (Theorem sec5:thm1)
         neg = np.nonzero(evals < -max(opts.neg_tol, opts.tol) * (1.0 + abs(lmax)))[0][: opts.n_neg]

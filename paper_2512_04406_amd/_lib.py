@@ -36,14 +36,16 @@ class Options(C.Structure):
                 ("polish_fp64", _i32), ("polish_eta", _f64), ("eig_tol", _f64), ("eig_maxit", _i32),
                 ("time_limit_s", _f64), ("verbose", _i32), ("seed", _u64),
                 ("resume", _i32), ("escape_when_solved", _i32), ("deflate", _i32),
-                ("direct_admm", _i32), ("rtr_warm_radius", _i32), ("rtr_maxiter_polish", _i32)]
+                ("direct_admm", _i32), ("rtr_warm_radius", _i32), ("rtr_maxiter_polish", _i32),
+                ("round_rank_one", _i32), ("round_eta", _f64), ("round_gap", _f64)]
 
 
 class Result(C.Structure):
     _fields_ = [("status", _i32), ("outer_iters", _i32), ("rtr_iters", _i64), ("hvps", _i64),
                 ("cost_grads", _i64), ("eig_iters", _i64), ("p_final", _i32), ("p_max_reached", _i32),
                 ("value", _f64), ("eta_p", _f64), ("eta_d", _f64), ("eta_g", _f64), ("sigma", _f64),
-                ("seconds", _f64), ("t_eval", _f64), ("t_hvp", _f64), ("t_eig", _f64), ("t_update", _f64)]
+                ("seconds", _f64), ("t_eval", _f64), ("t_hvp", _f64), ("t_eig", _f64), ("t_update", _f64),
+                ("rank_one_round", _i32)]
 
 
 # name -> (restype, argtypes)

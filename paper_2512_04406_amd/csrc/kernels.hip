@@ -1370,6 +1370,17 @@ __global__ __launch_bounds__(256) void k_rightmul(int n, int p, int q, const dou
   }
 }
 
+// rank-one compression: out_i = sign((Y v)_i) in {+1, -1} (zero to +1), the
+// width-1 point of the oblique manifold nearest the leading direction v of Y
+__global__ __launch_bounds__(256) void k_sign_col(int n, int p, const double* __restrict__ Yin,
+                                                  const double* __restrict__ v, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < p; ++k) s += Yin[(size_t)i * p + k] * v[k];
+  out[i] = (s >= 0.0) ? 1.0 : -1.0;
+}
+
 // column `col` of U (n x p) = v; with zero_rest the other columns are cleared
 __global__ __launch_bounds__(256) void k_set_col(int n, int p, int col, const double* __restrict__ v,
                                                  double* __restrict__ U, int zero_rest) {
@@ -2717,6 +2728,12 @@ mdsdp_status launch_vt_w(int n, int k, const double* V, const double* w, double*
 mdsdp_status launch_rightmul(int n, int p, int q, const double* Yin, const double* M, bool normalize,
                              double* Yout, hipStream_t s) {
   k_rightmul<<<blocks_for(n, 256), 256, 0, s>>>(n, p, q, Yin, M, normalize ? 1 : 0, Yout);
+  MDSDP_HIP(hipGetLastError());
+  return MDSDP_OK;
+}
+
+mdsdp_status launch_sign_col(int n, int p, const double* Yin, const double* v, double* out, hipStream_t s) {
+  k_sign_col<<<blocks_for(n, 256), 256, 0, s>>>(n, p, Yin, v, out);
   MDSDP_HIP(hipGetLastError());
   return MDSDP_OK;
 }

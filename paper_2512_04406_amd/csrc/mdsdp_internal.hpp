@@ -245,6 +245,7 @@ mdsdp_status launch_tcg_update(int n, int p, const double* Y, const double* sc_c
 mdsdp_status launch_vt_w(int n, int k, const double* V, const double* w, double* h, hipStream_t s);
 mdsdp_status launch_rightmul(int n, int p, int q, const double* Yin, const double* M, bool normalize,
                              double* Yout, hipStream_t s);
+mdsdp_status launch_sign_col(int n, int p, const double* Yin, const double* v, double* out, hipStream_t s);
 mdsdp_status launch_set_col(int n, int p, int col, const double* v, double* U, hipStream_t s,
                            bool zero_rest = true);
 mdsdp_status launch_gemv_sub(int n, int k, const double* V, const double* h, double* w, hipStream_t s);

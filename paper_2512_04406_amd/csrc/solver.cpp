@@ -40,7 +40,14 @@
 //  * rank rule: drop singular directions of Y below tau_rank * s_1, then add
 //    one zero column per carried negative eigenvector (at most n_neg per
 //    outer step, p <= p_max);
-//  * sigma rule eq. sec5:eq1 with ||R|| = ||Q(Z)||_F and the final ||grad||.
+//  * sigma rule eq. sec5:eq1 with ||R|| = ||Q(Z)||_F and the final ||grad||;
+//  * rank-one compression (Theorem thm:finite-locking, Remark
+//    rem:inexact-near-locking): once eta_max < round_eta and s_2 <= round_gap
+//    s_1, eq. res is also evaluated at Y1 = sign(Y v_1) with the current
+//    multiplier and no multiplier step; the solve ends there when that point
+//    meets the tolerance;
+//  * a solve ends only on an eta_d from a verify eigensolve (random start,
+//    residual error, no early stop; see certificate_spectrum).
 #include <math.h>
 #include <string.h>
 
@@ -689,6 +696,101 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
   return MDSDP_OK;
 }
 
+// Bounds on the spectrum of the certificate X = Xt + D - Diag(z) (z of the
+// last multiplier update) for eta_d of eq. res and the curvature test of
+// Theorem sec5:thm1.  With Q an orthonormal basis of range(Y) and
+// A = Q^T X Q, B = (I - Q Q^T) X Q, C = the compression of X to the complement
+// of range(Q): X = [[A, B^T], [B, C]] in [Q, Q_perp], so by Weyl's inequality
+// lambda_min(X) >= min(lambda_min(A), lambda_min(C)) - ||B||_2.  X Y = grad / 2
+// is small at a solved subproblem, so A and B are small and the Lanczos run on
+// C does not have to resolve the cluster of eigenvalues near zero that
+// range(Y) carries.  An unconverged Lanczos run only certifies an eigenvalue
+// within its error estimate of theta_min, so lo uses theta_min minus that
+// estimate then.  wv / Vv: eigen-decomposition of Y^T Y, idx its order by
+// decreasing eigenvalue.  Qb, XQb: n x p buffers; qc: p doubles.
+// Neither a residual nor a gap estimate can show that the Krylov space has
+// reached the bottom of the spectrum: a run warm-started near an eigenvector
+// that is not the lowest can meet its stopping test within a few steps.  The
+// fast mode (warm start, gap-based error, stop once theta_min minus the error
+// is at least stop_above) steers the iteration; every eta_d that ends a solve
+// comes from a verify run (random start, residual error, no early stop).
+struct CertSpectrum {
+  double lo = 0.0;    // certified lower bound of lambda_min(X)
+  double lmin = 0.0;  // smallest Ritz value of the run
+  double lmax = 0.0;  // largest Ritz value (of the run and of A)
+  int iters = 0, nfound = 0;
+  bool conv = false;
+};
+
+static mdsdp_status certificate_spectrum(mdsdp_problem P, int p, const double* Y, const std::vector<double>& wv,
+                                         const std::vector<double>& Vv, const std::vector<int>& idx, bool deflate,
+                                         double eig_tol, int budget, uint64_t seed, int nvec, const double* warm,
+                                         double* evec, double* Qb, double* XQb, double* qc, double stop_above,
+                                         CertSpectrum* out, hipStream_t s, bool verify = false) {
+  const int n = P->n;
+  double lmin = 0, lmax = 0, lres = 0.0;
+  double lmin_A = 0.0, lmax_A = 0.0, nB = 0.0;
+  int eit = 0, nfound = 0;
+  bool conv = false;
+  int rq = 0;
+  {
+    const double w0 = std::max(0.0, wv[idx[0]]);
+    for (int i = 0; i < p; ++i)
+      if (wv[idx[i]] > 1e-14 * w0) ++rq;
+    rq = std::min(rq, n - 2);
+  }
+  if (deflate && rq > 0) {
+    // Q = Y V_r diag(w_r)^{-1/2}  (n x rq, in Qb); X Q in XQb, then Q^T there
+    std::vector<double> Mq((size_t)p * rq);
+    for (int i = 0; i < p; ++i)
+      for (int c = 0; c < rq; ++c) Mq[(size_t)i * rq + c] = Vv[i * p + idx[c]] / sqrt(wv[idx[c]]);
+    memcpy(P->hbuf + 64, Mq.data(), Mq.size() * sizeof(double));
+    MDSDP_HIP(hipMemcpyAsync(P->gpart + GP_M, P->hbuf + 64, Mq.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    CHK(launch_rightmul(n, p, rq, Y, P->gpart + GP_M, false, Qb, s));
+    CHK(mdsdp_certificate_matvec(P, rq, Qb, XQb, s));
+    CHK(launch_gram(P, rq, Qb, XQb, s));
+    const int pw = P->gram_pw;
+    std::vector<double> G((size_t)pw * pw), Aq((size_t)rq * rq), wa(rq), Va((size_t)rq * rq);
+    CHK(read_dev(P, P->gram + GRAM_U, pw * pw, G.data(), s));
+    double a2 = 0.0;
+    for (int i = 0; i < rq; ++i)
+      for (int j = 0; j < rq; ++j) {
+        Aq[i * rq + j] = 0.5 * (G[(size_t)i * pw + j] + G[(size_t)j * pw + i]);
+        a2 += Aq[i * rq + j] * Aq[i * rq + j];
+      }
+    sym_eig(rq, Aq.data(), wa.data(), Va.data());
+    lmin_A = *std::min_element(wa.begin(), wa.end());
+    lmax_A = *std::max_element(wa.begin(), wa.end());
+    double xq2;
+    {
+      const double* a1[1] = {XQb};
+      CHK(dots(P, 1, a1, a1, (long long)n * rq, &xq2, s));
+    }
+    nB = sqrt(std::max(0.0, xq2 - a2));  // ||X Q - Q A||_F >= ||B||_2
+    CHK(launch_transpose(n, rq, Qb, XQb, s));  // Q^T (rq x n) for the projections
+  } else {
+    rq = 0;
+  }
+  // verify: a fresh random start, the residual alone as the error estimate
+  // and no early stop, i.e. the run stops only once theta_min has converged
+  // (or at the budget)
+  CHK(lanczos(P, eig_tol, budget, seed, &lmin, &lmax, evec, &eit, &conv, s, nvec, 1e-12, &nfound,
+              verify ? nullptr : warm, &lres, !verify, 1, nullptr, nullptr, rq > 0 ? XQb : nullptr, rq, qc, !verify,
+              stop_above));
+  double lo = conv ? lmin : lmin - lres;
+  if (rq > 0) {
+    lo = std::min(lo, lmin_A) - nB;
+    lmax = std::max(lmax, lmax_A);
+  }
+  out->lo = lo;
+  out->lmin = lmin;
+  out->lmax = lmax;
+  out->iters = eit;
+  out->nfound = nfound;
+  out->conv = conv;
+  return MDSDP_OK;
+}
+
 }  // namespace mdsdp
 
 using namespace mdsdp;
@@ -725,6 +827,9 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->direct_admm = 0;
   o->rtr_warm_radius = 1;
   o->rtr_maxiter_polish = 50;
+  o->round_rank_one = 1;
+  o->round_eta = 1e-3;
+  o->round_gap = 0.1;
   o->eig_tol = 1e-10;
   o->eig_maxit = 300;
   o->time_limit_s = 0.0;
@@ -856,6 +961,10 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     set_error("hvp_prec must be MDSDP_FP64 or MDSDP_FP32");
     return MDSDP_EINVAL;
   }
+  if (!(opt->round_eta >= 0.0 && opt->round_gap >= 0.0 && opt->round_gap <= 1.0)) {
+    set_error("need round_eta >= 0 and 0 <= round_gap <= 1");
+    return MDSDP_EINVAL;
+  }
   if (!P || !Ybuf || !res) {
     set_error("NULL argument");
     return MDSDP_EINVAL;
@@ -907,7 +1016,9 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   double stall_cap = INFINITY;   // tolerance cap after an RTR call that took no step
   bool have_evec = false;
   int eig_budget = opt->eig_maxit;
+  const int verify_budget = std::min(n, std::max(4 * opt->eig_maxit, 64));
   double warm_delta = 0.0;
+  int rounded = 0;
   for (k = 0; k < opt->max_outer; ++k) {
     CHK(mdsdp_set_sigma(P, sigma));
     // polishing phase (eta_max < polish_eta): FP64 HVPs and the larger RTR budget
@@ -985,79 +1096,39 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     std::vector<int> idx(p);
     for (int i = 0; i < p; ++i) idx[i] = i;
     std::sort(idx.begin(), idx.end(), [&](int x, int y) { return wv[x] > wv[y]; });
-    // certificate spectrum.  With Q an orthonormal basis of range(Y) and
-    // A = Q^T X Q, B = (I - Q Q^T) X Q, C = the compression of X to the
-    // complement of range(Q): X = [[A, B^T], [B, C]] in [Q, Q_perp], so by
-    // Weyl's inequality lambda_min(X) >= min(lambda_min(A), lambda_min(C)) - ||B||_2.
-    // X Y = grad / 2 is small at a solved subproblem, so A and B are small and
-    // the Lanczos run on C does not have to resolve the cluster of eigenvalues
-    // near zero that range(Y) carries.
     auto te = clk::now();
-    double lmin = 0, lmax = 0;
-    int eit = 0;
-    bool conv = false;
-    int nfound = 0;
-    double lres = 0.0;
-    double lmin_A = 0.0, lmax_A = 0.0, nB = 0.0;
-    int rq = 0;
-    {
-      const double w0 = std::max(0.0, wv[idx[0]]);
-      for (int i = 0; i < p; ++i)
-        if (wv[idx[i]] > 1e-14 * w0) ++rq;
-      rq = std::min(rq, n - 2);
-    }
-    if (opt->deflate && rq > 0) {
-      // Q = Y V_r diag(w_r)^{-1/2}  (n x rq, in W.r); X Q in W.Hd, then Q^T there
-      std::vector<double> Mq((size_t)p * rq);
-      for (int i = 0; i < p; ++i)
-        for (int c = 0; c < rq; ++c) Mq[(size_t)i * rq + c] = Vv[i * p + idx[c]] / sqrt(wv[idx[c]]);
-      memcpy(P->hbuf + 64, Mq.data(), Mq.size() * sizeof(double));
-      MDSDP_HIP(hipMemcpyAsync(P->gpart + GP_M, P->hbuf + 64, Mq.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      CHK(launch_rightmul(n, p, rq, Y, P->gpart + GP_M, false, W.r, s));
-      CHK(mdsdp_certificate_matvec(P, rq, W.r, W.Hd, s));
-      CHK(launch_gram(P, rq, W.r, W.Hd, s));
-      const int pw = P->gram_pw;
-      std::vector<double> G((size_t)pw * pw), Aq((size_t)rq * rq), wa(rq), Va((size_t)rq * rq);
-      CHK(read_dev(P, P->gram + GRAM_U, pw * pw, G.data(), s));
-      double a2 = 0.0;
-      for (int i = 0; i < rq; ++i)
-        for (int j = 0; j < rq; ++j) {
-          Aq[i * rq + j] = 0.5 * (G[(size_t)i * pw + j] + G[(size_t)j * pw + i]);
-          a2 += Aq[i * rq + j] * Aq[i * rq + j];
-        }
-      sym_eig(rq, Aq.data(), wa.data(), Va.data());
-      lmin_A = *std::min_element(wa.begin(), wa.end());
-      lmax_A = *std::max_element(wa.begin(), wa.end());
-      double xq2;
-      {
-        const double* a1[1] = {W.Hd};
-        CHK(dots(P, 1, a1, a1, (long long)n * rq, &xq2, s));
-      }
-      nB = sqrt(std::max(0.0, xq2 - a2));  // ||X Q - Q A||_F >= ||B||_2
-      CHK(launch_transpose(n, rq, W.r, W.Hd, s));  // Q^T (rq x n) for the projections
-    } else {
-      rq = 0;
-    }
-    CHK(lanczos(P, opt->eig_tol, eig_budget, opt->seed + (uint64_t)k, &lmin, &lmax, evec, &eit, &conv, s,
-                std::max(1, opt->n_neg), 1e-12, &nfound, have_evec ? evec : nullptr, &lres, true, 1, nullptr,
-                nullptr, rq > 0 ? W.Hd : nullptr, rq, W.qc, true, -0.5 * opt->tol));
+    CertSpectrum sp;
+    CHK(certificate_spectrum(P, p, Y, wv, Vv, idx, opt->deflate != 0, opt->eig_tol, eig_budget,
+                             opt->seed + (uint64_t)k, std::max(1, opt->n_neg), have_evec ? evec : nullptr, evec, W.r,
+                             W.Hd, W.qc, -0.5 * opt->tol, &sp, s));
     have_evec = true;
-    C.eig_iters += eit;
+    C.eig_iters += sp.iters;
     C.t_eig += secs(te, clk::now());
+    const double lmin = sp.lmin, lmax = sp.lmax, lo = sp.lo;
+    const bool conv = sp.conv;
+    const int nfound = sp.nfound, eit = sp.iters;
     const double normR = kk[0], bty = kk[1], sumz = kk[2], cx = kk[3];
     eta[0] = normR / (1.0 + P->normC);
-    // an unconverged Lanczos only certifies an eigenvalue within its error
-    // estimate of theta_min: use theta_min - estimate then; with deflation the
-    // bound combines the compressions (see above)
-    double lo = conv ? lmin : lmin - lres;
-    if (rq > 0) {
-      lo = std::min(lo, lmin_A) - nB;
-      lmax = std::max(lmax, lmax_A);
-    }
     eta[1] = std::max(0.0, -lo) / (1.0 + fabs(lmax));
     const double prim = cx + sumz;
     eta[2] = fabs(prim - bty) / (1.0 + fabs(prim) + fabs(bty));
     eta_max = std::max(eta[0], std::max(eta[1], eta[2]));
+    if (eta_max <= opt->tol) {
+      // acceptance: eta_d again from a verify run
+      const auto tv = clk::now();
+      CertSpectrum spv;
+      CHK(certificate_spectrum(P, p, Y, wv, Vv, idx, opt->deflate != 0, opt->eig_tol, verify_budget,
+                               opt->seed + (uint64_t)k + 0x632BE59BD9B4E019ull, 1, nullptr, W.it2.d, W.r, W.Hd,
+                               W.qc, 0.0, &spv, s, true));
+      C.eig_iters += spv.iters;
+      C.t_eig += secs(tv, clk::now());
+      eta[1] = std::max(0.0, -spv.lo) / (1.0 + fabs(spv.lmax));
+      eta_max = std::max(eta[0], std::max(eta[1], eta[2]));
+      if (opt->verbose)
+        fprintf(stderr, "[mdsdp] k=%d verified eta_d=%.2e (%d steps%s)\n", k, eta[1], spv.iters,
+                spv.conv ? "" : ", unconverged");
+      if (eta_max > opt->tol) eig_budget = std::min(n, 2 * eig_budget);
+    }
     // when the dual residual (an unconverged Lanczos estimate) is among the
     // largest residuals, give the next eigensolve more steps (it restarts
     // from the current Ritz vector)
@@ -1075,12 +1146,63 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
       hrow[7] = (double)C.hvps;
     }
     if (opt->verbose)
-      fprintf(stderr, "[mdsdp] k=%d p=%d sigma=%.3g eta=(%.2e %.2e %.2e) value=%.10f gnorm=%.2e rtr=%d hvps=%lld eig=%d\n",
-              k, p, sigma, eta[0], eta[1], eta[2], value, rs.gn, rs.iters, C.hvps, eit);
+      fprintf(stderr,
+              "[mdsdp] k=%d p=%d sigma=%.3g eta=(%.2e %.2e %.2e) value=%.10f gnorm=%.2e rtr=%d hvps=%lld eig=%d "
+              "s2/s1=%.2e\n",
+              k, p, sigma, eta[0], eta[1], eta[2], value, rs.gn, rs.iters, C.hvps, eit,
+              p > 1 ? sqrt(std::max(0.0, wv[idx[1]]) / std::max(1e-300, wv[idx[0]])) : 0.0);
     if (eta_max <= opt->tol) {
       final_status = MDSDP_OK;
       ++k;
       break;
+    }
+    // rank-one compression test (Theorem thm:finite-locking, Remark
+    // rem:inexact-near-locking): once Y is close to rank one, eq. res is
+    // evaluated at S1 = Y1 Y1^T, Y1 = sign(Y v_1) (v_1 the leading right
+    // singular vector), with the current multiplier and no multiplier step
+    // (sigma 0 in the update pass: Xt stays, z becomes z(S1)).  The solve
+    // stops there when that point meets the tolerance; otherwise nothing of
+    // the iteration changes (the next multiplier update recomputes z).
+    if (opt->round_rank_one && !opt->direct_admm && eta_max < opt->round_eta &&
+        (p == 1 || wv[idx[1]] <= opt->round_gap * opt->round_gap * wv[idx[0]])) {
+      const auto tr = clk::now();
+      for (int i = 0; i < p; ++i) P->hbuf[64 + i] = Vv[i * p + idx[0]];
+      MDSDP_HIP(hipMemcpyAsync(P->gpart + GP_M, P->hbuf + 64, p * sizeof(double), hipMemcpyHostToDevice, s));
+      double* Y1 = W.it2.eta;
+      CHK(launch_sign_col(n, p, Y, P->gpart + GP_M, Y1, s));
+      const double sigma_keep = P->sigma;
+      P->sigma = 0.0;
+      const mdsdp_status ust = mdsdp_update_multiplier(P, 1, Y1, nullptr, nullptr, P->scal + SC_KKT, s);
+      P->sigma = sigma_keep;
+      CHK(ust);
+      double k1[4];
+      CHK(read_dev(P, P->scal + SC_KKT, 4, k1, s));
+      double eta1[3] = {k1[0] / (1.0 + P->normC), INFINITY,
+                        fabs(k1[3] + k1[2] - k1[1]) / (1.0 + fabs(k1[3] + k1[2]) + fabs(k1[1]))};
+      // the eigensolve only for a point that is feasible and has no gap
+      if (eta1[0] <= opt->tol && eta1[2] <= opt->tol) {
+        const std::vector<double> w1(1, (double)n), V1(1, 1.0);
+        const std::vector<int> i1(1, 0);
+        CertSpectrum sp1;
+        CHK(certificate_spectrum(P, 1, Y1, w1, V1, i1, opt->deflate != 0, opt->eig_tol,
+                                 std::max(eig_budget, verify_budget), opt->seed + (uint64_t)k + 0x9E3779B97F4A7C15ull,
+                                 1, nullptr, W.it2.d, W.it2.Heta, W.it2.r, W.qc, 0.0, &sp1, s, true));
+        C.eig_iters += sp1.iters;
+        eta1[1] = std::max(0.0, -sp1.lo) / (1.0 + fabs(sp1.lmax));
+      }
+      C.t_eig += secs(tr, clk::now());
+      if (opt->verbose)
+        fprintf(stderr, "[mdsdp] k=%d rank-one compression eta=(%.2e %.2e %.2e)\n", k, eta1[0], eta1[1], eta1[2]);
+      if (std::max(eta1[0], std::max(eta1[1], eta1[2])) <= opt->tol) {
+        MDSDP_HIP(hipMemcpyAsync(Y, Y1, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        p = 1;
+        for (int i = 0; i < 3; ++i) eta[i] = eta1[i];
+        value = k1[1];
+        rounded = 1;
+        final_status = MDSDP_OK;
+        ++k;
+        break;
+      }
     }
     if (opt->time_limit_s > 0 && secs(t_start, clk::now()) > opt->time_limit_s) {
       ++k;
@@ -1145,6 +1267,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
   res->t_hvp = C.t_hvp;
   res->t_eig = C.t_eig;
   res->t_update = C.t_update;
+  res->rank_one_round = rounded;
   if (final_status == MDSDP_ENONFINITE) return MDSDP_ENONFINITE;
   return final_status == MDSDP_OK ? MDSDP_OK : MDSDP_ENOCONV;
 }

@@ -108,6 +108,7 @@ class SolveResult:
     seconds: float
     phases: dict
     history: np.ndarray
+    rank_one_round: bool = False  # the final point is the rank-one compression
 
 
 class Problem:
@@ -380,4 +381,5 @@ class Problem:
                            cost_grads=res.cost_grads, eig_iters=res.eig_iters, p_final=res.p_final,
                            p_max_reached=res.p_max_reached, sigma=res.sigma, seconds=res.seconds,
                            phases=dict(eval=res.t_eval, hvp=res.t_hvp, eig=res.t_eig, update=res.t_update),
-                           history=hist[: min(res.outer_iters, history_cap)].copy())
+                           history=hist[: min(res.outer_iters, history_cap)].copy(),
+                           rank_one_round=bool(res.rank_one_round))

@@ -166,6 +166,8 @@ def test_nonfinite_classmap_data_rejected_on_host(where):
     ("kappa1", 20.0, b"kappa1"),           # kappa1 > kappa2
     ("gamma", 1.0, b"gamma"),
     ("hvp_prec", 7, b"hvp_prec"),
+    ("round_gap", 1.5, b"round_gap"),
+    ("round_eta", -1.0, b"round_eta"),
 ])
 def test_solver_options_validated_first(field, value, msg):
     """Invalid options of Algorithm alg1 / eq. sec5:eq1 are rejected with
@@ -176,6 +178,7 @@ def test_solver_options_validated_first(field, value, msg):
     o = _lib.Options()
     L.mdsdp_default_options(C.byref(o))
     assert o.sigma_hold == 1 and o.escape_when_solved == 0 and o.gtol_ratio > 0 and o.rtr_maxiter == 10
+    assert o.round_rank_one == 1 and o.round_eta == 1e-3 and o.round_gap == 0.1
     setattr(o, field, value)
     res = _lib.Result()
     assert L.mdsdp_solve(None, C.byref(o), 2, None, C.byref(res), None, 0, None) == -1

@@ -175,3 +175,47 @@ def test_solve_q40_mixed_and_fp64_match_oracle_value():
     assert abs(r32.value - r64.value) <= 1e-8 * (1 + abs(r64.value))
     x, fx = alm.rank_one_rounding(r32.Y.cpu().numpy(), Q, c, None)
     assert abs(fx - r32.value) <= 1e-8 * (1 + abs(fx))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rank_one_compression_certified_by_oracle(prec):
+    """The rank-one compression test (Theorem thm:finite-locking, Remark
+    rem:inexact-near-locking) tried after every outer step (round_eta =
+    round_gap = 1) on q = 20: the solve reaches the brute-force minimum; when
+    it stops at the compressed point, that point is a sign vector and the
+    oracle, recomputing eq. res from it and the GPU's multiplier with dense
+    LAPACK, finds eta_max <= 1e-8.  With the test off the value is the same."""
+    from paper_2512_04406_amd.problem import ORDER_COLEX, Problem
+
+    Q, c = bqp_instance(20, 1)
+    fmin, _ = brute.brute_force_min(Q, c)
+    rel = bqp.build_relaxation(Q, c, "colex")
+    prob = Problem.bqp(Q, c, ORDER_COLEX)
+    out = {}
+    for mode in ("on", "off"):
+        o = prob.default_options()
+        o.hvp_prec = prec
+        if mode == "on":
+            o.round_eta, o.round_gap = 1.0, 1.0
+        else:
+            o.round_rank_one = 0
+        print(f"[round] q=20 prec={prec} {mode}", flush=True)
+        r = prob.solve(_t(gaussian(prob.n, 3, 7)), o)
+        print(f"   value={r.value:.10f} eta={r.eta} outer={r.outer_iters} p={r.p_final} "
+              f"rounded={r.rank_one_round}", flush=True)
+        assert r.status == 0 and max(r.eta) <= 1e-8
+        assert abs(r.value - fmin) <= 1e-8 * (1 + abs(fmin))
+        out[mode] = r
+        if r.rank_one_round:
+            assert mode == "on"
+            Y = r.Y.cpu().numpy()
+            assert Y.shape == (prob.n, 1) and np.all(np.abs(Y) == 1.0)
+            Xt = prob.get_multiplier().cpu().numpy()
+            S = Y @ Y.T
+            y = rel_class_average(S, rel)
+            D = D_matrix(rel.b, rel.cls, rel.counts)
+            z = np.einsum("ij,ij->i", (Xt + D) @ Y, Y)
+            eta = alm.kkt_residuals(S, y, Xt + D - np.diag(z), z, rel.b, rel.cls)
+            print(f"   oracle eta={eta}", flush=True)
+            assert max(eta) <= 2e-8
+    assert out["on"].outer_iters <= out["off"].outer_iters

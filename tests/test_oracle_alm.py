@@ -108,3 +108,90 @@ def test_adjoint_of_value_in_C_by_central_differences():
     vm = alm.solve(rel.cls, rel.counts, rel.b, Y0, opts, C=G - eps * E).value
     fd = (vp - vm) / (2 * eps)
     assert abs(fd - pred) <= 1e-3 * (1 + abs(pred))
+
+
+def _rel_and_point(q, seed, order="colex"):
+    Q, c = bqp_instance(q, seed)
+    rel = bqp.build_relaxation(Q, c, order)
+    fmin, xmin = brute.brute_force_min(Q, c)
+    return Q, c, rel, fmin, np.asarray(xmin, dtype=float)
+
+
+def test_rank_one_candidate_of_a_near_rank_one_moment_factor():
+    """Remark rem:inexact-near-locking: the compression of a factor close to
+    v(x) v(x)^T is v(x) itself (exact signs), and S1 = v(x) v(x)^T is a
+    feasible moment matrix, so R = A*(y) - S1 = 0 and, for any multiplier Xt in
+    the range of Q, <Xt, S1> = 0 and sum z = <D, S1> = b^T y: eta_p = eta_g = 0
+    whatever Xt is (only eta_d depends on Xt)."""
+    from oracle.operators import D_matrix
+
+    q = 7
+    Q, c, rel, fmin, xmin = _rel_and_point(q, 3)
+    v = bqp.monomial_vector(xmin, "colex")
+    rng = np.random.default_rng(11)
+    Y = np.hstack([v[:, None], 0.05 * rng.standard_normal((rel.n, 3))])
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    W = rng.standard_normal((rel.n, rel.n))
+    Xt = Q_op(W + W.T, rel.cls, rel.counts)
+    D = D_matrix(rel.b, rel.cls, rel.counts)
+    cand = alm._rank_one_candidate(Y, Xt, D, rel.cls, rel.counts, rel.b, None, None, 0.1)
+    assert cand is not None
+    Y1, y1, z1, X1, S1, eta = cand
+    assert Y1.shape == (rel.n, 1)
+    assert np.array_equal(Y1[:, 0], v) or np.array_equal(Y1[:, 0], -v)
+    assert eta[0] <= 1e-14 and eta[2] <= 1e-13
+    # b^T y is the BQP objective at x (the relaxation's linear form on v(x) v(x)^T)
+    assert abs(float(rel.b @ y1) - float(xmin @ Q @ xmin + c @ xmin)) <= 1e-12 * (1 + abs(fmin))
+    # X1 v = 0 exactly (z is the row sum that cancels it), so lambda_min(X1) <= 0
+    assert np.max(np.abs(X1 @ Y1[:, 0])) <= 1e-10 * (1 + np.max(np.abs(X1)))
+
+
+def test_rank_one_candidate_gap_gate_and_infeasible_signs():
+    """No candidate while s_2 > gap s_1; a sign pattern that is not a moment
+    vector gives a nonzero primal residual, so the test can only reject it."""
+    from oracle.operators import D_matrix
+
+    Q, c, rel, fmin, xmin = _rel_and_point(6, 1)
+    rng = np.random.default_rng(5)
+    D = D_matrix(rel.b, rel.cls, rel.counts)
+    Xt = np.zeros((rel.n, rel.n))
+    Y = rng.standard_normal((rel.n, 4))
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    assert alm._rank_one_candidate(Y, Xt, D, rel.cls, rel.counts, rel.b, None, None, 0.1) is None
+    u = np.where(rng.standard_normal(rel.n) >= 0, 1.0, -1.0)
+    u[0] = 1.0
+    v = bqp.monomial_vector(xmin, "colex")
+    if np.array_equal(u, v) or np.array_equal(u, -v):
+        u[-1] = -u[-1]
+    cand = alm._rank_one_candidate(u[:, None], Xt, D, rel.cls, rel.counts, rel.b, None, None, 0.1)
+    assert cand is not None and cand[5][0] > 1e-3
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_rank_one_compression_does_not_change_the_optimum(seed):
+    """With the compression test on (default) and off, the q = 10 solve ends
+    at the brute-force minimum; when it accepts the compressed point that
+    point meets eta_max <= 1e-8 and its factor is a sign vector."""
+    Q, c, rel, fmin, xmin = _rel_and_point(10, seed)
+    Y0 = gaussian(rel.n, 2, 100 + seed)
+    on = alm.solve(rel.cls, rel.counts, rel.b, Y0, alm.ALMOptions(round_eta=1.0, round_gap=1.0))
+    off = alm.solve(rel.cls, rel.counts, rel.b, Y0, alm.ALMOptions(round_rank_one=False))
+    for r in (on, off):
+        assert max(r.eta) <= 1e-8
+        assert abs(r.value - fmin) <= 1e-8 * (1 + abs(fmin))
+    if on.history[-1].get("rounded"):
+        assert on.Y.shape[1] == 1 and np.all(np.abs(on.Y) == 1.0)
+    assert len(on.history) <= len(off.history) + 1
+
+
+@pytest.mark.parametrize("kw", [dict(sigma_hold=False), dict(escape_when_solved=True),
+                                dict(rtr_maxiter=50, rtr_maxiter_polish=50)])
+def test_readings_of_the_outer_loop_reach_the_same_optimum(kw):
+    """The sigma rule as printed (no hold), the escape gated on solved
+    subproblems, and one fixed RTR budget of 50 iterations all end at the
+    brute-force minimum at q = 10 with eta_max <= 1e-8: the readings change
+    the path of the iteration, not its limit."""
+    Q, c, rel, fmin, xmin = _rel_and_point(10, 2)
+    r = alm.solve(rel.cls, rel.counts, rel.b, gaussian(rel.n, 2, 102), alm.ALMOptions(**kw))
+    assert max(r.eta) <= 1e-8
+    assert abs(r.value - fmin) <= 1e-8 * (1 + abs(fmin))
