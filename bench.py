@@ -390,12 +390,13 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("fp32 MFMA tiles (HVP product pass) + fp64 (class sums, gradient, multiplier, KKT)"
-                  if hvp_prec == FP32 else "f64"),
+        "dtype": "f32+f64" if hvp_prec == FP32 else "f64",
+        "dtype_detail": ("f32 MFMA tiles in the HVP product pass; f64 class sums, gradient, multiplier update, "
+                         "eigensolve and KKT" if hvp_prec == FP32 else "f64 throughout"),
         "data": "synthetic",
         "config": {"workload": f"dense BQP q={q} n={n} m={m}, Q,c ~ N(0,1) seed {args.seed}, order-2 moment "
                                f"relaxation, ManiDSDP outer iterations at rank <= {args.p_steps} from p0={p}",
-                   "global_batch": 1, "seq_len": n, "parallelism": "single GPU"},
+                   "q": q, "n": n, "m": m, "p0": p, "p_max": args.p_steps, "seed": args.seed},
         "timed_steps": {"hvps": r_t.hvps, "seconds": total, "eta_max_after": max(r_t.eta), "p_final": r_t.p_final,
                         "sigma": r_t.sigma, "phases_s": r_t.phases},
         "fp64_steps": fp64_steps,

@@ -260,6 +260,17 @@ mdsdp_status mdsdp_certificate_estimate(mdsdp_problem prob, double tol, int32_t 
 /* Adjoint of the optimal value w.r.t. C: dv/dC = X + Diag z = Xt + D
  * (Lagrangian duality, dual problem PSDP).  Writes a dense n x n FP64 device
  * matrix. */
+/* Certified lower bound of lambda_min of the certificate X = Xt + D - Diag(z)
+ * (z of the last mdsdp_update_multiplier) as a solve ends on it (eq. res,
+ * eta_d): Lanczos on the complement of range(Y) (Y_dev: n x p FP64 device,
+ * 1 <= p <= min(512, n - 2)) from a random start, run until theta_min has
+ * converged to tol (1 + |theta_max|) or maxit steps, combined with the
+ * compression to range(Y): lambda_min(X) >= the smaller eigenvalue of
+ * [[lambda_min(Q^T X Q), -||B||], [-||B||, lambda_min(C)]] (B the coupling,
+ * C the complement block).  out_host[4] = {lower bound, largest Ritz value,
+ * Lanczos steps, converged (1/0)}.  Allocates its work buffers. */
+mdsdp_status mdsdp_certificate_bound(mdsdp_problem prob, int32_t p, const double* Y_dev, double tol,
+                                    int32_t maxit, uint64_t seed, double* out_host, void* stream);
 mdsdp_status mdsdp_adjoint_C(mdsdp_problem prob, double* dC_dev, void* stream);
 
 /* ---- full solve (Algorithm alg1 with RTR + truncated CG) ------------------- */
@@ -268,7 +279,8 @@ typedef struct {
   int32_t max_outer;   /* default 200 */
   double sigma0, sigma_min, sigma_max, gamma, kappa1, kappa2; /* eq. sec5:eq1 */
   int32_t p_max;       /* largest factor width, 1..512 (default 512) */
-  int32_t n_neg;       /* negative-curvature directions added per outer step (Theorem sec5:thm1) */
+  int32_t n_neg;       /* negative-curvature directions added per outer step (Theorem sec5:thm1);
+                          default 15, so that one column plus the carried ones fit 16-column tiles */
   double tau_rank;     /* drop singular directions below tau_rank * s_1 */
   double gtol0, gtol_min;  /* inner tolerance of subproblem k (see gtol_ratio); default 1e-2, 1e-10 */
   double gtol_decay;   /* in (0, 1]; used only when gtol_ratio <= 0 */
@@ -315,6 +327,10 @@ typedef struct {
                           iteration is unchanged otherwise.  0: off */
   double round_eta;    /* default 1e-3 */
   double round_gap;    /* in [0, 1], default 0.1 */
+  int32_t tcg_maxinner_polish; /* truncated-CG steps per RTR iteration once eta_max < polish_eta
+                          (default 1000; before that tcg_maxinner) */
+  int32_t rtr_stall;   /* > 0: an RTR call also ends after this many consecutive iterations that leave
+                          ||grad|| above 0.9 times its best value in the call; 0 (default): off */
 } mdsdp_options;
 
 typedef struct {

@@ -23,7 +23,8 @@ Readings of points the paper leaves open:
 * rank rule (delegated by the paper to ManiSDP section 5.1, not in the text):
   after each subproblem, drop singular directions of Y below tau_rank * s_1
   (Y <- Y V_r, rows renormalised), then append one zero column per carried
-  eigenvector (at most n_neg of them, p <= p_max).
+  eigenvector (at most n_neg = 15 of them, p <= p_max; near a rank-one
+  solution the factor then has 16 columns).
 * inner tolerance: RTR for subproblem k stops at ||grad|| <= gtol_k with
   gtol_k = max(gtol_min, min(gtol0, gtol_ratio ||R^k|| / (1 + ||b||))), i.e. the
   subproblem is solved to a fixed fraction of the same scaled primal residual
@@ -46,8 +47,12 @@ Readings of points the paper leaves open:
   increase branch and the rule after a solved subproblem are as printed;
   sigma_hold = False applies the rule as printed after every step).
 * inner budget: the subproblem is solved approximately (Algorithm alg1 step
-  3): at most rtr_maxiter = 10 RTR iterations, and rtr_maxiter_polish = 50
-  once eta_max < polish_eta = 1e-4 (the polishing phase).
+  3): at most rtr_maxiter = 10 RTR iterations of at most tcg_maxinner = 200
+  truncated-CG steps, and rtr_maxiter_polish = 50 of at most
+  tcg_maxinner_polish = 1000 once eta_max < polish_eta = 1e-4 (the polishing
+  phase: near the solution the subproblem Hessian is ill-conditioned, and
+  with 200 steps the inner gradient stalls above the tolerance, so the rule
+  of eq. sec5:eq1 can never raise sigma).
 * carried direction (step 9): formed after every outer step whose
   certificate has an eigenvalue below -max(neg_tol, tol) (1 + |lambda_max|)
   (curvature below the stopping tolerance's scale adds no columns); with
@@ -88,7 +93,7 @@ class ALMOptions:
     kappa1: float = 0.1
     kappa2: float = 10.0
     p_max: int = 512
-    n_neg: int = 16
+    n_neg: int = 15
     tau_rank: float = 1e-4
     gtol0: float = 1e-2
     gtol_min: float = 1e-10
@@ -100,6 +105,9 @@ class ALMOptions:
     direct: bool = False  # the direct-DSDP ADMM subproblem (ablation), see DirectSubproblem
     rtr_maxiter: int = 10
     rtr_maxiter_polish: int = 50
+    tcg_maxinner: int = 200
+    tcg_maxinner_polish: int = 1000
+    rtr_stall: int = 0  # > 0: RTR also stops after this many iterations without progress
     polish_eta: float = 1e-4
     neg_tol: float = 1e-12
     round_rank_one: bool = True  # rank-one compression test (Remark rem:inexact-near-locking)
@@ -214,8 +222,10 @@ def solve(cls: np.ndarray, counts: np.ndarray, b: np.ndarray, Y0: np.ndarray,
         else:
             g = min(opts.gtol0, 0.1 * eta_max, opts.gtol_decay * gtol)
         gtol = max(opts.gtol_min, min(g, stall_cap))
-        budget = max(opts.rtr_maxiter, opts.rtr_maxiter_polish) if eta_max < opts.polish_eta else opts.rtr_maxiter
-        res = rtr(sub, Y, gtol, maxiter=budget)
+        polish = eta_max < opts.polish_eta
+        budget = max(opts.rtr_maxiter, opts.rtr_maxiter_polish) if polish else opts.rtr_maxiter
+        inner = max(opts.tcg_maxinner, opts.tcg_maxinner_polish) if polish else opts.tcg_maxinner
+        res = rtr(sub, Y, gtol, maxiter=budget, maxinner=inner, max_stall=opts.rtr_stall)
         if opts.gtol_stall > 0.0 and res.iters == 0 and res.gradnorm > 0.0:
             stall_cap = min(stall_cap, opts.gtol_stall * res.gradnorm)
         Y = res.Y

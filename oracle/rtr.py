@@ -92,7 +92,10 @@ class RTRResult:
 def rtr(sub: Subproblem, Y: np.ndarray, gradtol: float, maxiter: int = 50,
         Delta0: float | None = None, Delta_bar: float | None = None,
         rho_prime: float = 0.1, kappa: float = 0.1, theta: float = 1.0,
-        maxinner: int = 200) -> RTRResult:
+        maxinner: int = 200, max_stall: int = 0) -> RTRResult:
+    """max_stall > 0: also stop after max_stall consecutive iterations that
+    leave the gradient norm above 0.9 times the best value of this call (the
+    gradient is then at the level of its rounding errors)."""
     n = Y.shape[0]
     if Delta_bar is None:
         Delta_bar = math.pi * math.sqrt(n)
@@ -102,8 +105,10 @@ def rtr(sub: Subproblem, Y: np.ndarray, gradtol: float, maxiter: int = 50,
     gn = math.sqrt(_inner(g, g))
     n_hvp = 0
     it = 0
+    gn_best = gn
+    stall = 0
     for it in range(1, maxiter + 1):
-        if gn <= gradtol:
+        if gn <= gradtol or (max_stall > 0 and stall >= max_stall):
             it -= 1
             break
         eta, Heta, nh, stop = tcg(sub, Y, g, Delta, kappa, theta, maxinner)
@@ -121,4 +126,8 @@ def rtr(sub: Subproblem, Y: np.ndarray, gradtol: float, maxiter: int = 50,
             Y, f = Yp, fp
             g = sub.rgrad(Y)
             gn = math.sqrt(_inner(g, g))
+        if gn < 0.9 * gn_best:
+            gn_best, stall = gn, 0
+        else:
+            stall += 1
     return RTRResult(Y=Y, f=f, grad=g, gradnorm=gn, iters=it, n_hvp=n_hvp)

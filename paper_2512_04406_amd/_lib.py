@@ -37,7 +37,8 @@ class Options(C.Structure):
                 ("time_limit_s", _f64), ("verbose", _i32), ("seed", _u64),
                 ("resume", _i32), ("escape_when_solved", _i32), ("deflate", _i32),
                 ("direct_admm", _i32), ("rtr_warm_radius", _i32), ("rtr_maxiter_polish", _i32),
-                ("round_rank_one", _i32), ("round_eta", _f64), ("round_gap", _f64)]
+                ("round_rank_one", _i32), ("round_eta", _f64), ("round_gap", _f64),
+                ("tcg_maxinner_polish", _i32), ("rtr_stall", _i32)]
 
 
 class Result(C.Structure):
@@ -78,6 +79,7 @@ SIGNATURES = {
     "mdsdp_sync_status": (_i32, [_vp, _vp]),
     "mdsdp_min_eigpair_noalloc": (_i32, [_vp, _i32, _f64, _i32, _u64, _vp, _pf64, _vp, _pi32, _vp]),
     "mdsdp_set_direct": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "mdsdp_certificate_bound": (_i32, [_vp, _i32, _vp, _f64, _i32, _u64, _vp, _vp]),
     "mdsdp_certificate_estimate": (_i32, [_vp, _f64, _i32, _u64, _vp, _vp, _vp, _pi32, _vp]),
     "mdsdp_adjoint_C": (_i32, [_vp, _vp, _vp]),
     "mdsdp_default_options": (None, [C.POINTER(Options)]),

@@ -330,32 +330,37 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
     const long long t = (long long)sg.J * (sg.J + 1) / 2 + I;
     const bool diag = (I == sg.J);
     const double wgt = diag ? 1.0 : 2.0;
-    // ---- batched memory phase for this wave's 16 x 64 slab of the tile ----
+    // ---- memory phase for this wave's 16 x 64 slab of the tile, in two
+    // halves of two 16 x 16 sub-blocks each (half the registers of one batch
+    // of sixteen entries per lane: more waves per SIMD hide the latency) ----
     typedef typename std::conditional<sizeof(T) == 8 || MODE != M_HVP, double, float>::type XT;
     const size_t tb = (size_t)t * TSLOTS + (size_t)(w * 4) * 256 + li;
-    uint32_t cwv[4][4];
-    XT xv[4][4];
+    uint32_t cwv[2][4];
+    XT xv[2][4];
+    double2 dyv[2][4];  // {D, y}, or for the HVP {D - sigma y, -sigma y'}
+    auto load_half = [&](int h) {
 #pragma unroll
-    for (int sc = 0; sc < 4; ++sc)
+      for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const size_t off = tb + sc * 256 + drow<T>(lk, v) * 16;
-        cwv[sc][v] = a.cls[off];
-        if (sizeof(XT) == 8)
-          xv[sc][v] = (XT)a.Xt[off];
-        else
-          xv[sc][v] = (XT)a.Xt32[slot32(off)];
-      }
-    double2 dyv[4][4];  // {D, y}, or for the HVP {D - sigma y, -sigma y'}
+        for (int v = 0; v < 4; ++v) {
+          const size_t off = tb + (2 * h + s2) * 256 + drow<T>(lk, v) * 16;
+          cwv[s2][v] = a.cls[off];
+          if (sizeof(XT) == 8)
+            xv[s2][v] = (XT)a.Xt[off];
+          else
+            xv[s2][v] = (XT)a.Xt32[slot32(off)];
+        }
 #pragma unroll
-    for (int sc = 0; sc < 4; ++sc)
+      for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const uint32_t cw = cwv[sc][v];
-        const bool valid = !(cw & 0x80000000u);
-        const uint32_t id = valid ? (cw & CLS_MASK) : 0u;
-        dyv[sc][v] = (MODE == M_HVP) ? a.ab64[id] : a.cy[id];
-      }
+        for (int v = 0; v < 4; ++v) {
+          const uint32_t cw = cwv[s2][v];
+          const bool valid = !(cw & 0x80000000u);
+          const uint32_t id = valid ? (cw & CLS_MASK) : 0u;
+          dyv[s2][v] = (MODE == M_HVP) ? a.ab64[id] : a.cy[id];
+        }
+    };
+    load_half(0);
     // S blocks of the four sub-blocks (MFMA from LDS, K = p)
     v4 Sbv[4];
 #pragma unroll
@@ -397,22 +402,24 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
     for (int c = 0; c < NC; ++c) accR[c] = v4{0, 0, 0, 0};
 #pragma unroll
     for (int sc = 0; sc < 4; ++sc) {
+      if (sc == 2) load_half(1);
+      const int s2 = sc & 1;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int rv = drow<T>(lk, v);
         const size_t off = tb + sc * 256 + rv * 16;
-        const uint32_t cw = cwv[sc][v];
+        const uint32_t cw = cwv[s2][v];
         const bool valid = !(cw & 0x80000000u);
         T av = 0, bv = 0;
         if (valid) {
           // class data times the slot's coefficient w_e: {w D, w y} (or the HVP pair)
           const double we = coef_of(cw);
-          const double2 dy = make_double2(we * dyv[sc][v].x, we * dyv[sc][v].y);
+          const double2 dy = make_double2(we * dyv[s2][v].x, we * dyv[s2][v].y);
           const double Ce = a.Ct ? a.Ct[off] : 0.0;
           if (MODE == M_GRAD || MODE == M_MULT) {
             const double Zv = (double)Sbv[sc][v] + Ce;
             const double r = Zv - dy.y;
-            const double x = (double)xv[sc][v];
+            const double x = (double)xv[s2][v];
             p_r2 += wgt * r * r;
             if (MODE == M_GRAD) {
               p_xz += wgt * x * Zv;
@@ -428,10 +435,10 @@ __global__ __launch_bounds__(256) void k_resid(KArgs a) {
               av = (T)(xn + dy.x);
             }
           } else if (MODE == M_XMV) {
-            av = (T)((double)xv[sc][v] + dy.x);
+            av = (T)((double)xv[s2][v] + dy.x);
           } else {  // HVP (FP64 tiles; the FP32-tile HVP is k_hvp32)
             bv = (T)dy.y;
-            av = (T)((double)xv[sc][v] + dy.x + sigma * Ce);
+            av = (T)((double)xv[s2][v] + dy.x + sigma * Ce);
           }
         }
         tAw[rv * LP + li] = av;

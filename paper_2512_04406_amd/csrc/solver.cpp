@@ -28,9 +28,10 @@
 //    at its iteration budget: ||grad|| then measures an unfinished inner
 //    solve, not a dual residual, and with a 10-step budget the printed rule
 //    drives sigma down on every step of a large instance;
-//  * inner budget: rtr_maxiter (10) RTR iterations per subproblem until
-//    eta_max < polish_eta (1e-4), rtr_maxiter_polish (50) after that, when the
-//    HVPs also switch to FP64 (polish_fp64);
+//  * inner budget: rtr_maxiter (10) RTR iterations of at most tcg_maxinner
+//    (200) truncated-CG steps per subproblem until eta_max < polish_eta
+//    (1e-4); rtr_maxiter_polish (50) of at most tcg_maxinner_polish (1000)
+//    after that, when the HVPs also switch to FP64 (polish_fp64);
 //  * carried direction: backtracking t = sqrt(n), sqrt(n)/2, ... along
 //    R_[Y,0](t [0, v]) until Psi_k decreases, then RTR.  By default the
 //    direction and its zero columns are added after every outer step whose
@@ -38,8 +39,10 @@
 //    (step 9 of Algorithm alg1); escape_when_solved restricts that to steps
 //    whose RTR call reached its tolerance;
 //  * rank rule: drop singular directions of Y below tau_rank * s_1, then add
-//    one zero column per carried negative eigenvector (at most n_neg per
-//    outer step, p <= p_max);
+//    one zero column per carried negative eigenvector (at most n_neg = 15 per
+//    outer step, p <= p_max): near the solution the factor is one column plus
+//    the carried ones, and 16 columns fill the 16-column MFMA tiles exactly
+//    (17 are staged as 32 and cost 1.8 times as much per HVP);
 //  * sigma rule eq. sec5:eq1 with ||R|| = ||Q(Z)||_F and the final ||grad||;
 //  * rank-one compression (Theorem thm:finite-locking, Remark
 //    rem:inexact-near-locking): once eta_max < round_eta and s_2 <= round_gap
@@ -443,11 +446,12 @@ struct RTRState {
   double f = 0, gn = 0;
   int iters = 0;
   double Delta0 = 0.0;  // in: initial radius (0: Delta_bar / 8); out: the final radius
+  bool stalled = false; // out: the call ended on the stall stop
 };
 
 mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, int maxinner, int prec,
                  Work& W, Counters& C, RTRState& st, hipStream_t s, int verbose = 0,
-                 clk::time_point deadline = clk::time_point::max()) {
+                 clk::time_point deadline = clk::time_point::max(), int max_stall = 0) {
   const int n = P->n;
   const long long len = (long long)n * p;
   const double Delta_bar = M_PI * sqrt((double)n);
@@ -465,8 +469,18 @@ mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, i
     return MDSDP_ENONFINITE;
   }
   int it = 0;
+  // stall stop (max_stall > 0): the call ends after max_stall consecutive
+  // iterations that leave the gradient norm above 0.9 times the best so far
+  // (the gradient has reached the level of its rounding errors)
+  double gn_best = gn;
+  int stall = 0;
+  st.stalled = false;
   for (; it < maxiter; ++it) {
     if (gn <= gtol) break;
+    if (max_stall > 0 && stall >= max_stall) {
+      st.stalled = true;
+      break;
+    }
     int stop = 0;
     const long long hv0 = C.hvps;
     const double Delta_used = Delta;
@@ -501,6 +515,12 @@ mdsdp_status rtr(mdsdp_problem P, int p, double*& Y, double gtol, int maxiter, i
       CHK(eval(P, p, Y, W.g, &fcur, C, s));
     }
     C.rtr_iters++;
+    if (gn < 0.9 * gn_best) {
+      gn_best = gn;
+      stall = 0;
+    } else {
+      ++stall;
+    }
     if (clk::now() > deadline) {
       ++it;
       break;
@@ -527,7 +547,7 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
                             double* resid_out = nullptr, bool use_gap = false, int kconv = 1,
                             double* evals_out = nullptr, double* ext = nullptr, const double* Qd = nullptr,
                             int rq = 0, double* qc = nullptr, bool stop_nonneg = false,
-                            double stop_above = 0.0) {
+                            double stop_above = 0.0, double neg_resolve = 0.0, double reject_below = 0.0) {
   const int n = P->n;
   maxit = std::max(2, std::min(maxit, n));
   // basis V (n x (maxit + 1)), w (n), h (4 maxit + 16): the caller's fixed
@@ -597,9 +617,9 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
   // The recurrence runs on the device: step j stores alpha_j and beta_j^2 in
   // alpha_d[j], beta2_d[j] and normalises the next basis vector by the
   // device value, so the host reads the scalars only every LZ_BATCH steps;
-  // it then replays the convergence tests step by step on those scalars, so
-  // the stopping step is the same as with a read-back after every step (the
-  // steps enqueued beyond it are discarded).
+  // it then replays the convergence tests on those scalars, step by step for
+  // the first 24 steps and at the last step of each batch after that (the
+  // steps enqueued beyond a stop are discarded).
   constexpr int LZ_BATCH = 8;
   double* alpha_d = h + 2 * maxit + 8;
   double* beta2_d = alpha_d + maxit;
@@ -627,6 +647,13 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
       al.push_back(P->hbuf[j - j0]);
       const double bj = sqrt(std::max(0.0, P->hbuf[LZ_BATCH + j - j0]));
       k = j + 1;
+      // the tests cost O(k) host work per Ritz value (bisection, inverse
+      // iteration): every step while k is small, then at the end of each batch
+      // (and at a vanishing beta_j, where the run must stop)
+      if (k >= 24 && j != j1 - 1 && !(bj <= 1e-14 * (1.0 + fabs(th_max)))) {
+        be.push_back(bj);
+        continue;
+      }
       th_min = tridiag_eig(k, al.data(), be.data(), 0);
       th_max = tridiag_eig(k, al.data(), be.data(), k - 1);
       tridiag_evec(k, al.data(), be.data(), th_min, sv);
@@ -661,6 +688,23 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
       // the dual residual and the curvature test need
       if (stop_nonneg && k >= 3 && th_min - err >= stop_above * (1.0 + fabs(th_max))) {
         *converged = true;
+        stop = true;
+        break;
+      }
+      // negative curvature resolved (neg_resolve > 0): theta_min lies below
+      // -neg_resolve (1 + |theta_max|) and its error estimate is at most a
+      // tenth of |theta_min|; lambda_min <= theta_min, so the certificate is
+      // not PSD.  (Not used by the solver: stopping there leaves few and poor
+      // Ritz vectors for the carried directions, and at q = 100 the rank then
+      // grew four times slower and the solve stalled.)
+      if (neg_resolve > 0.0 && k >= 3 && th_min < -neg_resolve * (1.0 + fabs(th_max)) && err <= 0.1 * fabs(th_min)) {
+        *converged = true;
+        stop = true;
+        break;
+      }
+      // rejection (reject_below < 0): lambda_min <= theta_min < reject_below
+      // (1 + |theta_max|) already decides the test the caller makes
+      if (reject_below < 0.0 && k >= 3 && th_min < reject_below * (1.0 + fabs(th_max))) {
         stop = true;
         break;
       }
@@ -700,8 +744,11 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
 // last multiplier update) for eta_d of eq. res and the curvature test of
 // Theorem sec5:thm1.  With Q an orthonormal basis of range(Y) and
 // A = Q^T X Q, B = (I - Q Q^T) X Q, C = the compression of X to the complement
-// of range(Q): X = [[A, B^T], [B, C]] in [Q, Q_perp], so by Weyl's inequality
-// lambda_min(X) >= min(lambda_min(A), lambda_min(C)) - ||B||_2.  X Y = grad / 2
+// of range(Q): X = [[A, B^T], [B, C]] in [Q, Q_perp], and lambda_min(X) is at
+// least the smaller eigenvalue of [[lambda_min(A), -||B||_2], [-||B||_2,
+// lambda_min(C)]] (a sharpening of Weyl's min(lambda_min(A), lambda_min(C)) -
+// ||B||_2; ||B||_2 from the rq x rq matrix B^T B for rq <= 64, else the
+// Frobenius norm, which bounds it).  X Y = grad / 2
 // is small at a solved subproblem, so A and B are small and the Lanczos run on
 // C does not have to resolve the cluster of eigenvalues near zero that
 // range(Y) carries.  An unconverged Lanczos run only certifies an eigenvalue
@@ -726,7 +773,8 @@ static mdsdp_status certificate_spectrum(mdsdp_problem P, int p, const double* Y
                                          const std::vector<double>& Vv, const std::vector<int>& idx, bool deflate,
                                          double eig_tol, int budget, uint64_t seed, int nvec, const double* warm,
                                          double* evec, double* Qb, double* XQb, double* qc, double stop_above,
-                                         CertSpectrum* out, hipStream_t s, bool verify = false) {
+                                         CertSpectrum* out, hipStream_t s, bool verify = false,
+                                         double neg_resolve = 0.0, double reject_below = 0.0) {
   const int n = P->n;
   double lmin = 0, lmax = 0, lres = 0.0;
   double lmin_A = 0.0, lmax_A = 0.0, nB = 0.0;
@@ -758,15 +806,28 @@ static mdsdp_status certificate_spectrum(mdsdp_problem P, int p, const double* Y
         Aq[i * rq + j] = 0.5 * (G[(size_t)i * pw + j] + G[(size_t)j * pw + i]);
         a2 += Aq[i * rq + j] * Aq[i * rq + j];
       }
+    if (rq <= 64) {
+      // ||B||_2^2 = lambda_max(B^T B), B^T B = (X Q)^T (X Q) - A^2 (rq x rq)
+      CHK(launch_gram(P, rq, XQb, XQb, s, false));
+      std::vector<double> G2((size_t)pw * pw), M((size_t)rq * rq), wm(rq), Vm((size_t)rq * rq);
+      CHK(read_dev(P, P->gram + GRAM_U, pw * pw, G2.data(), s));
+      for (int i = 0; i < rq; ++i)
+        for (int j = 0; j < rq; ++j) {
+          double aa = 0.0;
+          for (int l = 0; l < rq; ++l) aa += Aq[i * rq + l] * Aq[l * rq + j];
+          M[i * rq + j] = 0.5 * (G2[(size_t)i * pw + j] + G2[(size_t)j * pw + i]) - aa;
+        }
+      sym_eig(rq, M.data(), wm.data(), Vm.data());
+      nB = sqrt(std::max(0.0, *std::max_element(wm.begin(), wm.end())));
+    } else {
+      double xq2;
+      const double* a1[1] = {XQb};
+      CHK(dots(P, 1, a1, a1, (long long)n * rq, &xq2, s));
+      nB = sqrt(std::max(0.0, xq2 - a2));  // ||X Q - Q A||_F >= ||B||_2
+    }
     sym_eig(rq, Aq.data(), wa.data(), Va.data());
     lmin_A = *std::min_element(wa.begin(), wa.end());
     lmax_A = *std::max_element(wa.begin(), wa.end());
-    double xq2;
-    {
-      const double* a1[1] = {XQb};
-      CHK(dots(P, 1, a1, a1, (long long)n * rq, &xq2, s));
-    }
-    nB = sqrt(std::max(0.0, xq2 - a2));  // ||X Q - Q A||_F >= ||B||_2
     CHK(launch_transpose(n, rq, Qb, XQb, s));  // Q^T (rq x n) for the projections
   } else {
     rq = 0;
@@ -776,10 +837,15 @@ static mdsdp_status certificate_spectrum(mdsdp_problem P, int p, const double* Y
   // (or at the budget)
   CHK(lanczos(P, eig_tol, budget, seed, &lmin, &lmax, evec, &eit, &conv, s, nvec, 1e-12, &nfound,
               verify ? nullptr : warm, &lres, !verify, 1, nullptr, nullptr, rq > 0 ? XQb : nullptr, rq, qc, !verify,
-              stop_above));
+              stop_above, neg_resolve, reject_below));
   double lo = conv ? lmin : lmin - lres;
   if (rq > 0) {
-    lo = std::min(lo, lmin_A) - nB;
+    // for a unit x = (u, w) in [Q, Q_perp]: x^T X x >= a |u|^2 - 2 b |u| |w| + c |w|^2
+    // with a = lambda_min(A), c = lambda_min(C), b = ||B||_2, whose minimum over
+    // |u|^2 + |w|^2 = 1 is the smaller eigenvalue of [[a, -b], [-b, c]]
+    // (at least min(a, c) - b, and a - b^2 / (c - a) when c - a >> b)
+    const double a_ = lmin_A, c_ = lo;
+    lo = 0.5 * (a_ + c_) - sqrt(0.25 * (a_ - c_) * (a_ - c_) + nB * nB);
     lmax = std::max(lmax, lmax_A);
   }
   out->lo = lo;
@@ -809,7 +875,7 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->kappa1 = 0.1;
   o->kappa2 = 10.0;
   o->p_max = PMAX;
-  o->n_neg = 16;
+  o->n_neg = 15;
   o->tau_rank = 1e-4;
   o->gtol0 = 1e-2;
   o->gtol_min = 1e-10;
@@ -827,6 +893,8 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->direct_admm = 0;
   o->rtr_warm_radius = 1;
   o->rtr_maxiter_polish = 50;
+  o->tcg_maxinner_polish = 1000;
+  o->rtr_stall = 0;
   o->round_rank_one = 1;
   o->round_eta = 1e-3;
   o->round_gap = 0.1;
@@ -928,6 +996,49 @@ mdsdp_status mdsdp_certificate_estimate(mdsdp_problem P, double tol, int32_t max
   return st;
 }
 
+mdsdp_status mdsdp_certificate_bound(mdsdp_problem P, int32_t p, const double* Y, double tol, int32_t maxit,
+                                    uint64_t seed, double* out, void* stream) {
+  if (!P || !Y || !out) {
+    set_error("NULL argument");
+    return MDSDP_EINVAL;
+  }
+  if (p < 1 || p > PMAX || p > P->n - 2 || maxit < 3 || !(tol > 0.0)) {
+    set_error("need 1 <= p <= min(512, n - 2), maxit >= 3 and tol > 0");
+    return MDSDP_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int n = P->n;
+  CHK(launch_gram(P, p, Y, Y, s));
+  P->gram_yy_valid = false;
+  std::vector<double> wv(p), Vv((size_t)p * p);
+  {
+    const int pw = P->gram_pw;
+    std::vector<double> G((size_t)pw * pw), A((size_t)p * p);
+    CHK(read_dev(P, P->gram, pw * pw, G.data(), s));
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) A[i * p + j] = G[(size_t)i * pw + j];
+    sym_eig(p, A.data(), wv.data(), Vv.data());
+  }
+  std::vector<int> idx(p);
+  for (int i = 0; i < p; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return wv[x] > wv[y]; });
+  double* buf = nullptr;
+  const size_t len = 3 * (size_t)n * p + n + PMAX;
+  MDSDP_HIP(hipMalloc((void**)&buf, len * sizeof(double)));
+  CertSpectrum sp;
+  const mdsdp_status st = certificate_spectrum(P, p, Y, wv, Vv, idx, true, tol, maxit, seed, 1, nullptr, buf,
+                                               buf + n, buf + n + (size_t)n * p, buf + n + 2 * (size_t)n * p, 0.0,
+                                               &sp, s, true);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (st != MDSDP_OK) return st;
+  out[0] = sp.lo;
+  out[1] = sp.lmax;
+  out[2] = sp.iters;
+  out[3] = sp.conv ? 1.0 : 0.0;
+  return MDSDP_OK;
+}
+
 mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, double* Ybuf, mdsdp_result* res,
                          double* hist, int32_t hist_cap, void* stream) {
   if (!opt) {
@@ -1025,6 +1136,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
     const bool polish = eta_max < opt->polish_eta;
     const int prec = (opt->polish_fp64 && polish) ? MDSDP_FP64 : opt->hvp_prec;
     const int rtr_budget = polish ? std::max(opt->rtr_maxiter, opt->rtr_maxiter_polish) : opt->rtr_maxiter;
+    const int tcg_budget = polish ? std::max(opt->tcg_maxinner, opt->tcg_maxinner_polish) : opt->tcg_maxinner;
     if (carry) {
       // backtracking along the carried negative-curvature direction
       double f0;
@@ -1058,8 +1170,8 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
         opt->time_limit_s > 0 ? t_start + std::chrono::duration_cast<clk::duration>(
                                               std::chrono::duration<double>(opt->time_limit_s))
                               : clk::time_point::max();
-    mdsdp_status rst = rtr(P, p, Y, gtol, rtr_budget, opt->tcg_maxinner, prec, W, C, rs, s, opt->verbose,
-                           deadline);
+    mdsdp_status rst = rtr(P, p, Y, gtol, rtr_budget, tcg_budget, prec, W, C, rs, s, opt->verbose,
+                           deadline, opt->rtr_stall);
     if (rst == MDSDP_ENONFINITE) {
       final_status = MDSDP_ENONFINITE;
       ++k;
@@ -1119,7 +1231,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
       CertSpectrum spv;
       CHK(certificate_spectrum(P, p, Y, wv, Vv, idx, opt->deflate != 0, opt->eig_tol, verify_budget,
                                opt->seed + (uint64_t)k + 0x632BE59BD9B4E019ull, 1, nullptr, W.it2.d, W.r, W.Hd,
-                               W.qc, 0.0, &spv, s, true));
+                               W.qc, 0.0, &spv, s, true, 0.0, -2.0 * opt->tol));
       C.eig_iters += spv.iters;
       C.t_eig += secs(tv, clk::now());
       eta[1] = std::max(0.0, -spv.lo) / (1.0 + fabs(spv.lmax));
@@ -1186,7 +1298,8 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
         CertSpectrum sp1;
         CHK(certificate_spectrum(P, 1, Y1, w1, V1, i1, opt->deflate != 0, opt->eig_tol,
                                  std::max(eig_budget, verify_budget), opt->seed + (uint64_t)k + 0x9E3779B97F4A7C15ull,
-                                 1, nullptr, W.it2.d, W.it2.Heta, W.it2.r, W.qc, 0.0, &sp1, s, true));
+                                 1, nullptr, W.it2.d, W.it2.Heta, W.it2.r, W.qc, 0.0, &sp1, s, true, 0.0,
+                                 -2.0 * opt->tol));
         C.eig_iters += sp1.iters;
         eta1[1] = std::max(0.0, -sp1.lo) / (1.0 + fabs(sp1.lmax));
       }

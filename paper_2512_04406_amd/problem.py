@@ -283,6 +283,15 @@ class Problem:
         return {"theta_min": float(out[0]), "theta_max": float(out[1]), "err": float(out[2]),
                 "converged": bool(out[3]), "evec": v, "iters": it.value}
 
+    def certificate_bound(self, Y: torch.Tensor, tol: float = 1e-10, maxit: int = 1200, seed: int = 0) -> dict:
+        """The certified lower bound of lambda_min of the certificate that a
+        solve ends on, deflated against range(Y) (mdsdp_certificate_bound)."""
+        _dev_f64(Y, "Y")
+        out = np.zeros(4, dtype=np.float64)
+        call("mdsdp_certificate_bound", self._h, Y.shape[1], _ptr(Y), tol, maxit, seed, _ptr(out), _stream())
+        return {"lower": float(out[0]), "theta_max": float(out[1]), "iters": int(out[2]),
+                "converged": bool(out[3])}
+
     def set_direct(self, on: bool, Y: torch.Tensor | None = None) -> None:
         """Switch to (or from) the direct-DSDP ADMM subproblem; with Y the
         stale class averages y^k are taken at Y."""

@@ -193,6 +193,9 @@ def test_status_and_eigpair_validation():
     ev = np.zeros(2)
     lmax = C.c_double()
     assert L.mdsdp_min_eigpair(None, 2, 1e-8, 10, 0, _p(ev), C.byref(lmax), None, None, None) == -1
+    out = np.zeros(4)
+    assert L.mdsdp_certificate_bound(None, 2, None, 1e-8, 10, 0, _p(out), None) == -1
+    assert b"NULL" in L.mdsdp_last_error()
 
 
 @pytest.mark.parametrize("q", [1, 2, 3, 5, 8, 13])

@@ -172,3 +172,27 @@ def test_solver_eigen_estimate_brackets_lapack(q, p):
         # denominator 1 + |theta_max| of eta_d errs on the large-eta side
         # (for lambda_max > 0, as here)
         assert e["theta_max"] <= w[-1] + 1e-9 * (1 + abs(w[-1]))
+
+
+@pytest.mark.parametrize("q,p,near", [(12, 3, False), (20, 4, False), (20, 4, True)])
+def test_certificate_bound_below_lapack(q, p, near):
+    """mdsdp_certificate_bound (the eta_d a solve ends on): Lanczos on the
+    complement of range(Y) combined with the compression to range(Y) through
+    the 2 x 2 bound; it must never exceed LAPACK's lambda_min of the dense
+    certificate.  `near`: Y spans eigenvectors of X near its bottom (the
+    situation at the end of a solve), where the bound must also be close."""
+    prob, X = _certificate(q, p)
+    n = X.shape[0]
+    w, V = np.linalg.eigh(X)
+    if near:
+        Y = V[:, :p] + 1e-6 * gaussian(n, p, 9)
+    else:
+        Y = gaussian(n, p, 8)
+    print(f"[cert-bound] q={q} n={n} p={p} near={near}", flush=True)
+    b = prob.certificate_bound(_t(Y), tol=1e-11, maxit=n)
+    scale = 1 + abs(w[-1])
+    print(f"   lower={b['lower']:.6e} lapack={w[0]:.6e} conv={b['converged']} iters={b['iters']}", flush=True)
+    assert b["lower"] <= w[0] + 1e-9 * scale
+    assert b["theta_max"] <= w[-1] + 1e-9 * scale
+    if near:
+        assert b["lower"] >= w[0] - 1e-5 * scale
