@@ -281,7 +281,7 @@ typedef struct {
   int32_t p_max;       /* largest factor width, 1..512 (default 512) */
   int32_t n_neg;       /* negative-curvature directions added per outer step (Theorem sec5:thm1);
                           default 15, so that one column plus the carried ones fit 16-column tiles */
-  double tau_rank;     /* drop singular directions below tau_rank * s_1 */
+  double tau_rank;     /* drop singular directions below tau_rank * s_1 (default 1e-7) */
   double gtol0, gtol_min;  /* inner tolerance of subproblem k (see gtol_ratio); default 1e-2, 1e-10 */
   double gtol_decay;   /* in (0, 1]; used only when gtol_ratio <= 0 */
   double gtol_ratio;   /* > 0 (default 0.1): RTR for subproblem k stops at

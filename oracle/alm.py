@@ -94,7 +94,7 @@ class ALMOptions:
     kappa2: float = 10.0
     p_max: int = 512
     n_neg: int = 15
-    tau_rank: float = 1e-4
+    tau_rank: float = 1e-7
     gtol0: float = 1e-2
     gtol_min: float = 1e-10
     gtol_decay: float = 1.0

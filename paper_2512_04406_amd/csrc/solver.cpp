@@ -38,7 +38,7 @@
 //    certificate curvature is below -max(1e-12, tol) (1 + |lambda_max|)
 //    (step 9 of Algorithm alg1); escape_when_solved restricts that to steps
 //    whose RTR call reached its tolerance;
-//  * rank rule: drop singular directions of Y below tau_rank * s_1, then add
+//  * rank rule: drop singular directions of Y below tau_rank * s_1 (1e-7), then add
 //    one zero column per carried negative eigenvector (at most n_neg = 15 per
 //    outer step, p <= p_max): near the solution the factor is one column plus
 //    the carried ones, and 16 columns fill the 16-column MFMA tiles exactly
@@ -876,7 +876,7 @@ void mdsdp_default_options(mdsdp_options* o) {
   o->kappa2 = 10.0;
   o->p_max = PMAX;
   o->n_neg = 15;
-  o->tau_rank = 1e-4;
+  o->tau_rank = 1e-7;
   o->gtol0 = 1e-2;
   o->gtol_min = 1e-10;
   o->gtol_decay = 1.0;

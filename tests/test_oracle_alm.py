@@ -185,12 +185,16 @@ def test_rank_one_compression_does_not_change_the_optimum(seed):
 
 
 @pytest.mark.parametrize("kw", [dict(sigma_hold=False), dict(escape_when_solved=True),
-                                dict(rtr_maxiter=50, rtr_maxiter_polish=50)])
+                                dict(rtr_maxiter=50, rtr_maxiter_polish=50), dict(rtr_stall=3),
+                                dict(tcg_maxinner_polish=200, n_neg=16), dict(kappa1=0.01, kappa2=0.1),
+                                dict(tau_rank=1e-4)])
 def test_readings_of_the_outer_loop_reach_the_same_optimum(kw):
     """The sigma rule as printed (no hold), the escape gated on solved
-    subproblems, and one fixed RTR budget of 50 iterations all end at the
-    brute-force minimum at q = 10 with eta_max <= 1e-8: the readings change
-    the path of the iteration, not its limit."""
+    subproblems, one fixed RTR budget of 50 iterations, the RTR stall stop,
+    the former polish budget and escape width, other sigma-rule constants and
+    a lower rank threshold all end at the brute-force minimum at q = 10 with
+    eta_max <= 1e-8: the readings change the path of the iteration, not its
+    limit."""
     Q, c, rel, fmin, xmin = _rel_and_point(10, 2)
     r = alm.solve(rel.cls, rel.counts, rel.b, gaussian(rel.n, 2, 102), alm.ALMOptions(**kw))
     assert max(r.eta) <= 1e-8
