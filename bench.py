@@ -137,7 +137,7 @@ def main() -> int:
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--prec", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--hvp-iters", type=int, default=200)
-    ap.add_argument("--kkt-time-limit-s", type=float, default=150.0,
+    ap.add_argument("--kkt-time-limit-s", type=float, default=500.0,
                     help="cap of each full time-to-KKT solve (0 skips them)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
@@ -184,7 +184,7 @@ def main() -> int:
             o = pr.default_options()
             o.hvp_prec = prec
             o.time_limit_s = cap
-            o.verbose = 1 if args.verbose else 0
+            o.verbose = 1  # one stderr line per outer step (progress of multi-minute solves)
             if args.p_max > 0:
                 o.p_max = args.p_max
             torch.cuda.synchronize()

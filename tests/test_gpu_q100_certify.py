@@ -45,6 +45,7 @@ def test_q100_solve_certified_by_oracle(instance, prec):
     o = prob.default_options()
     o.hvp_prec = prec
     o.time_limit_s = float(os.environ.get("MDSDP_Q100_CAP_S", "520"))
+    o.verbose = 1  # one stderr line per outer step: the solve takes minutes
     print(f"[q100] prec={prec} n={prob.n}", flush=True)
     r = prob.solve(torch.from_numpy(gaussian(prob.n, 16, 100)).cuda(), o)
     print(f"   status={r.status} eta={r.eta} value={r.value!r} outer={r.outer_iters} hvps={r.hvps} "
