@@ -21,9 +21,10 @@ counted as in the method's traffic model, each packed entry's class word and
 multiplier shadow read once and the class data y, y' gathered once per class
 in FP64; measured HBM traffic from the committed rocprofv3 counter summary
 when it matches the current kernel sources); capped full solves to
-eta_max <= 1e-8 at q = 100 in mixed precision and in FP64 (dynamic rank); the
-q = 40 dense, sparse-Q q = 120 and Hermitian UCQP q = 30 instances; and the
-FP64 oracle timed on the host CPU on a bounded sample.
+eta_max <= 1e-8 at q = 100 in mixed precision and in FP64 (dynamic rank; about
+six and eight minutes); the q = 40 dense, sparse-Q q = 120 and Hermitian UCQP
+q = 30 instances; the DSDP' / direct-DSDP ADMM comparison; and the FP64 oracle
+timed on the host CPU on a bounded sample.
 
 `--kkt-only mixed,fp64 [--q Q --p P0] --kkt-time-limit-s T` runs only the full
 solves (time to KKT) and prints their JSON.
@@ -124,8 +125,8 @@ def cpu_baseline(q: int, p: int, budget_s: float) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed outer iterations")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed outer iterations before the timed ones")
+    ap.add_argument("--steps", type=int, default=30, help="timed outer iterations")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed outer iterations before the timed ones")
     ap.add_argument("--q", type=int, default=100)
     ap.add_argument("--p", type=int, default=16, help="factor width of the isolated HVP and start rank p0")
     ap.add_argument("--p-max", type=int, default=0, help="rank cap of the full time-to-KKT solves (0 = library default)")
