@@ -547,7 +547,7 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
                             double* resid_out = nullptr, bool use_gap = false, int kconv = 1,
                             double* evals_out = nullptr, double* ext = nullptr, const double* Qd = nullptr,
                             int rq = 0, double* qc = nullptr, bool stop_nonneg = false,
-                            double stop_above = 0.0, double neg_resolve = 0.0, double reject_below = 0.0) {
+                            double stop_above = 0.0, double reject_below = 0.0) {
   const int n = P->n;
   maxit = std::max(2, std::min(maxit, n));
   // basis V (n x (maxit + 1)), w (n), h (4 maxit + 16): the caller's fixed
@@ -691,17 +691,6 @@ static mdsdp_status lanczos(mdsdp_problem P, double tol, int maxit, uint64_t see
         stop = true;
         break;
       }
-      // negative curvature resolved (neg_resolve > 0): theta_min lies below
-      // -neg_resolve (1 + |theta_max|) and its error estimate is at most a
-      // tenth of |theta_min|; lambda_min <= theta_min, so the certificate is
-      // not PSD.  (Not used by the solver: stopping there leaves few and poor
-      // Ritz vectors for the carried directions, and at q = 100 the rank then
-      // grew four times slower and the solve stalled.)
-      if (neg_resolve > 0.0 && k >= 3 && th_min < -neg_resolve * (1.0 + fabs(th_max)) && err <= 0.1 * fabs(th_min)) {
-        *converged = true;
-        stop = true;
-        break;
-      }
       // rejection (reject_below < 0): lambda_min <= theta_min < reject_below
       // (1 + |theta_max|) already decides the test the caller makes
       if (reject_below < 0.0 && k >= 3 && th_min < reject_below * (1.0 + fabs(th_max))) {
@@ -774,7 +763,7 @@ static mdsdp_status certificate_spectrum(mdsdp_problem P, int p, const double* Y
                                          double eig_tol, int budget, uint64_t seed, int nvec, const double* warm,
                                          double* evec, double* Qb, double* XQb, double* qc, double stop_above,
                                          CertSpectrum* out, hipStream_t s, bool verify = false,
-                                         double neg_resolve = 0.0, double reject_below = 0.0) {
+                                         double reject_below = 0.0) {
   const int n = P->n;
   double lmin = 0, lmax = 0, lres = 0.0;
   double lmin_A = 0.0, lmax_A = 0.0, nB = 0.0;
@@ -837,7 +826,7 @@ static mdsdp_status certificate_spectrum(mdsdp_problem P, int p, const double* Y
   // (or at the budget)
   CHK(lanczos(P, eig_tol, budget, seed, &lmin, &lmax, evec, &eit, &conv, s, nvec, 1e-12, &nfound,
               verify ? nullptr : warm, &lres, !verify, 1, nullptr, nullptr, rq > 0 ? XQb : nullptr, rq, qc, !verify,
-              stop_above, neg_resolve, reject_below));
+              stop_above, reject_below));
   double lo = conv ? lmin : lmin - lres;
   if (rq > 0) {
     // for a unit x = (u, w) in [Q, Q_perp]: x^T X x >= a |u|^2 - 2 b |u| |w| + c |w|^2
@@ -1231,7 +1220,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
       CertSpectrum spv;
       CHK(certificate_spectrum(P, p, Y, wv, Vv, idx, opt->deflate != 0, opt->eig_tol, verify_budget,
                                opt->seed + (uint64_t)k + 0x632BE59BD9B4E019ull, 1, nullptr, W.it2.d, W.r, W.Hd,
-                               W.qc, 0.0, &spv, s, true, 0.0, -2.0 * opt->tol));
+                               W.qc, 0.0, &spv, s, true, -2.0 * opt->tol));
       C.eig_iters += spv.iters;
       C.t_eig += secs(tv, clk::now());
       eta[1] = std::max(0.0, -spv.lo) / (1.0 + fabs(spv.lmax));
@@ -1298,7 +1287,7 @@ mdsdp_status mdsdp_solve(mdsdp_problem P, const mdsdp_options* opt, int32_t p0, 
         CertSpectrum sp1;
         CHK(certificate_spectrum(P, 1, Y1, w1, V1, i1, opt->deflate != 0, opt->eig_tol,
                                  std::max(eig_budget, verify_budget), opt->seed + (uint64_t)k + 0x9E3779B97F4A7C15ull,
-                                 1, nullptr, W.it2.d, W.it2.Heta, W.it2.r, W.qc, 0.0, &sp1, s, true, 0.0,
+                                 1, nullptr, W.it2.d, W.it2.Heta, W.it2.r, W.qc, 0.0, &sp1, s, true,
                                  -2.0 * opt->tol));
         C.eig_iters += sp1.iters;
         eta1[1] = std::max(0.0, -sp1.lo) / (1.0 + fabs(sp1.lmax));
