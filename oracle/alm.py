@@ -22,9 +22,12 @@ Readings of points the paper leaves open:
   gradient vanishes on the new columns).
 * rank rule (delegated by the paper to ManiSDP section 5.1, not in the text):
   after each subproblem, drop singular directions of Y below tau_rank * s_1
-  (Y <- Y V_r, rows renormalised), then append one zero column per carried
-  eigenvector (at most n_neg = 15 of them, p <= p_max; near a rank-one
-  solution the factor then has 16 columns).
+  (tau_rank = 1e-7; Y <- Y V_r, rows renormalised), then append one zero
+  column per carried eigenvector (at most n_neg = 15 of them, p <= p_max;
+  near a rank-one solution the factor then has 16 columns).  A column carried
+  along a negative-curvature direction of size |lambda| only grows to about
+  sqrt(|lambda| / sigma) relative to the leading one, so a larger threshold
+  removes it at the next step before it can act on the certificate.
 * inner tolerance: RTR for subproblem k stops at ||grad|| <= gtol_k with
   gtol_k = max(gtol_min, min(gtol0, gtol_ratio ||R^k|| / (1 + ||b||))), i.e. the
   subproblem is solved to a fixed fraction of the same scaled primal residual
