@@ -125,3 +125,41 @@ def test_parity_bounds_catch_one_wrong_row():
     row = 7
     bad[row] -= pen[row] - (pen[row] @ Y[row]) * Y[row]
     assert elem_err(bad, ref, B) > 1e-4
+
+
+def test_deflated_eigenvalue_bound_is_a_lower_bound():
+    """The bound a GPU solve ends on (deflation against range(Y)): for an
+    orthonormal Q and X = [[A, B^T], [B, C]] in [Q, Q_perp], lambda_min(X) is at
+    least the smaller eigenvalue of [[lambda_min(A), -||B||_2], [-||B||_2,
+    lambda_min(C)]], which is itself at least Weyl's min(.) - ||B||_2, and is
+    tight when B = 0.  Checked by LAPACK on random symmetric matrices, including
+    the end-of-solve situation (range(Y) close to the bottom eigenvectors)."""
+    rng = np.random.default_rng(17)
+    for trial in range(60):
+        n, r = 40, 1 + trial % 6
+        M = rng.standard_normal((n, n))
+        X = 0.5 * (M + M.T)
+        if trial % 3 == 0:  # range(Q) near the bottom of the spectrum
+            w, V = np.linalg.eigh(X)
+            Q, _ = np.linalg.qr(V[:, :r] + 1e-3 * rng.standard_normal((n, r)))
+        else:
+            Q, _ = np.linalg.qr(rng.standard_normal((n, r)))
+        P, _ = np.linalg.qr(np.hstack([Q, rng.standard_normal((n, n - r))]))
+        Qp = P[:, r:]
+        A = Q.T @ X @ Q
+        B = Qp.T @ X @ Q
+        Cc = Qp.T @ X @ Qp
+        a, c = np.linalg.eigvalsh(A)[0], np.linalg.eigvalsh(Cc)[0]
+        b = np.linalg.norm(B, 2)
+        bound = 0.5 * (a + c) - np.sqrt(0.25 * (a - c) ** 2 + b * b)
+        lmin = np.linalg.eigvalsh(X)[0]
+        assert bound <= lmin + 1e-12
+        assert bound >= min(a, c) - b - 1e-12
+        # B^T B = (X Q)^T (X Q) - A^2 gives ||B||_2 without Q_perp
+        G = (X @ Q).T @ (X @ Q) - A @ A
+        assert abs(np.sqrt(max(0.0, np.linalg.eigvalsh(0.5 * (G + G.T))[-1])) - b) <= 1e-9 * (1 + b)
+    # B = 0: the bound is exact
+    X = np.diag(np.arange(1.0, 9.0))
+    Q = np.eye(8)[:, :2]
+    a, c = 1.0, 3.0
+    assert 0.5 * (a + c) - np.sqrt(0.25 * (a - c) ** 2) == np.linalg.eigvalsh(X)[0]
