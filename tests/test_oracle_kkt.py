@@ -15,7 +15,9 @@ one of eta_p, eta_d, eta_g fails:
 * X = X0 - mu v v^T / ||v||^2 has lambda_min = -mu and lambda_max = kappa, so
   eta_d = mu / (1 + kappa);
 * z = z0 + delta e_1: the primal value moves by delta and the dual does not, so
-  eta_g = |delta| / (1 + |sum z0 + delta| + |sum z0|).
+  eta_g = |delta| / (1 + |sum z0 + delta| + |sum z0|);
+* the lower bound of lambda_min that deflation against range(Y) gives (the
+  smaller eigenvalue of a 2 x 2 matrix of block bounds) against LAPACK.
 """
 
 import numpy as np
