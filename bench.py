@@ -27,7 +27,8 @@ q = 30 instances; the DSDP' / direct-DSDP ADMM comparison; and the FP64 oracle
 timed on the host CPU on a bounded sample.
 
 `--kkt-only mixed,fp64 [--q Q --p P0] --kkt-time-limit-s T` runs only the full
-solves (time to KKT) and prints their JSON.
+solves (time to KKT) and prints their JSON; `--batch-only N` solves N small
+dense BQPs (q uniform in [8, 30]) with mdsdp_solve_batch and prints its JSON.
 """
 
 from __future__ import annotations
@@ -198,7 +199,6 @@ def main() -> int:
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--kkt-only", default="",
                     help="only the capped time-to-KKT solves: 'mixed', 'fp64' or 'mixed,fp64'")
-    ap.add_argument("--verbose", action="store_true", help="one stderr line per outer iteration of the solves")
     ap.add_argument("--batch-only", type=int, default=0,
                     help="solve a batch of this many dense BQPs, q uniform in [8, 30], with mdsdp_solve_batch "
                          "and print its JSON (nothing else)")
