@@ -275,7 +275,8 @@ mdsdp_status mdsdp_adjoint_C(mdsdp_problem prob, double* dC_dev, void* stream);
 
 /* ---- full solve (Algorithm alg1 with RTR + truncated CG) ------------------- */
 typedef struct {
-  double tol;          /* stop when eta_max <= tol (eq. res); default 1e-8 */
+  double tol;          /* stop when eta_max <= tol (eq. res; the eta_d a solve ends on comes from a
+                          verify eigensolve: random start, residual error, no early stop); default 1e-8 */
   int32_t max_outer;   /* default 200 */
   double sigma0, sigma_min, sigma_max, gamma, kappa1, kappa2; /* eq. sec5:eq1 */
   int32_t p_max;       /* largest factor width, 1..512 (default 512) */
@@ -307,11 +308,11 @@ typedef struct {
                           multiplier Xt with sigma = sigma0 (e.g. the sigma a previous solve returned) */
   int32_t escape_when_solved; /* 1: form the carried direction of Theorem sec5:thm1 and add its zero
                           columns only after an RTR call that reached its tolerance; 0 (default): after
-                          every outer step whose certificate has curvature below -tol (1 + |lambda_max|)
-                          (step 9 of Algorithm alg1) */
+                          every outer step whose certificate has curvature below
+                          -max(1e-12, tol) (1 + |lambda_max|) (step 9 of Algorithm alg1) */
   int32_t deflate;     /* 1 (default): the certificate eigensolve runs on the complement of range(Y)
-                          and combines it with the compression Q^T X Q to range(Y) (Weyl bound, see
-                          mdsdp_solve); 0: plain Lanczos on X */
+                          and combines it with the compression Q^T X Q to range(Y) (the block bound of
+                          mdsdp_certificate_bound); 0: plain Lanczos on X */
   int32_t direct_admm; /* 1: solve DSDP by the two-block ADMM with the direct S-subproblem
                           (mdsdp_set_direct; the ablation of section "Why solve DSDP' instead of
                           DSDP"); 0 (default): ManiDSDP on DSDP' */
