@@ -186,7 +186,7 @@ def main() -> int:
     ap.add_argument("--p", type=int, default=16, help="factor width of the isolated HVP and start rank p0")
     ap.add_argument("--p-max", type=int, default=0, help="rank cap of the full time-to-KKT solves (0 = library default)")
     ap.add_argument("--p-steps", type=int, default=16, help="rank cap of the timed outer iterations")
-    ap.add_argument("--ablation-time-limit-s", type=float, default=20.0,
+    ap.add_argument("--ablation-time-limit-s", type=float, default=10.0,
                     help="cap of each solve of the DSDP' / direct-DSDP comparison (0 skips it)")
     ap.add_argument("--ucqp-time-limit-s", type=float, default=60.0,
                     help="cap of each Hermitian UCQP q=30 full solve (0 skips them)")
